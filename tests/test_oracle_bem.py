@@ -1,0 +1,120 @@
+"""Pins of the oracle's collocation system (eqs. (BEMpot), (BEMfld),
+(matrixBEM)) and its solve: solve quality, the Dirichlet rows reproduced by
+the field evaluation, the dielectric jump condition, the parallel-plate field,
+a conducting sphere in a dielectric shell (closed form), and mesh symmetry."""
+import numpy as np
+import pytest
+
+from paper_2110_09214_amd import workloads as W
+
+
+@pytest.fixture(scope="module")
+def plates(orc):
+    m = W.parallel_plate_mesh(n=16)
+    sig, A = orc.bem_solve(m)
+    return m, sig, A
+
+
+def test_backward_error(orc, plates):
+    m, sig, A = plates
+    r = orc.residual_dense(A, sig, m.rhs)
+    berr = np.abs(r).max() / (np.abs(A).sum(axis=1).max() * np.abs(sig).max())
+    assert berr <= 1e-15
+
+
+def test_dirichlet_rows_reproduced_by_field_evaluation(orc, plates):
+    """V evaluated (eq. (BEM2)) at every ed collocation point equals the
+    applied voltage: assembly rows, the solve and the evaluation agree."""
+    m, sig, _ = plates
+    _, _, cen, _ = orc.tri_geometry(m.a, m.b, m.c)
+    _, V = orc.panel_field(cen, m.a, m.b, m.c, sig, want_v=True)
+    assert np.abs(V - m.rhs).max() <= 1e-12 * 500.0
+
+
+def test_parallel_plate_centre_field(orc):
+    """Config-1 geometry: centre field close to V/d = 5e5 V/m (fringing and
+    discretisation keep it within 1e-2)."""
+    m = W.parallel_plate_mesh(n=32)
+    sig, _ = orc.bem_solve(m, refine=1)
+    E = orc.panel_field(np.array([[0, 0, 0.5e-3], [1e-3, -1e-3, 0.3e-3]]), m.a, m.b, m.c, sig)
+    for e in E:
+        assert abs(e[2] - 5e5) <= 1e-2 * 5e5     # field points from the 0 V plate to the -500 V plate: +z
+        assert np.hypot(e[0], e[1]) <= 1e-2 * 5e5
+
+
+def test_plate_mesh_rotation_symmetry(orc, plates):
+    """The diagonal split is invariant under the 180 degree rotation about the
+    plate axis, so E(R x) = R E(x)."""
+    m, sig, _ = plates
+    R = np.diag([-1.0, -1.0, 1.0])
+    x = np.random.default_rng(5).uniform([-4e-3, -4e-3, 1e-4], [4e-3, 4e-3, 9e-4], size=(20, 3))
+    E1 = orc.panel_field(x, m.a, m.b, m.c, sig)
+    E2 = orc.panel_field(x @ R.T, m.a, m.b, m.c, sig)
+    assert np.abs(E2 - E1 @ R.T).max() <= 1e-9 * np.abs(E1).max()
+
+
+@pytest.fixture(scope="module")
+def shell(orc):
+    out = {}
+    for sub in (2, 3):
+        m = W.sphere_in_shell_mesh(a=1.0, b=2.0, eps_shell=4.0, v=1.0, subdiv=sub)
+        sig, A = orc.bem_solve(m, refine=1)
+        out[sub] = (m, sig)
+    return out
+
+
+def test_sphere_in_dielectric_shell(orc, shell):
+    """Conducting sphere (a=1, V=1) in a shell (eps=4, b=2): Q from
+    V = k_e Q [(1/eps)(1/a - 1/b) + 1/b]; |E| = k_e Q/(eps r^2) in the shell and
+    k_e Q / r^2 outside.  Flat facets miss the curvature part of the
+    normal-field kernel on the dd sphere, so the error shrinks only as O(h)."""
+    k = orc.constants()["k_e"]
+    eps, a, b = 4.0, 1.0, 2.0
+    Q = 1.0 / (k * ((1 / eps) * (1 / a - 1 / b) + 1 / b))
+    rng = np.random.default_rng(9)
+    dirs = rng.normal(size=(8, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    errs = []
+    for sub in (2, 3):
+        m, sig = shell[sub]
+        pts = np.concatenate([1.5 * dirs, 3.0 * dirs])
+        E = orc.panel_field(pts, m.a, m.b, m.c, sig)
+        Er = np.einsum("ij,ij->i", E, np.concatenate([dirs, dirs]))
+        exact = np.concatenate([np.full(8, k * Q / (eps * 1.5 ** 2)), np.full(8, k * Q / 9.0)])
+        errs.append(np.abs(Er / exact - 1).max())
+    assert errs[1] < 0.04
+    assert errs[1] < 0.75 * errs[0]
+
+
+def test_dielectric_slab_between_plates(orc):
+    """Plates 1 mm apart at 0 / -500 V with an eps = 3 slab 0.4 mm thick on the
+    0 V plate: flat cells represent the interfaces exactly, and the centre
+    fields approach E_vac = V/(t/eps + d - t), E_slab = E_vac/eps."""
+    m = W.plates_with_slab_mesh(n=12)
+    sig, _ = orc.bem_solve(m, refine=1)
+    E = orc.panel_field(np.array([[0, 0, 0.7e-3], [0, 0, 0.2e-3]]), m.a, m.b, m.c, sig)
+    ev = 500.0 / (0.4e-3 / 3 + 0.6e-3)
+    assert E[0, 2] == pytest.approx(ev, rel=3e-4)
+    assert E[1, 2] == pytest.approx(ev / 3, rel=3e-4)
+
+
+def test_dielectric_jump_condition(orc, shell):
+    """eps2 E(c + d n).n - eps1 E(c - d n).n = sigma_F / eps0 = 0 at the dd
+    collocation points (eq. (contfld)), up to O(d / D)."""
+    m, sig = shell[2]
+    nrm, area, cen, diam = orc.tri_geometry(m.a, m.b, m.c)
+    dd = np.nonzero(m.kind == 1)[0][:40]
+    d = 1e-7 * diam[dd][:, None]
+    Ep = orc.panel_field(cen[dd] + d * nrm[dd], m.a, m.b, m.c, sig)
+    Em = orc.panel_field(cen[dd] - d * nrm[dd], m.a, m.b, m.c, sig)
+    jump = m.eps2[dd] * np.einsum("ij,ij->i", Ep, nrm[dd]) - m.eps1[dd] * np.einsum("ij,ij->i", Em, nrm[dd])
+    scale = np.abs(np.einsum("ij,ij->i", Ep, nrm[dd])).max()
+    assert np.abs(jump).max() <= 1e-5 * scale
+
+
+def test_matrix_free_residual_rows(orc, plates):
+    m, sig, A = plates
+    rows = np.array([0, 7, 300, m.n - 1])
+    res, absr = orc.bem_residual_rows(m, sig, m.rhs, rows)
+    assert np.allclose(absr, np.abs(A[rows]).sum(axis=1), rtol=1e-14)
+    assert np.abs(res).max() <= 1e-15 * absr.max() * np.abs(sig).max()
