@@ -1,0 +1,345 @@
+// C ABI entry points of libobem: contexts, argument validation, mesh binding
+// and the field evaluation driver.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <vector>
+
+#include "cellmath.hpp"
+#include "obem_internal.hpp"
+
+namespace obem {
+
+obem_status fail(obem_ctx *ctx, obem_status st, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return st;
+}
+
+obem_status hip_fail(obem_ctx *ctx, hipError_t e, const char *what, int line) {
+  if (ctx) {
+    ctx->sticky = true;
+    char buf[512];
+    snprintf(buf, sizeof buf, "HIP error %d (%s) in %s [line %d]", (int)e, hipGetErrorString(e), what, line);
+    ctx->err = buf;
+  }
+  return OBEM_EDEVICE;
+}
+
+void *ws_get(obem_ctx *ctx, int slot, size_t bytes) {
+  DevBuf &b = ctx->ws[slot];
+  if (bytes == 0) bytes = 1;
+  if (b.bytes >= bytes) return b.p;
+  if (b.p) {
+    // the buffer may still be in use by queued work on the context stream
+    hipStreamSynchronize(ctx->stream);
+    hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = std::max(bytes, (size_t)4096);
+  want = (want + 255) / 256 * 256;
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    hipGetLastError();
+    b.p = nullptr;
+    return nullptr;
+  }
+  b.bytes = want;
+  return b.p;
+}
+
+bool is_device_ptr(const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged ||
+         attr.type == hipMemoryTypeUnified;
+}
+
+// ---------------------------------------------------------------------------
+// Mesh derivation: normal, area, centroid, diameter, quadrature points.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mesh_derive(int n, double *f, const int8_t *kind, const double *e1,
+                                                     const double *e2, int *bad) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  auto F = [&](int fld) -> double & { return f[(size_t)fld * n + k]; };
+  d3 a = mk3(F(MF_AX), F(MF_AY), F(MF_AZ));
+  d3 b = mk3(F(MF_BX), F(MF_BY), F(MF_BZ));
+  d3 c = mk3(F(MF_CX), F(MF_CY), F(MF_CZ));
+  d3 N2 = cross3(b - a, c - a);
+  double n2 = norm3(N2);
+  double L = fmax(norm3(b - a), fmax(norm3(c - b), norm3(a - c)));
+  if (!(n2 > 0.0) || !(n2 <= 1e300) || !(L > 0.0)) {
+    atomicAdd(bad, 1);
+    n2 = 1.0;
+  }
+  d3 nn = N2 * (1.0 / n2);
+  F(MF_NX) = nn.x;
+  F(MF_NY) = nn.y;
+  F(MF_NZ) = nn.z;
+  F(MF_AREA) = 0.5 * n2;
+  F(MF_DIAM) = L;
+  d3 g = (a + b + c) * (1.0 / 3.0);
+  F(MF_GX) = g.x;
+  F(MF_GY) = g.y;
+  F(MF_GZ) = g.z;
+  const bool dd = kind[k] == 1;
+  F(MF_EPS1) = (dd && e1) ? e1[k] : 1.0;
+  F(MF_EPS2) = (dd && e2) ? e2[k] : 1.0;
+  // 7-point rule: centroid, then (a, a, 1-2a) and (b, b, 1-2b) families
+  const double bary7[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3},
+                              {Rule7::a, Rule7::a, 1 - 2 * Rule7::a},
+                              {Rule7::a, 1 - 2 * Rule7::a, Rule7::a},
+                              {1 - 2 * Rule7::a, Rule7::a, Rule7::a},
+                              {Rule7::b, Rule7::b, 1 - 2 * Rule7::b},
+                              {Rule7::b, 1 - 2 * Rule7::b, Rule7::b},
+                              {1 - 2 * Rule7::b, Rule7::b, Rule7::b}};
+  for (int q = 0; q < 7; ++q) {
+    d3 p = a * bary7[q][0] + b * bary7[q][1] + c * bary7[q][2];
+    F(MF_Q7 + 3 * q) = p.x;
+    F(MF_Q7 + 3 * q + 1) = p.y;
+    F(MF_Q7 + 3 * q + 2) = p.z;
+  }
+  const double bary3[3][3] = {{2.0 / 3, 1.0 / 6, 1.0 / 6}, {1.0 / 6, 2.0 / 3, 1.0 / 6}, {1.0 / 6, 1.0 / 6, 2.0 / 3}};
+  for (int q = 0; q < 3; ++q) {
+    d3 p = a * bary3[q][0] + b * bary3[q][1] + c * bary3[q][2];
+    F(MF_Q3 + 3 * q) = p.x;
+    F(MF_Q3 + 3 * q + 1) = p.y;
+    F(MF_Q3 + 3 * q + 2) = p.z;
+  }
+}
+
+}  // namespace obem
+
+using namespace obem;
+
+#define CHECK_CTX(ctx)                                                       \
+  do {                                                                       \
+    if (!(ctx)) return OBEM_EINVAL;                                          \
+    if ((ctx)->sticky) return OBEM_ESTATE;                                   \
+    if (hipSetDevice((ctx)->device) != hipSuccess) {                         \
+      hipGetLastError();                                                     \
+      return fail(ctx, OBEM_EDEVICE, "hipSetDevice(%d) failed", (ctx)->device); \
+    }                                                                        \
+  } while (0)
+
+#define REQ_DEV(ctx, p, name)                                                             \
+  do {                                                                                    \
+    if (!is_device_ptr(p)) return fail(ctx, OBEM_EINVAL, "%s is NULL or not device memory", name); \
+  } while (0)
+
+#define OPT_DEV(ctx, p, name)                                                             \
+  do {                                                                                    \
+    if ((p) && !is_device_ptr(p)) return fail(ctx, OBEM_EINVAL, "%s is not device memory", name); \
+  } while (0)
+
+static const int64_t kMaxCount = (int64_t)1 << 31;
+
+extern "C" {
+
+void obem_constants(double *out) {
+  if (!out) return;
+  out[0] = kEps0;
+  out[1] = kKe;
+  out[2] = kQe;
+  out[3] = kMe;
+  out[4] = kKb;
+  out[5] = kAmu;
+}
+
+obem_status obem_create(obem_ctx **out, int device, void *hip_stream) {
+  if (!out) return OBEM_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    hipGetLastError();
+    return OBEM_EINVAL;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    hipGetLastError();
+    return OBEM_EDEVICE;
+  }
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return OBEM_EDEVICE;  // code objects are gfx950 only
+  obem_ctx *c = new obem_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  *out = c;
+  return OBEM_OK;
+}
+
+obem_status obem_destroy(obem_ctx *ctx) {
+  if (!ctx) return OBEM_EINVAL;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  for (auto &b : ctx->ws)
+    if (b.p) hipFree(b.p);
+  solver_release(ctx);
+  hipGetLastError();
+  delete ctx;
+  return OBEM_OK;
+}
+
+const char *obem_last_error(const obem_ctx *ctx) {
+  if (!ctx) return "null context";
+  return ctx->err.c_str();
+}
+
+obem_status obem_mesh_bind(obem_ctx *ctx, const obem_mesh *mesh, obem_meshh **out) {
+  CHECK_CTX(ctx);
+  if (!mesh || !out) return fail(ctx, OBEM_EINVAL, "mesh/out is NULL");
+  *out = nullptr;
+  const int64_t n = mesh->n_panels;
+  if (n <= 0 || n >= kMaxCount) return fail(ctx, OBEM_EINVAL, "n_panels=%lld out of range", (long long)n);
+  const double *v[9] = {mesh->ax, mesh->ay, mesh->az, mesh->bx, mesh->by, mesh->bz, mesh->cx, mesh->cy, mesh->cz};
+  for (int k = 0; k < 9; ++k) REQ_DEV(ctx, v[k], "mesh vertex array");
+  REQ_DEV(ctx, mesh->kind, "mesh->kind");
+  std::vector<int8_t> hk((size_t)n);
+  OBEM_HIP(ctx, hipMemcpy(hk.data(), mesh->kind, (size_t)n, hipMemcpyDeviceToHost));
+  int64_t n_dd = 0;
+  for (int8_t k : hk) {
+    if (k != 0 && k != 1) return fail(ctx, OBEM_EINVAL, "mesh->kind must be 0 (ed) or 1 (dd)");
+    n_dd += k;
+  }
+  if (n_dd) {
+    REQ_DEV(ctx, mesh->eps_r1, "mesh->eps_r1");
+    REQ_DEV(ctx, mesh->eps_r2, "mesh->eps_r2");
+  }
+  obem_meshh *m = new obem_meshh();
+  m->n = n;
+  m->n_dd = n_dd;
+  if (hipMalloc(&m->f, sizeof(double) * MF_COUNT * (size_t)n) != hipSuccess ||
+      hipMalloc(&m->kind, (size_t)n) != hipSuccess) {
+    hipGetLastError();
+    hipFree(m->f);
+    delete m;
+    return fail(ctx, OBEM_ENOMEM, "mesh allocation failed");
+  }
+  for (int k = 0; k < 9; ++k)
+    OBEM_HIP(ctx, hipMemcpyAsync(m->f + (size_t)k * n, v[k], sizeof(double) * n, hipMemcpyDeviceToDevice, ctx->stream));
+  OBEM_HIP(ctx, hipMemcpyAsync(m->kind, mesh->kind, (size_t)n, hipMemcpyDeviceToDevice, ctx->stream));
+  int *bad = (int *)ws_get(ctx, WS_MISC0, sizeof(int));
+  if (!bad) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  OBEM_HIP(ctx, hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
+  hipLaunchKernelGGL(k_mesh_derive, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, (int)n, m->f,
+                     m->kind, mesh->eps_r1, mesh->eps_r2, bad);
+  OBEM_HIP(ctx, hipGetLastError());
+  int hbad = 0;
+  OBEM_HIP(ctx, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  // host copies for the bounding box and diameters
+  std::vector<double> hv((size_t)n * 9), hd((size_t)n);
+  OBEM_HIP(ctx, hipMemcpyAsync(hv.data(), m->f, sizeof(double) * 9 * n, hipMemcpyDeviceToHost, ctx->stream));
+  OBEM_HIP(ctx, hipMemcpyAsync(hd.data(), m->f + (size_t)MF_DIAM * n, sizeof(double) * n, hipMemcpyDeviceToHost,
+                               ctx->stream));
+  OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (hbad) {
+    hipFree(m->f);
+    hipFree(m->kind);
+    delete m;
+    return fail(ctx, OBEM_EINVAL, "mesh has %d degenerate or non-finite cells", hbad);
+  }
+  for (int c = 0; c < 3; ++c) {
+    m->bbox_lo[c] = INFINITY;
+    m->bbox_hi[c] = -INFINITY;
+  }
+  for (int64_t k = 0; k < n; ++k)
+    for (int vtx = 0; vtx < 3; ++vtx)
+      for (int c = 0; c < 3; ++c) {
+        double x = hv[(size_t)(3 * vtx + c) * n + k];
+        m->bbox_lo[c] = std::min(m->bbox_lo[c], x);
+        m->bbox_hi[c] = std::max(m->bbox_hi[c], x);
+      }
+  m->max_diam = *std::max_element(hd.begin(), hd.end());
+  *out = m;
+  return OBEM_OK;
+}
+
+obem_status obem_mesh_release(obem_ctx *ctx, obem_meshh *m) {
+  if (!ctx || !m) return OBEM_EINVAL;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  hipFree(m->f);
+  hipFree(m->kind);
+  bem_release(m);
+  hipFree(m->grid_start);
+  hipFree(m->grid_items);
+  hipGetLastError();
+  delete m;
+  return OBEM_OK;
+}
+
+obem_status obem_mesh_geometry(obem_ctx *ctx, const obem_meshh *m, double *area, double *cx, double *cy,
+                               double *cz, double *diameter) {
+  CHECK_CTX(ctx);
+  if (!m) return fail(ctx, OBEM_EINVAL, "mesh is NULL");
+  double *dst[5] = {area, cx, cy, cz, diameter};
+  const int src[5] = {MF_AREA, MF_GX, MF_GY, MF_GZ, MF_DIAM};
+  for (int k = 0; k < 5; ++k) {
+    if (!dst[k]) continue;
+    OPT_DEV(ctx, dst[k], "output array");
+    OBEM_HIP(ctx, hipMemcpyAsync(dst[k], m->field(src[k]), sizeof(double) * m->n, hipMemcpyDeviceToDevice,
+                                 ctx->stream));
+  }
+  return OBEM_OK;
+}
+
+obem_status field_eval(obem_ctx *ctx, const obem_meshh *mesh, const double *sigma, int64_t n_src,
+                       const double *sx, const double *sy, const double *sz, const double *sq, int64_t n_tgt,
+                       const double *tx, const double *ty, const double *tz, double soft,
+                       obem_precision precision, unsigned flags, double *Ex, double *Ey, double *Ez, double *V) {
+  CHECK_CTX(ctx);
+  if (n_tgt < 0 || n_tgt >= kMaxCount || n_src < 0 || n_src >= kMaxCount)
+    return fail(ctx, OBEM_EINVAL, "n_tgt/n_src out of range");
+  if (!(soft >= 0.0) || !std::isfinite(soft)) return fail(ctx, OBEM_EINVAL, "soft must be finite and >= 0");
+  if (precision != OBEM_FP64 && precision != OBEM_MIXED) return fail(ctx, OBEM_EINVAL, "bad precision");
+  if (flags & ~(OBEM_TGT_IS_SRC | OBEM_WANT_V)) return fail(ctx, OBEM_EINVAL, "unknown flags");
+  const bool tis = flags & OBEM_TGT_IS_SRC;
+  const bool want_v = flags & OBEM_WANT_V;
+  if (tis && n_src != n_tgt) return fail(ctx, OBEM_EINVAL, "OBEM_TGT_IS_SRC needs n_src == n_tgt");
+  if (n_tgt == 0) return OBEM_OK;
+  REQ_DEV(ctx, tx, "tx");
+  REQ_DEV(ctx, ty, "ty");
+  REQ_DEV(ctx, tz, "tz");
+  REQ_DEV(ctx, Ex, "Ex");
+  REQ_DEV(ctx, Ey, "Ey");
+  REQ_DEV(ctx, Ez, "Ez");
+  if (want_v) REQ_DEV(ctx, V, "V");
+  if (n_src > 0) {
+    REQ_DEV(ctx, sx, "sx");
+    REQ_DEV(ctx, sy, "sy");
+    REQ_DEV(ctx, sz, "sz");
+    REQ_DEV(ctx, sq, "sq");
+  }
+  if (mesh) REQ_DEV(ctx, sigma, "sigma");
+  TargetOrder to;
+  obem_status st = order_targets(ctx, n_tgt, tx, ty, tz, &to);
+  if (st) return st;
+  double *acc = (double *)ws_get(ctx, WS_ACC, sizeof(double) * 4 * (size_t)n_tgt);
+  if (!acc) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  if (mesh) {
+    st = launch_panel_field(ctx, mesh, sigma, to, precision, want_v, acc);
+  } else {
+    st = launch_fill(ctx, acc, 4 * (size_t)n_tgt, 0.0);
+  }
+  if (st) return st;
+  if (n_src > 0) {
+    st = launch_pair_field(ctx, n_src, sx, sy, sz, sq, to, soft, precision, tis, want_v, nullptr, acc, nullptr,
+                           nullptr);
+    if (st) return st;
+  }
+  return launch_scatter(ctx, to, acc, kKe, Ex, Ey, Ez, want_v ? V : nullptr);
+}
+
+}  // extern "C"

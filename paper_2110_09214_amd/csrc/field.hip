@@ -1,0 +1,665 @@
+// Field evaluation kernels for gfx950: target ordering, cell (panel) field,
+// pairwise point-charge field, fixed-order reduction and scatter.
+//
+// Layout: targets are reordered along a Morton curve so that the 256 targets
+// of a workgroup are spatially compact; each workgroup recentres its targets
+// and the staged source/cell data on its first target (FP64 difference, then
+// FP32), which keeps FP32 differences relative to the pair distance instead
+// of the absolute coordinates.  Sums are accumulated per tile in registers and
+// carried across tiles with a compensated (Neumaier) FP32 sum in the mixed
+// mode, plainly in FP64 in the FP64 mode.  No floating-point atomics: every
+// reduction has a fixed order.
+#include <hipcub/hipcub.hpp>
+
+#include "cellmath.hpp"
+#include "obem_internal.hpp"
+
+namespace obem {
+
+constexpr int kThreads = 256;
+
+// ---------------------------------------------------------------------------
+// Target ordering
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_bbox_partial(int n, const double *__restrict__ x,
+                                                      const double *__restrict__ y,
+                                                      const double *__restrict__ z, double *part) {
+  __shared__ double s[6][256];
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    double v[3] = {x[i], y[i], z[i]};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = fmin(lo[c], v[c]);
+      hi[c] = fmax(hi[c], v[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    s[c][threadIdx.x] = lo[c];
+    s[3 + c][threadIdx.x] = hi[c];
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        s[c][threadIdx.x] = fmin(s[c][threadIdx.x], s[c][threadIdx.x + w]);
+        s[3 + c][threadIdx.x] = fmax(s[3 + c][threadIdx.x], s[3 + c][threadIdx.x + w]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_bbox_final(int nb, const double *part, double *bbox) {
+  __shared__ double s[6][256];
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int b = threadIdx.x; b < nb; b += 256) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = fmin(lo[c], part[b * 6 + c]);
+      hi[c] = fmax(hi[c], part[b * 6 + 3 + c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    s[c][threadIdx.x] = lo[c];
+    s[3 + c][threadIdx.x] = hi[c];
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        s[c][threadIdx.x] = fmin(s[c][threadIdx.x], s[c][threadIdx.x + w]);
+        s[3 + c][threadIdx.x] = fmax(s[3 + c][threadIdx.x], s[3 + c][threadIdx.x + w]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) bbox[threadIdx.x] = s[threadIdx.x][0];
+}
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_morton(int n, const double *__restrict__ x, const double *__restrict__ y,
+                                                const double *__restrict__ z, const double *bbox,
+                                                uint32_t *keys, int32_t *idx) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double v[3] = {x[i], y[i], z[i]};
+  uint32_t q[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double span = bbox[3 + c] - bbox[c];
+    double t = span > 0.0 ? (v[c] - bbox[c]) / span : 0.0;
+    int qi = (int)(t * 1024.0);
+    q[c] = (uint32_t)min(max(qi, 0), 1023);
+  }
+  keys[i] = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
+  idx[i] = i;
+}
+
+__global__ __launch_bounds__(256) void k_gather3(int n, const int32_t *__restrict__ perm,
+                                                 const double *__restrict__ x, const double *__restrict__ y,
+                                                 const double *__restrict__ z, double *out) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  int j = perm[i];
+  out[i] = x[j];
+  out[(size_t)n + i] = y[j];
+  out[2 * (size_t)n + i] = z[j];
+}
+
+static inline int nblk(int64_t n, int t = 256) { return (int)((n + t - 1) / t); }
+
+obem_status order_targets(obem_ctx *ctx, int64_t n64, const double *tx, const double *ty, const double *tz,
+                          TargetOrder *out) {
+  int n = (int)n64;
+  out->n = n;
+  if (n == 0) return OBEM_OK;
+  const int nb = 256;
+  double *bbox = (double *)ws_get(ctx, WS_BBOX, sizeof(double) * (6 * nb + 6));
+  uint32_t *k0 = (uint32_t *)ws_get(ctx, WS_KEYS0, sizeof(uint32_t) * n);
+  uint32_t *k1 = (uint32_t *)ws_get(ctx, WS_KEYS1, sizeof(uint32_t) * n);
+  int32_t *i0 = (int32_t *)ws_get(ctx, WS_IDX0, sizeof(int32_t) * n);
+  int32_t *i1 = (int32_t *)ws_get(ctx, WS_IDX1, sizeof(int32_t) * n);
+  double *xs = (double *)ws_get(ctx, WS_TSORT, sizeof(double) * 3 * (size_t)n);
+  if (!bbox || !k0 || !k1 || !i0 || !i1 || !xs) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(256), 0, ctx->stream, n, tx, ty, tz, bbox + 6);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, ctx->stream, nb, bbox + 6, bbox);
+  hipLaunchKernelGGL(k_morton, dim3(nblk(n)), dim3(256), 0, ctx->stream, n, tx, ty, tz, bbox, k0, i0);
+  size_t tmp_bytes = 0;
+  OBEM_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, k0, k1, i0, i1, n, 0, 30, ctx->stream));
+  void *tmp = ws_get(ctx, WS_SORT_TMP, tmp_bytes + 256);
+  if (!tmp) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  OBEM_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, k0, k1, i0, i1, n, 0, 30, ctx->stream));
+  hipLaunchKernelGGL(k_gather3, dim3(nblk(n)), dim3(256), 0, ctx->stream, n, i1, tx, ty, tz, xs);
+  OBEM_HIP(ctx, hipGetLastError());
+  out->perm = i1;
+  out->xs = xs;
+  return OBEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Cell (panel) field
+// ---------------------------------------------------------------------------
+constexpr int kPT = 64;               // cells per LDS tile
+constexpr int kNG = 3 + 21 + 9;       // staged FP32 geometry: centroid, 7-pt and 3-pt points
+
+struct PanelTile {
+  float g[kNG][kPT];
+  float w[4][kPT];     // area*sigma*{w0, wa, wb, 1/3}
+  float lim[2][kPT];   // (3 D)^2, (64 D)^2
+};
+
+__device__ __forceinline__ void neumaier(float &s, float &c, float v) {
+  float t = s + v;
+  if (fabsf(s) >= fabsf(v))
+    c += (s - t) + v;
+  else
+    c += (v - t) + s;
+  s = t;
+}
+
+// Near cells: FP64 closed form from the FP64 master geometry.
+template <bool WANT_V>
+__device__ __forceinline__ void near_cell(const double *__restrict__ f, int N, int k, double sig, double x0,
+                                          double x1, double x2, double &ex, double &ey, double &ez,
+                                          double &ev) {
+  d3 P[3];
+  P[0] = mk3(f[MF_AX * (size_t)N + k] - x0, f[MF_AY * (size_t)N + k] - x1, f[MF_AZ * (size_t)N + k] - x2);
+  P[1] = mk3(f[MF_BX * (size_t)N + k] - x0, f[MF_BY * (size_t)N + k] - x1, f[MF_BZ * (size_t)N + k] - x2);
+  P[2] = mk3(f[MF_CX * (size_t)N + k] - x0, f[MF_CY * (size_t)N + k] - x1, f[MF_CZ * (size_t)N + k] - x2);
+  d3 n = mk3(f[MF_NX * (size_t)N + k], f[MF_NY * (size_t)N + k], f[MF_NZ * (size_t)N + k]);
+  double twoarea = 2.0 * f[MF_AREA * (size_t)N + k];
+  d3 IE;
+  double IV;
+  cell_closed_form<WANT_V>(P, n, twoarea, IE, IV);
+  ex = fma(sig, IE.x, ex);
+  ey = fma(sig, IE.y, ey);
+  ez = fma(sig, IE.z, ez);
+  if (WANT_V) ev = fma(sig, IV, ev);
+}
+
+template <bool WANT_V>
+__global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double *__restrict__ xs, int N,
+                                                          const double *__restrict__ f,
+                                                          const double *__restrict__ sigma, double *acc) {
+  __shared__ PanelTile T;
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.x * kThreads;
+  const int i = i0 + tid;
+  const bool active = i < n_t;
+  const double c0 = xs[i0], c1 = xs[(size_t)n_t + i0], c2 = xs[2 * (size_t)n_t + i0];
+  const double x0 = active ? xs[i] : c0;
+  const double x1 = active ? xs[(size_t)n_t + i] : c1;
+  const double x2 = active ? xs[2 * (size_t)n_t + i] : c2;
+  const float r0 = (float)(x0 - c0), r1 = (float)(x1 - c1), r2 = (float)(x2 - c2);
+  float hx = 0.f, hy = 0.f, hz = 0.f, hv = 0.f, lx = 0.f, ly = 0.f, lz = 0.f, lv = 0.f;
+  double nx = 0.0, ny = 0.0, nz = 0.0, nv = 0.0;
+  for (int k0 = 0; k0 < N; k0 += kPT) {
+    const int cnt = min(kPT, N - k0);
+    __syncthreads();
+    for (int idx = tid; idx < kNG * kPT; idx += kThreads) {
+      const int fld = idx / kPT, k = idx % kPT;
+      float v = 0.f;
+      if (k < cnt) {
+        const int src = (fld < 3) ? (MF_GX + fld) : (MF_Q7 + fld - 3);
+        const int c = fld % 3;
+        const double cc = (c == 0) ? c0 : (c == 1 ? c1 : c2);
+        v = (float)(f[(size_t)src * N + k0 + k] - cc);
+      }
+      T.g[fld][k] = v;
+    }
+    if (tid < kPT) {
+      const int k = tid;
+      if (k < cnt) {
+        const double as = f[(size_t)MF_AREA * N + k0 + k] * sigma[k0 + k];
+        const double D = f[(size_t)MF_DIAM * N + k0 + k];
+        T.w[0][k] = (float)(as * Rule7::w0);
+        T.w[1][k] = (float)(as * Rule7::wa);
+        T.w[2][k] = (float)(as * Rule7::wb);
+        T.w[3][k] = (float)(as * (1.0 / 3.0));
+        T.lim[0][k] = (float)(kNearMixed * kNearMixed * D * D);
+        T.lim[1][k] = (float)(kFar3Mixed * kFar3Mixed * D * D);
+      }
+    }
+    __syncthreads();
+    float px = 0.f, py = 0.f, pz = 0.f, pv = 0.f;
+    for (int k = 0; k < cnt; ++k) {
+      const float dx = r0 - T.g[0][k], dy = r1 - T.g[1][k], dz = r2 - T.g[2][k];
+      const float R2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+      const bool nearp = R2 < T.lim[0][k];
+      if (__any(nearp)) {
+        if (nearp && active) near_cell<WANT_V>(f, N, k0 + k, sigma[k0 + k], x0, x1, x2, nx, ny, nz, nv);
+      }
+      const bool need7 = (!nearp) && (R2 < T.lim[1][k]);
+      if (__any(need7)) {
+        if (!nearp) {
+#pragma unroll
+          for (int q = 0; q < 7; ++q) {
+            const float w = T.w[q == 0 ? 0 : (q < 4 ? 1 : 2)][k];
+            const float ex = r0 - T.g[3 + 3 * q][k], ey = r1 - T.g[4 + 3 * q][k], ez = r2 - T.g[5 + 3 * q][k];
+            const float rr = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+            const float ri = __builtin_amdgcn_rsqf(rr);
+            const float wr = w * ri;
+            const float s = wr * (ri * ri);
+            px = fmaf(s, ex, px);
+            py = fmaf(s, ey, py);
+            pz = fmaf(s, ez, pz);
+            if (WANT_V) pv += wr;
+          }
+        }
+      } else if (!nearp) {
+        const float w = T.w[3][k];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const float ex = r0 - T.g[24 + 3 * q][k], ey = r1 - T.g[25 + 3 * q][k], ez = r2 - T.g[26 + 3 * q][k];
+          const float rr = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+          const float ri = __builtin_amdgcn_rsqf(rr);
+          const float wr = w * ri;
+          const float s = wr * (ri * ri);
+          px = fmaf(s, ex, px);
+          py = fmaf(s, ey, py);
+          pz = fmaf(s, ez, pz);
+          if (WANT_V) pv += wr;
+        }
+      }
+    }
+    neumaier(hx, lx, px);
+    neumaier(hy, ly, py);
+    neumaier(hz, lz, pz);
+    if (WANT_V) neumaier(hv, lv, pv);
+  }
+  if (active) {
+    acc[i] = ((double)hx + (double)lx) + nx;
+    acc[(size_t)n_t + i] = ((double)hy + (double)ly) + ny;
+    acc[2 * (size_t)n_t + i] = ((double)hz + (double)lz) + nz;
+    acc[3 * (size_t)n_t + i] = WANT_V ? ((double)hv + (double)lv) + nv : 0.0;
+  }
+}
+
+// FP64 mode: closed form up to 48 diameters, FP64 7-point rule beyond.  All
+// lanes read the same cell, so cell data come through scalar loads.
+template <bool WANT_V>
+__global__ __launch_bounds__(kThreads) void k_panel_fp64(int n_t, const double *__restrict__ xs, int N,
+                                                         const double *__restrict__ f,
+                                                         const double *__restrict__ sigma, double *acc) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const bool active = i < n_t;
+  const int ii = active ? i : 0;
+  const double x0 = xs[ii], x1 = xs[(size_t)n_t + ii], x2 = xs[2 * (size_t)n_t + ii];
+  double ex = 0.0, ey = 0.0, ez = 0.0, ev = 0.0;
+  for (int k = 0; k < N; ++k) {
+    const double dx = x0 - f[(size_t)MF_GX * N + k], dy = x1 - f[(size_t)MF_GY * N + k],
+                 dz = x2 - f[(size_t)MF_GZ * N + k];
+    const double D = f[(size_t)MF_DIAM * N + k];
+    const double R2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const bool quad = R2 >= kQuadFp64 * kQuadFp64 * D * D;
+    const double sig = sigma[k];
+    if (!__all(quad)) {
+      if (!quad) near_cell<WANT_V>(f, N, k, sig, x0, x1, x2, ex, ey, ez, ev);
+    }
+    if (__any(quad)) {
+      if (quad) {
+        const double as = f[(size_t)MF_AREA * N + k] * sig;
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+          const double w = as * (q == 0 ? Rule7::w0 : (q < 4 ? Rule7::wa : Rule7::wb));
+          const double qx = x0 - f[(size_t)(MF_Q7 + 3 * q) * N + k];
+          const double qy = x1 - f[(size_t)(MF_Q7 + 3 * q + 1) * N + k];
+          const double qz = x2 - f[(size_t)(MF_Q7 + 3 * q + 2) * N + k];
+          const double rr = fma(qx, qx, fma(qy, qy, qz * qz));
+          const double ri = 1.0 / sqrt(rr);
+          const double wr = w * ri;
+          const double s = wr * ri * ri;
+          ex = fma(s, qx, ex);
+          ey = fma(s, qy, ey);
+          ez = fma(s, qz, ez);
+          if (WANT_V) ev += wr;
+        }
+      }
+    }
+  }
+  if (active) {
+    acc[i] = ex;
+    acc[(size_t)n_t + i] = ey;
+    acc[2 * (size_t)n_t + i] = ez;
+    acc[3 * (size_t)n_t + i] = ev;
+  }
+}
+
+obem_status launch_panel_field(obem_ctx *ctx, const obem_meshh *m, const double *sigma, const TargetOrder &to,
+                               obem_precision prec, bool want_v, double *acc) {
+  const int n_t = to.n;
+  if (n_t == 0) return OBEM_OK;
+  const int N = (int)m->n;
+  dim3 grid(nblk(n_t)), block(kThreads);
+  if (prec == OBEM_MIXED) {
+    if (want_v)
+      hipLaunchKernelGGL(k_panel_mixed<true>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, acc);
+    else
+      hipLaunchKernelGGL(k_panel_mixed<false>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, acc);
+  } else {
+    if (want_v)
+      hipLaunchKernelGGL(k_panel_fp64<true>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, acc);
+    else
+      hipLaunchKernelGGL(k_panel_fp64<false>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, acc);
+  }
+  OBEM_HIP(ctx, hipGetLastError());
+  return OBEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Pairwise point-charge field, eq. (nbody) with Plummer softening
+// ---------------------------------------------------------------------------
+// Each workgroup takes 256 consecutive (sorted) targets and one chunk of the
+// sources (gridDim.y chunks, so small target sets still fill the chip), and
+// writes per-chunk partial sums part[chunk][4][n_t] (Ex, Ey, Ez, V) plus the
+// nearest opposite-species source; k_pair_reduce then sums the chunks in
+// order.  Source tiles of 256 are staged in LDS (recentred FP32 position and
+// charge, read as broadcasts).
+// Species keys: electron 0 looks for cation 1 and vice versa.
+__device__ __forceinline__ int want_key(int8_t s) { return s == 0 ? 1 : (s == 1 ? 0 : -2); }
+
+// EXCL: 0 = no exclusion (a coincident term contributes exactly 0 to E when
+// soft > 0), 1 = drop zero-distance terms (soft == 0), 2 = drop the source
+// whose index equals the target's caller index (targets are the sources).
+template <bool WANT_V, bool NN, int EXCL>
+__global__ __launch_bounds__(kThreads) void k_pair_mixed(int n_t, const double *__restrict__ xs,
+                                                         const int32_t *__restrict__ perm, int n_s,
+                                                         const double *__restrict__ sx,
+                                                         const double *__restrict__ sy,
+                                                         const double *__restrict__ sz,
+                                                         const double *__restrict__ sq,
+                                                         const int8_t *__restrict__ species, float soft2,
+                                                         int chunk, double *part, float *nn_d2p,
+                                                         int32_t *nn_ip) {
+  __shared__ float4 S[kThreads];
+  __shared__ int K[kThreads];
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.x * kThreads;
+  const int i = i0 + tid;
+  const bool active = i < n_t;
+  const double c0 = xs[i0], c1 = xs[(size_t)n_t + i0], c2 = xs[2 * (size_t)n_t + i0];
+  const double x0 = active ? xs[i] : c0;
+  const double x1 = active ? xs[(size_t)n_t + i] : c1;
+  const double x2 = active ? xs[2 * (size_t)n_t + i] : c2;
+  const float r0 = (float)(x0 - c0), r1 = (float)(x1 - c1), r2 = (float)(x2 - c2);
+  int want = -2;
+  if (NN && active) want = want_key(species[perm[i]]);
+  const int self = active ? perm[i] : -1;
+  const int jb = blockIdx.y * chunk;
+  const int je = min(n_s, jb + chunk);
+  float hx = 0.f, hy = 0.f, hz = 0.f, hv = 0.f, lx = 0.f, ly = 0.f, lz = 0.f, lv = 0.f;
+  float best = INFINITY;
+  int bidx = -1;
+  for (int jt = jb; jt < je; jt += kThreads) {
+    const int cnt = min(kThreads, je - jt);
+    __syncthreads();
+    if (tid < cnt) {
+      const int j = jt + tid;
+      S[tid] = make_float4((float)(sx[j] - c0), (float)(sy[j] - c1), (float)(sz[j] - c2), (float)sq[j]);
+      if (NN) K[tid] = species[j];
+    }
+    __syncthreads();
+    float px = 0.f, py = 0.f, pz = 0.f, pv = 0.f;
+    for (int jj = 0; jj < cnt; ++jj) {
+      const float4 s = S[jj];
+      const float dx = r0 - s.x, dy = r1 - s.y, dz = r2 - s.z;
+      const float rr = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, soft2)));
+      float ri = __builtin_amdgcn_rsqf(rr);
+      if (EXCL == 1) ri = rr > 0.f ? ri : 0.f;
+      if (EXCL == 2) ri = (jt + jj == self) ? 0.f : ri;
+      const float qr = s.w * ri;
+      const float w = qr * (ri * ri);
+      px = fmaf(w, dx, px);
+      py = fmaf(w, dy, py);
+      pz = fmaf(w, dz, pz);
+      if (WANT_V) pv += qr;
+      if (NN) {
+        if (K[jj] == want && rr < best && (EXCL != 1 || rr > 0.f)) {
+          best = rr;
+          bidx = jt + jj;
+        }
+      }
+    }
+    neumaier(hx, lx, px);
+    neumaier(hy, ly, py);
+    neumaier(hz, lz, pz);
+    if (WANT_V) neumaier(hv, lv, pv);
+  }
+  if (active) {
+    const size_t o = (size_t)blockIdx.y * 4 * n_t;
+    part[o + i] = (double)hx + (double)lx;
+    part[o + (size_t)n_t + i] = (double)hy + (double)ly;
+    part[o + 2 * (size_t)n_t + i] = (double)hz + (double)lz;
+    part[o + 3 * (size_t)n_t + i] = WANT_V ? (double)hv + (double)lv : 0.0;
+    if (NN) {
+      nn_d2p[(size_t)blockIdx.y * n_t + i] = best;
+      nn_ip[(size_t)blockIdx.y * n_t + i] = bidx;
+    }
+  }
+}
+
+template <bool WANT_V, bool NN, int EXCL>
+__global__ __launch_bounds__(kThreads) void k_pair_fp64(int n_t, const double *__restrict__ xs,
+                                                        const int32_t *__restrict__ perm, int n_s,
+                                                        const double *__restrict__ sx,
+                                                        const double *__restrict__ sy,
+                                                        const double *__restrict__ sz,
+                                                        const double *__restrict__ sq,
+                                                        const int8_t *__restrict__ species, double soft2,
+                                                        int chunk, double *part, double *nn_d2p,
+                                                        int32_t *nn_ip) {
+  __shared__ double4 S[kThreads];
+  __shared__ int K[kThreads];
+  const int tid = threadIdx.x;
+  const int i = blockIdx.x * kThreads + tid;
+  const bool active = i < n_t;
+  const int ii = active ? i : 0;
+  const double x0 = xs[ii], x1 = xs[(size_t)n_t + ii], x2 = xs[2 * (size_t)n_t + ii];
+  int want = -2;
+  if (NN && active) want = want_key(species[perm[i]]);
+  const int self = active ? perm[i] : -1;
+  const int jb = blockIdx.y * chunk;
+  const int je = min(n_s, jb + chunk);
+  double ex = 0.0, ey = 0.0, ez = 0.0, ev = 0.0;
+  double best = INFINITY;
+  int bidx = -1;
+  for (int jt = jb; jt < je; jt += kThreads) {
+    const int cnt = min(kThreads, je - jt);
+    __syncthreads();
+    if (tid < cnt) {
+      const int j = jt + tid;
+      S[tid] = make_double4(sx[j], sy[j], sz[j], sq[j]);
+      if (NN) K[tid] = species[j];
+    }
+    __syncthreads();
+    for (int jj = 0; jj < cnt; ++jj) {
+      const double4 s = S[jj];
+      const double dx = x0 - s.x, dy = x1 - s.y, dz = x2 - s.z;
+      const double dd = fma(dx, dx, fma(dy, dy, dz * dz));
+      const double rr = dd + soft2;
+      double ri = 1.0 / sqrt(rr);
+      if (EXCL == 1) ri = rr > 0.0 ? ri : 0.0;
+      if (EXCL == 2) ri = (jt + jj == self) ? 0.0 : ri;
+      const double qr = s.w * ri;
+      const double w = qr * ri * ri;
+      ex = fma(w, dx, ex);
+      ey = fma(w, dy, ey);
+      ez = fma(w, dz, ez);
+      if (WANT_V) ev += qr;
+      if (NN) {
+        if (K[jj] == want && dd < best && (EXCL != 1 || rr > 0.0)) {
+          best = dd;
+          bidx = jt + jj;
+        }
+      }
+    }
+  }
+  if (active) {
+    const size_t o = (size_t)blockIdx.y * 4 * n_t;
+    part[o + i] = ex;
+    part[o + (size_t)n_t + i] = ey;
+    part[o + 2 * (size_t)n_t + i] = ez;
+    part[o + 3 * (size_t)n_t + i] = ev;
+    if (NN) {
+      nn_d2p[(size_t)blockIdx.y * n_t + i] = best;
+      nn_ip[(size_t)blockIdx.y * n_t + i] = bidx;
+    }
+  }
+}
+
+// acc[c][i] = (has_base ? acc[c][i] : 0) + sum over chunks in order; nearest
+// partner = smallest distance, ties to the earlier chunk (lower source index).
+template <typename DT>
+__global__ __launch_bounds__(256) void k_pair_reduce(int n_t, int nsplit, const double *__restrict__ part,
+                                                     int has_base, double *acc, const DT *__restrict__ nn_d2p,
+                                                     const int32_t *__restrict__ nn_ip, double *nn_d2,
+                                                     int32_t *nn_idx) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_t) return;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double s = has_base ? acc[(size_t)c * n_t + i] : 0.0;
+    for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * 4 * n_t + (size_t)c * n_t + i];
+    acc[(size_t)c * n_t + i] = s;
+  }
+  if (nn_idx) {
+    DT best = INFINITY;
+    int32_t bi = -1;
+    for (int k = 0; k < nsplit; ++k) {
+      DT d = nn_d2p[(size_t)k * n_t + i];
+      if (d < best) {
+        best = d;
+        bi = nn_ip[(size_t)k * n_t + i];
+      }
+    }
+    nn_d2[i] = (double)best;
+    nn_idx[i] = bi;
+  }
+}
+
+template <bool WANT_V, bool NN, int CZ>
+static void launch_pair_t(obem_ctx *ctx, dim3 grid, int n_t, const double *xs, const int32_t *perm, int n_s,
+                          const double *sx, const double *sy, const double *sz, const double *sq,
+                          const int8_t *sp, double soft, obem_precision prec, int chunk, double *part,
+                          void *nnd, int32_t *nni) {
+  if (prec == OBEM_MIXED)
+    hipLaunchKernelGGL((k_pair_mixed<WANT_V, NN, CZ>), grid, dim3(kThreads), 0, ctx->stream, n_t, xs, perm, n_s,
+                       sx, sy, sz, sq, sp, (float)(soft * soft), chunk, part, (float *)nnd, nni);
+  else
+    hipLaunchKernelGGL((k_pair_fp64<WANT_V, NN, CZ>), grid, dim3(kThreads), 0, ctx->stream, n_t, xs, perm, n_s,
+                       sx, sy, sz, sq, sp, soft * soft, chunk, part, (double *)nnd, nni);
+}
+
+obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, const double *sy, const double *sz,
+                              const double *sq, const TargetOrder &to, double soft, obem_precision prec,
+                              bool tgt_is_src, bool want_v, const int8_t *species, double *acc, int32_t *nn_idx,
+                              double *nn_d2) {
+  const int n_t = to.n;
+  const int n_s = (int)n_src;
+  if (n_t == 0 || n_s == 0) return OBEM_OK;
+  const int bt = nblk(n_t);
+  // enough workgroups to fill 256 CUs several times over, chunks >= 1024 sources
+  int nsplit = (2048 + bt - 1) / bt;
+  nsplit = std::max(1, std::min(nsplit, (n_s + 1023) / 1024));
+  nsplit = std::min(nsplit, 64);
+  int chunk = (n_s + nsplit - 1) / nsplit;
+  chunk = (chunk + kThreads - 1) / kThreads * kThreads;
+  nsplit = (n_s + chunk - 1) / chunk;
+  double *part = (double *)ws_get(ctx, WS_PART, sizeof(double) * 4 * (size_t)n_t * nsplit);
+  const bool nn = nn_idx != nullptr;
+  void *nnd = nullptr;
+  int32_t *nni = nullptr;
+  if (nn) {
+    nnd = ws_get(ctx, WS_NN, sizeof(double) * (size_t)n_t * nsplit);
+    nni = (int32_t *)ws_get(ctx, WS_MISC7, sizeof(int32_t) * (size_t)n_t * nsplit);
+    if (!nnd || !nni) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  }
+  if (!part) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  // soft == 0: drop zero-distance terms (the self term and coincident
+  // points); soft > 0 with targets = sources: only the potential needs the
+  // self term removed (its field term is exactly 0).
+  int excl = 0;
+  if (!(soft > 0.0))
+    excl = 1;
+  else if (tgt_is_src && want_v)
+    excl = 2;
+  dim3 grid(bt, nsplit);
+#define PAIR_CASE(V, N, Z)                                                                                   \
+  if (want_v == V && nn == N && excl == Z)                                                                   \
+    launch_pair_t<V, N, Z>(ctx, grid, n_t, to.xs, to.perm, n_s, sx, sy, sz, sq, species, soft, prec, chunk,  \
+                           part, nnd, nni);
+  PAIR_CASE(false, false, 0)
+  PAIR_CASE(false, false, 1)
+  PAIR_CASE(false, false, 2)
+  PAIR_CASE(false, true, 0)
+  PAIR_CASE(false, true, 1)
+  PAIR_CASE(false, true, 2)
+  PAIR_CASE(true, false, 0)
+  PAIR_CASE(true, false, 1)
+  PAIR_CASE(true, false, 2)
+  PAIR_CASE(true, true, 0)
+  PAIR_CASE(true, true, 1)
+  PAIR_CASE(true, true, 2)
+#undef PAIR_CASE
+  OBEM_HIP(ctx, hipGetLastError());
+  // the accumulator already holds the cell field when the panel kernel ran
+  if (prec == OBEM_MIXED)
+    hipLaunchKernelGGL(k_pair_reduce<float>, dim3(nblk(n_t)), dim3(256), 0, ctx->stream, n_t, nsplit, part, 1, acc,
+                       (const float *)nnd, nni, nn_d2, nn_idx);
+  else
+    hipLaunchKernelGGL(k_pair_reduce<double>, dim3(nblk(n_t)), dim3(256), 0, ctx->stream, n_t, nsplit, part, 1,
+                       acc, (const double *)nnd, nni, nn_d2, nn_idx);
+  OBEM_HIP(ctx, hipGetLastError());
+  return OBEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Scatter back to caller order, scaling by k_e
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scatter(int n, const int32_t *__restrict__ perm, const double *__restrict__ acc,
+                                                 double scale, double *Ex, double *Ey, double *Ez, double *V) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int j = perm[i];
+  Ex[j] = scale * acc[i];
+  Ey[j] = scale * acc[(size_t)n + i];
+  Ez[j] = scale * acc[2 * (size_t)n + i];
+  if (V) V[j] = scale * acc[3 * (size_t)n + i];
+}
+
+__global__ __launch_bounds__(256) void k_fill(size_t n, double *p, double v) {
+  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+obem_status launch_scatter(obem_ctx *ctx, const TargetOrder &to, const double *acc, double scale, double *Ex,
+                           double *Ey, double *Ez, double *V) {
+  if (to.n == 0) return OBEM_OK;
+  hipLaunchKernelGGL(k_scatter, dim3(nblk(to.n)), dim3(256), 0, ctx->stream, to.n, to.perm, acc, scale, Ex, Ey,
+                     Ez, V);
+  OBEM_HIP(ctx, hipGetLastError());
+  return OBEM_OK;
+}
+
+obem_status launch_fill(obem_ctx *ctx, double *p, size_t n, double v) {
+  if (n == 0) return OBEM_OK;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, n, p, v);
+  OBEM_HIP(ctx, hipGetLastError());
+  return OBEM_OK;
+}
+
+}  // namespace obem

@@ -1,0 +1,133 @@
+// Internal declarations of libobem: context / mesh-handle layout, error
+// plumbing and constants shared by the HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "obem.h"
+
+namespace obem {
+
+// CODATA 2018.
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kQe = 1.602176634e-19;
+constexpr double kMe = 9.1093837015e-31;
+constexpr double kKb = 1.380649e-23;
+constexpr double kAmu = 1.66053906660e-27;
+constexpr double kKe = 1.0 / (4.0 * kPi * kEps0);
+
+// Far-field regimes of the cell field (ratio of target distance from the
+// cell centroid to the cell diameter D):
+//   mixed: R < 3 D   -> FP64 closed form
+//          R < 64 D  -> FP32 7-point degree-5 rule
+//          else      -> FP32 3-point degree-2 rule
+//   fp64:  R < 48 D  -> FP64 closed form, else FP64 7-point rule
+constexpr double kNearMixed = 3.0;
+constexpr double kFar3Mixed = 64.0;
+constexpr double kQuadFp64 = 48.0;
+
+// Grow-only device buffer owned by a context.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace obem
+
+// Number of per-cell FP64 SoA arrays kept by a bound mesh.
+enum MeshField {
+  MF_AX = 0, MF_AY, MF_AZ, MF_BX, MF_BY, MF_BZ, MF_CX, MF_CY, MF_CZ,  // vertices
+  MF_NX, MF_NY, MF_NZ,                                                // unit normal
+  MF_GX, MF_GY, MF_GZ,                                                // centroid
+  MF_AREA, MF_DIAM, MF_EPS1, MF_EPS2,
+  MF_Q7 = 19,            // 7 quadrature points x 3 coordinates (21 arrays)
+  MF_Q3 = MF_Q7 + 21,    // 3 quadrature points x 3 coordinates (9 arrays)
+  MF_COUNT = MF_Q3 + 9
+};
+
+struct obem_meshh {
+  int64_t n = 0;
+  int64_t n_dd = 0;
+  double *f = nullptr;        // MF_COUNT x n, field-major
+  int8_t *kind = nullptr;
+  double bbox_lo[3], bbox_hi[3];
+  double max_diam = 0;
+  // collocation system (lazy)
+  double *A = nullptr;        // n x n column-major
+  double *LU = nullptr;       // n x n column-major
+  int32_t *ipiv = nullptr;
+  int32_t *info = nullptr;
+  bool factored = false;
+  double anorm_inf = 0;       // max_i sum_j |A_ij|
+  // absorption grid (uniform cells over the bbox, CSR of cell -> cell ids)
+  int32_t grid_n[3] = {0, 0, 0};
+  double grid_lo[3], grid_h[3];
+  int32_t *grid_start = nullptr;   // n_cells + 1
+  int32_t *grid_items = nullptr;
+  const double *field(int k) const { return f + (size_t)k * (size_t)n; }
+};
+
+struct obem_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool sticky = false;
+  std::string err;
+  obem::DevBuf ws[24];
+  void *rocblas = nullptr;   // rocblas_handle, created on first solve
+};
+
+namespace obem {
+
+obem_status fail(obem_ctx *ctx, obem_status st, const char *fmt, ...);
+obem_status hip_fail(obem_ctx *ctx, hipError_t e, const char *what, int line);
+// Ensure workspace slot `slot` holds at least `bytes`; returns device pointer or nullptr.
+void *ws_get(obem_ctx *ctx, int slot, size_t bytes);
+bool is_device_ptr(const void *p);
+
+#define OBEM_HIP(ctx, call)                                          \
+  do {                                                               \
+    hipError_t e_ = (call);                                          \
+    if (e_ != hipSuccess) return obem::hip_fail(ctx, e_, #call, __LINE__); \
+  } while (0)
+
+// Workspace slots.
+enum WsSlot {
+  WS_BBOX = 0, WS_KEYS0, WS_KEYS1, WS_IDX0, WS_IDX1, WS_SORT_TMP, WS_TSORT, WS_ACC, WS_PART,
+  WS_NN, WS_MISC0, WS_MISC1, WS_MISC2, WS_MISC3, WS_MISC4, WS_MISC5, WS_MISC6, WS_MISC7,
+  WS_SOLVE0, WS_SOLVE1, WS_SOLVE2
+};
+
+// Target ordering (Morton keys) used by the field kernels.
+struct TargetOrder {
+  int32_t n = 0;
+  int32_t *perm = nullptr;     // sorted position -> caller index
+  double *xs = nullptr;        // sorted FP64 SoA, 3 x n
+};
+obem_status order_targets(obem_ctx *ctx, int64_t n, const double *tx, const double *ty,
+                          const double *tz, TargetOrder *out);
+
+// Field kernels (field.hip).  acc: 4 x n FP64 accumulator in sorted order
+// (Ex, Ey, Ez, V) in units of 1/k_e.
+obem_status launch_panel_field(obem_ctx *ctx, const obem_meshh *m, const double *sigma,
+                               const TargetOrder &to, obem_precision prec, bool want_v, double *acc);
+obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, const double *sy,
+                              const double *sz, const double *sq, const TargetOrder &to, double soft,
+                              obem_precision prec, bool tgt_is_src, bool want_v, const int8_t *species,
+                              double *acc, int32_t *nn_idx, double *nn_d2);
+obem_status launch_scatter(obem_ctx *ctx, const TargetOrder &to, const double *acc, double scale,
+                           double *Ex, double *Ey, double *Ez, double *V);
+obem_status launch_fill(obem_ctx *ctx, double *p, size_t n, double v);
+
+// Collocation system (bem.hip).
+obem_status bem_factor(obem_ctx *ctx, obem_meshh *m);
+obem_status bem_solve(obem_ctx *ctx, obem_meshh *m, const double *rhs, double *sigma, int max_refine,
+                      obem_solve_info *info);
+void bem_release(obem_meshh *m);
+void solver_release(obem_ctx *ctx);
+
+}  // namespace obem

@@ -18,3 +18,17 @@ def orc():
 
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def ctx():
+    import torch
+
+    from paper_2110_09214_amd import binding
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = binding.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()

@@ -1,0 +1,118 @@
+"""GPU parity of field_eval against the CPU oracle (eqs. (BEM3), (nbody)).
+
+Tolerances: relative L2 over all targets and components <= 1e-12 in FP64
+mode and <= 1e-5 in mixed mode (the contract of the field path)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2110_09214_amd import binding as B
+from paper_2110_09214_amd import workloads as W
+from gpu_helpers import bind, dev, host, rel_l2, synthetic_sigma
+
+pytestmark = pytest.mark.gpu
+TOL = {B.OBEM_FP64: 1e-12, B.OBEM_MIXED: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def plates(orc):
+    m = W.parallel_plate_mesh()
+    sig, _ = orc.bem_solve(m, refine=1)
+    return m, sig
+
+
+@pytest.mark.parametrize("prec", [B.OBEM_FP64, B.OBEM_MIXED])
+def test_pairwise_config1_electrons(ctx, orc, prec):
+    x, q = W.parallel_plate_electrons()
+    E_ref, V_ref = orc.pair_field(x, x, q, 1e-7, tgt_is_src=True, want_v=True)
+    E, V = B.field_eval(ctx, None, None, dev(x), dev(q), dev(x), 1e-7, prec, tgt_is_src=True, want_v=True)
+    print("pair cfg1", prec, rel_l2(host(E), E_ref), rel_l2(host(V), V_ref))
+    assert rel_l2(host(E), E_ref) <= TOL[prec]
+    assert rel_l2(host(V), V_ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [B.OBEM_FP64, B.OBEM_MIXED])
+@pytest.mark.parametrize("soft", [0.0, 2e-7])
+def test_pairwise_separate_ragged(ctx, orc, prec, soft):
+    rng = np.random.default_rng(11)
+    xs = rng.normal(size=(3001, 3)) * 1e-4
+    q = rng.choice([-1.0, 1.0], size=3001) * W.E_CHARGE
+    xt = rng.normal(size=(1037, 3)) * 1e-4
+    E_ref, V_ref = orc.pair_field(xt, xs, q, soft, want_v=True)
+    E, V = B.field_eval(ctx, None, None, dev(xs), dev(q), dev(xt), soft, prec, want_v=True)
+    assert rel_l2(host(E), E_ref) <= TOL[prec]
+    assert rel_l2(host(V), V_ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [B.OBEM_FP64, B.OBEM_MIXED])
+def test_pairwise_tiny_and_empty(ctx, orc, prec):
+    xs = np.array([[1e-6, 2e-6, -3e-6]])
+    q = np.array([W.E_CHARGE])
+    xt = np.array([[0.0, 0.0, 0.0]])
+    E = B.field_eval(ctx, None, None, dev(xs), dev(q), dev(xt), 0.0, prec)
+    assert rel_l2(host(E), orc.pair_field(xt, xs, q, 0.0)) <= TOL[prec]
+    # no sources and no cells: zero field
+    E = B.field_eval(ctx, None, None, None, None, dev(np.ones((5, 3))), 0.0, prec)
+    assert np.all(host(E) == 0.0)
+
+
+def test_coincident_points_are_dropped_without_softening(ctx, orc):
+    x = np.array([[0.0, 0.0, 0.0], [1e-6, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    q = np.array([1.0, -2.0, 3.0]) * W.E_CHARGE
+    E = host(B.field_eval(ctx, None, None, dev(x), dev(q), dev(x), 0.0, B.OBEM_FP64, tgt_is_src=True))
+    assert np.all(np.isfinite(E))
+    ref = orc.pair_field(x[1:2], x[[0, 2]], q[[0, 2]], 0.0)
+    assert rel_l2(E[1:2], ref) <= 1e-14
+    for i in (0, 2):   # the coincident partner's term is dropped
+        assert rel_l2(E[i:i + 1], orc.pair_field(x[i:i + 1], x[[1]], q[[1]], 0.0)) <= 1e-14
+
+
+@pytest.mark.parametrize("prec", [B.OBEM_FP64, B.OBEM_MIXED])
+def test_panel_field_parallel_plates(ctx, orc, plates, prec):
+    m, sig = plates
+    rng = np.random.default_rng(7)
+    pts = rng.uniform([-6e-3, -6e-3, -0.5e-3], [6e-3, 6e-3, 1.5e-3], size=(1500, 3))
+    # points within a fraction of a cell diameter of the plates (FP64 near path)
+    near = rng.uniform([-4e-3, -4e-3, 0], [4e-3, 4e-3, 0], size=(300, 3))
+    near[:, 2] = np.where(rng.random(300) < 0.5, 1e-6, 1e-3 - 2e-6)
+    x = np.concatenate([pts, near])
+    E_ref, V_ref = orc.panel_field(x, m.a, m.b, m.c, sig, want_v=True)
+    bm = bind(ctx, m)
+    E, V = B.field_eval(ctx, bm, dev(sig), None, None, dev(x), 0.0, prec, want_v=True)
+    print("plates", prec, rel_l2(host(E), E_ref), rel_l2(host(V), V_ref))
+    assert rel_l2(host(E), E_ref) <= TOL[prec]
+    assert rel_l2(host(V), V_ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [B.OBEM_FP64, B.OBEM_MIXED])
+def test_config1_cells_plus_electrons(ctx, orc, plates, prec):
+    """The parallel-plate workload: cells + 4095 other electrons at each of
+    the 4096 electrons."""
+    m, sig = plates
+    x, q = W.parallel_plate_electrons()
+    E_ref = orc.panel_field(x, m.a, m.b, m.c, sig) + orc.pair_field(x, x, q, 1e-7, tgt_is_src=True)
+    bm = bind(ctx, m)
+    E = B.field_eval(ctx, bm, dev(sig), dev(x), dev(q), dev(x), 1e-7, prec, tgt_is_src=True)
+    err = rel_l2(host(E), E_ref)
+    print("config1 total", prec, err)
+    assert err <= TOL[prec]
+    # deterministic: a second call is bitwise identical
+    E2 = B.field_eval(ctx, bm, dev(sig), dev(x), dev(q), dev(x), 1e-7, prec, tgt_is_src=True)
+    assert torch.equal(E, E2)
+
+
+@pytest.mark.parametrize("prec", [B.OBEM_FP64, B.OBEM_MIXED])
+def test_gem_cell_full_size_sampled(ctx, orc, prec):
+    """GEM unit cell (~40k cells), 1M field points; the oracle checks 400
+    sampled points (uniform sample plus the points nearest the foil)."""
+    m = W.gem_cell_mesh()
+    sig = synthetic_sigma(m)
+    x = W.gem_cell_points()
+    bm = bind(ctx, m)
+    E = host(B.field_eval(ctx, bm, dev(sig), None, None, dev(x), 0.0, prec))
+    rng = np.random.default_rng(5)
+    idx = np.concatenate([rng.choice(len(x), 300, replace=False), np.argsort(np.abs(x[:, 2]))[:100]])
+    E_ref = orc.panel_field(x[idx], m.a, m.b, m.c, sig)
+    err = rel_l2(E[idx], E_ref)
+    print("gem", prec, err)
+    assert err <= TOL[prec]
