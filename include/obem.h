@@ -117,7 +117,8 @@ obem_status obem_mesh_geometry(obem_ctx *ctx, const obem_meshh *mesh, double *ar
  * products, correction solved with the same factors) until the backward
  * error stops decreasing.  rhs and sigma_out are device arrays of length
  * n_panels (they may alias).  info (host) may be NULL: then nothing is
- * synchronised.  Zero pivot: OBEM_ESINGULAR.  Backward error above 1e-14
+ * synchronised.  A zero pivot, or a smallest pivot below n * 2^-52 times the
+ * largest (duplicate or coincident cells), gives OBEM_ESINGULAR.  Backward error above 1e-14
  * after the sweeps: OBEM_ENOCONV (sigma_out is still written, info filled). */
 obem_status bem_solve_charges(obem_ctx *ctx, obem_meshh *mesh, const double *rhs, double *sigma_out,
                               int max_refine, obem_solve_info *info);

@@ -399,3 +399,18 @@ def track_step(state, mesh, sigma, gas, params, dd_counts, rhs0=None, area=None,
     stats["n_live"] = new_state["x"].shape[0]
     stats["children"] = take
     return new_state, sigma, new_counts, stats, E
+
+
+def fd_particle(x, q, w, soft, mesh, sigma, m, axis, h):
+    """Central difference of L = sum_i w_i . E(x_i) in coordinate `axis` of
+    particle m (targets = sources), re-summing only the terms involving m."""
+    x = _f64(x).reshape(-1, 3)
+    w = _f64(w).reshape(-1, 3)
+    if mesh is not None:
+        a, b, c, N, sg = _f64(mesh.a), _f64(mesh.b), _f64(mesh.c), mesh.n, _f64(sigma)
+    else:
+        a = b = c = np.zeros((1, 3))
+        N, sg = 0, np.zeros(1)
+    lib().oc_fd_particle.restype = C.c_double
+    return lib().oc_fd_particle(C.c_int64(x.shape[0]), _p(x), _p(_f64(q)), _p(w), C.c_double(soft), C.c_int64(N),
+                                _p(a), _p(b), _p(c), _p(sg), C.c_int64(m), C.c_int(axis), C.c_double(h))

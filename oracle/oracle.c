@@ -663,7 +663,11 @@ void oc_mc_step(int64_t n, double *x, double *v, int8_t *species, const int64_t 
             isotropic(u01(w2[0]), u01(w2[1]), uh);
             isotropic(u01(w2[2]), u01(w2[3]), ud);
             double eres_j = e_res * qe;
-            double r = ke * qe / (2.0 * eres_j);
+            /* eq. (distIoni) with the energy in eV (volts): r = k_e e / (2 E_res[eV]),
+             * i.e. the separation at which the pair's Coulomb energy k_e e^2 / r is
+             * 2 E_res (the same convention gives 4.59e-11 m for eq. (distRecomb)
+             * at 15.7 eV). */
+            double r = ke * qe * qe / (2.0 * eres_j);
             double s = sqrt(2.0 * (0.5 * eres_j) / me);
             double si = sqrt(2.0 * e_therm / g->m_cation);
             int nc = n_child[i];
@@ -720,4 +724,55 @@ void oc_mc_step(int64_t n, double *x, double *v, int8_t *species, const int64_t 
   }
   for (int k = 0; k < 10; ++k) counters[k] += cnt[k];
   free(T);
+}
+
+/* Central difference of L = sum_i w_i . E(x_i) (targets = sources = the n
+ * particles, cells with sigma) with respect to coordinate `axis` of particle
+ * m, step h.  Only the terms that involve particle m change, so they are
+ * re-summed directly (pairwise differences of the kernel), which keeps the
+ * difference accurate at any n. */
+double oc_fd_particle(int64_t n, const double *x, const double *q, const double *w, double soft, int64_t N,
+                      const double *a, const double *b, const double *c, const double *sigma, int64_t m, int axis,
+                      double h) {
+  real ke = k_e(), s2 = (real)soft * (real)soft;
+  v3 xm = ld(x + 3 * m);
+  v3 dp = mk(axis == 0 ? h : 0, axis == 1 ? h : 0, axis == 2 ? h : 0);
+  v3 xp = add(xm, dp), xn = sub(xm, dp);
+  real acc = 0;
+  /* source role: other targets see particle m move */
+#pragma omp parallel for reduction(+ : acc) schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    if (i == m) continue;
+    v3 xi = ld(x + 3 * i);
+    v3 d1 = sub(xi, xp), d2 = sub(xi, xn);
+    real S1 = dot(d1, d1) + s2, S2 = dot(d2, d2) + s2;
+    real i1 = 1.0L / (S1 * sqrtl(S1)), i2 = 1.0L / (S2 * sqrtl(S2));
+    v3 dK = sub(scl(d1, i1), scl(d2, i2));
+    acc += (real)q[m] * dot(ld(w + 3 * i), dK);
+  }
+  /* target role: the field at particle m itself */
+  real acc2 = 0;
+#pragma omp parallel for reduction(+ : acc2) schedule(static)
+  for (int64_t j = 0; j < n; ++j) {
+    if (j == m) continue;
+    v3 xj = ld(x + 3 * j);
+    v3 d1 = sub(xp, xj), d2 = sub(xn, xj);
+    real S1 = dot(d1, d1) + s2, S2 = dot(d2, d2) + s2;
+    real i1 = 1.0L / (S1 * sqrtl(S1)), i2 = 1.0L / (S2 * sqrtl(S2));
+    v3 dK = sub(scl(d1, i1), scl(d2, i2));
+    acc2 += (real)q[j] * dot(ld(w + 3 * m), dK);
+  }
+  real acc3 = 0;
+  if (N > 0) {
+#pragma omp parallel for reduction(+ : acc3) schedule(static)
+    for (int64_t k = 0; k < N; ++k) {
+      tri_t T;
+      tri_setup(a + 3 * k, b + 3 * k, c + 3 * k, &T);
+      v3 e1, e2;
+      tri_IV_IE(&T, xp, NULL, &e1);
+      tri_IV_IE(&T, xn, NULL, &e2);
+      acc3 += (real)sigma[k] * dot(ld(w + 3 * m), sub(e1, e2));
+    }
+  }
+  return (double)(ke * (acc + acc2 + acc3) / (2.0L * (real)h));
 }

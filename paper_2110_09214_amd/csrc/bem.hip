@@ -164,6 +164,31 @@ __global__ __launch_bounds__(256) void k_absmax3(int N, const double *a, const d
   if (threadIdx.x < 3) out[threadIdx.x] = s[threadIdx.x][0];
 }
 
+// min and max |U_ii| of the LU factors (single block, fixed order)
+__global__ __launch_bounds__(256) void k_diag_minmax(int N, const double *__restrict__ LU, double *out) {
+  __shared__ double lo[256], hi[256];
+  double a = INFINITY, b = 0.0;
+  for (int i = threadIdx.x; i < N; i += 256) {
+    const double d = fabs(LU[(size_t)i * N + i]);
+    a = fmin(a, d);
+    b = fmax(b, d);
+  }
+  lo[threadIdx.x] = a;
+  hi[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      lo[threadIdx.x] = fmin(lo[threadIdx.x], lo[threadIdx.x + w]);
+      hi[threadIdx.x] = fmax(hi[threadIdx.x], hi[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = lo[0];
+    out[1] = hi[0];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_axpy1(int N, const double *__restrict__ d, double *x) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < N) x[i] += d[i];
@@ -256,9 +281,20 @@ obem_status bem_factor(obem_ctx *ctx, obem_meshh *m) {
   if (rocsolver_dgetrf(h, N, N, m->LU, N, m->ipiv, m->info) != rocblas_status_success)
     return fail(ctx, OBEM_EDEVICE, "rocsolver_dgetrf failed");
   int32_t info = 0;
+  double *dm = (double *)ws_get(ctx, WS_MISC5, 2 * sizeof(double));
+  if (!dm) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  hipLaunchKernelGGL(k_diag_minmax, dim3(1), dim3(256), 0, ctx->stream, N, m->LU, dm);
+  OBEM_HIP(ctx, hipGetLastError());
+  double hd[2] = {0, 0};
   OBEM_HIP(ctx, hipMemcpyAsync(&info, m->info, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  OBEM_HIP(ctx, hipMemcpyAsync(hd, dm, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
   if (info != 0) return fail(ctx, OBEM_ESINGULAR, "zero pivot U(%d,%d): collocation matrix is singular", info, info);
+  // a pivot at rounding level relative to the largest one: numerically singular
+  // (duplicate or coincident cells)
+  if (!(hd[0] > (double)N * 2.220446049250313e-16 * hd[1]))
+    return fail(ctx, OBEM_ESINGULAR, "pivot ratio min|U_ii|/max|U_ii| = %.3e: collocation matrix is numerically singular",
+                hd[1] > 0 ? hd[0] / hd[1] : 0.0);
   m->factored = true;
   return OBEM_OK;
 }

@@ -1,7 +1,789 @@
-// Transport step (in progress).
+// One tracking step of the dynamic option (sections 3.3-3.4): charging-up
+// right-hand side and re-solve, field at every particle, electron-cation
+// recombination, constant-field flights with null-collision Monte Carlo,
+// absorption on cells, compaction with deterministic ids.
+//
+// Determinism: random numbers are counter-based (Philox4x32-10 keyed by the
+// seed, counter (id, step, flight)); every reduction is over integers
+// (event counts, charging counts, recombination keys) or has a fixed order,
+// so a step is bitwise reproducible.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "cellmath.hpp"
 #include "obem_internal.hpp"
 
-extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *, obem_particles *, const obem_gas *,
-                                  const obem_step_params *, int64_t *, double *, obem_step_stats *) {
-  return obem::fail(ctx, OBEM_EINVAL, "track_step: not available in this build");
+namespace obem {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds of the 4x32 S-P network.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox10(uint4 c, uint2 k) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k.x += 0x9E3779B9u;
+      k.y += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k.x, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k.y, (uint32_t)p0);
+  }
+  return c;
+}
+__device__ __forceinline__ double u01(uint32_t w) { return ((double)w + 0.5) * (1.0 / 4294967296.0); }
+
+struct GasDev {
+  int n;
+  double e_min, e_max;
+  const double *xs;
+  double thr[5];
+  double density, temperature, m_gas, m_cation, m_anion, ion_iso, ion_back;
+  double nu_e, nu_i;
+};
+
+struct StepDev {
+  double dt;
+  uint32_t step;
+  uint32_t key0, key1;
+  int max_coll, max_ion;
+  double lo[3], hi[3];
+};
+
+struct GridDev {
+  int nx, ny, nz;
+  double lo[3], h[3];
+  const int32_t *start, *items;
+  int N;
+  const double *f;
+  const int8_t *kind;
+};
+
+// Cross section k at eps (eV): linear in the normalised lethargy of eq.
+// (leth) between log-spaced nodes, clamped to the end nodes.
+__device__ __forceinline__ double xs_at(const GasDev &g, int k, double eps) {
+  const int n = g.n;
+  if (!(eps > g.e_min)) return g.xs[k * n];
+  if (eps >= g.e_max) return g.xs[k * n + n - 1];
+  const double p = (double)(n - 1) * (log(eps / g.e_min) / log(g.e_max / g.e_min));
+  int i = (int)floor(p);
+  if (i >= n - 1) i = n - 2;
+  const double fr = p - (double)i;
+  return g.xs[k * n + i] * (1.0 - fr) + g.xs[k * n + i + 1] * fr;
+}
+
+// N max_b max(sigma_tot,b, sigma_tot,b+1) v(E_b+1): exact bound on each bin.
+__global__ __launch_bounds__(256) void k_nu_max(GasDev g, double *out) {
+  __shared__ double s[256];
+  double best = 0.0;
+  for (int b = threadIdx.x; b + 1 < g.n; b += 256) {
+    const double E1 = g.e_min * pow(g.e_max / g.e_min, (double)(b + 1) / (double)(g.n - 1));
+    double s0 = 0, s1 = 0;
+    for (int k = 0; k < 5; ++k) {
+      s0 += g.xs[k * g.n + b];
+      s1 += g.xs[k * g.n + b + 1];
+    }
+    const double v1 = sqrt(2.0 * E1 * kQe / kMe);
+    best = fmax(best, g.density * (s0 > s1 ? s0 : s1) * v1);
+  }
+  s[threadIdx.x] = best;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s[0];
+}
+
+// First crossing of the chord p0 -> p1 with a cell (Moller-Trumbore, 1997),
+// smallest parameter t in (0, 1], ties to the lower cell index; the uniform
+// grid restricts the candidates to cells whose bounding boxes overlap the
+// chord's.
+__device__ __forceinline__ void mt_test(const GridDev &G, int k, d3 o, d3 dir, double &bt, int &best) {
+  const int N = G.N;
+  const double *f = G.f;
+  const d3 a = mk3(f[(size_t)MF_AX * N + k], f[(size_t)MF_AY * N + k], f[(size_t)MF_AZ * N + k]);
+  const d3 e1 = mk3(f[(size_t)MF_BX * N + k], f[(size_t)MF_BY * N + k], f[(size_t)MF_BZ * N + k]) - a;
+  const d3 e2 = mk3(f[(size_t)MF_CX * N + k], f[(size_t)MF_CY * N + k], f[(size_t)MF_CZ * N + k]) - a;
+  const d3 pv = cross3(dir, e2);
+  const double det = dot3(e1, pv);
+  if (det == 0.0) return;
+  const double inv = 1.0 / det;
+  const d3 tv = o - a;
+  const double u = dot3(tv, pv) * inv;
+  if (u < 0.0 || u > 1.0) return;
+  const d3 qv = cross3(tv, e1);
+  const double v = dot3(dir, qv) * inv;
+  if (v < 0.0 || u + v > 1.0) return;
+  const double t = dot3(e2, qv) * inv;
+  if (t > 0.0 && t <= 1.0 && (t < bt || (t == bt && k < best))) {
+    bt = t;
+    best = k;
+  }
+}
+
+__device__ int first_hit(const GridDev &G, const double *p0, const double *p1) {
+  if (G.N == 0) return -1;
+  const d3 o = mk3(p0[0], p0[1], p0[2]);
+  const d3 dir = mk3(p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]);
+  double bt = 2.0;
+  int best = -1;
+  int lo[3], hi[3];
+  const int nn[3] = {G.nx, G.ny, G.nz};
+  for (int c = 0; c < 3; ++c) {
+    const double a = fmin(p0[c], p1[c]), b = fmax(p0[c], p1[c]);
+    const double ta = floor((a - G.lo[c]) / G.h[c]), tb = floor((b - G.lo[c]) / G.h[c]);
+    if (tb < 0.0 || ta >= (double)nn[c]) return -1;  // chord outside every cell's box
+    lo[c] = (int)fmax(ta, 0.0);
+    hi[c] = (int)fmin(tb, (double)(nn[c] - 1));
+  }
+  const long long span = (long long)(hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1);
+  if (span > 4096) {  // very long chord: test every cell
+    for (int k = 0; k < G.N; ++k) mt_test(G, k, o, dir, bt, best);
+    return best;
+  }
+  for (int iz = lo[2]; iz <= hi[2]; ++iz)
+    for (int iy = lo[1]; iy <= hi[1]; ++iy)
+      for (int ix = lo[0]; ix <= hi[0]; ++ix) {
+        const int cell = (iz * G.ny + iy) * G.nx + ix;
+        for (int q = G.start[cell]; q < G.start[cell + 1]; ++q) mt_test(G, G.items[q], o, dir, bt, best);
+      }
+  return best;
+}
+
+__device__ __forceinline__ void iso_dir(double u2, double u3, double *d) {
+  const double ct = 1.0 - 2.0 * u2, st = sqrt(fmax(0.0, 1.0 - ct * ct)), ph = 2.0 * kPi * u3;
+  d[0] = st * cos(ph);
+  d[1] = st * sin(ph);
+  d[2] = ct;
+}
+
+enum { C_EL = 0, C_NULL = 5, C_ION = 6, C_OVF = 7, C_CAP = 8, C_DROP = 9, C_ABS = 10, C_LEFT = 11, C_DD = 12, NCNT = 13 };
+
+// Constant-field flights with null-collision Monte Carlo for one particle per
+// thread.  Outputs status (0 alive, 1 absorbed, 2 left the world box), the
+// hit cell, child pairs (electron, cation) in per-particle slots.
+__global__ __launch_bounds__(256) void k_push_mc(int n, double *X0, double *X1, double *X2, double *V0, double *V1,
+                                                 double *V2, int8_t *species, const int64_t *__restrict__ id,
+                                                 const double *__restrict__ E0, const double *__restrict__ E1,
+                                                 const double *__restrict__ E2, const uint8_t *__restrict__ dead,
+                                                 GasDev g, StepDev p, GridDev G, int8_t *status, int32_t *hit,
+                                                 int32_t *n_child, double *child, int64_t *dd_counts,
+                                                 unsigned long long *counters) {
+  __shared__ unsigned long long sc[NCNT];
+  if (threadIdx.x < NCNT) sc[threadIdx.x] = 0;
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  int cnt[NCNT];
+#pragma unroll
+  for (int k = 0; k < NCNT; ++k) cnt[k] = 0;
+  if (i < n) {
+    status[i] = 0;
+    hit[i] = -1;
+    n_child[i] = 0;
+  }
+  if (i < n && !dead[i]) {
+    double X[3] = {X0[i], X1[i], X2[i]};
+    double Vv[3] = {V0[i], V1[i], V2[i]};
+    const double Ef[3] = {E0[i], E1[i], E2[i]};
+    int sp = species[i];
+    double t = 0.0;
+    bool ballistic = false;
+    const uint64_t pid = (uint64_t)id[i];
+    const uint2 key = make_uint2(p.key0, p.key1);
+    const double e_therm = 1.5 * kKb * g.temperature;
+    int nc = 0;
+    int st = 0, hcell = -1;
+    for (int k = 0;; ++k) {
+      const double m = (sp == 0) ? kMe : (sp == 1 ? g.m_cation : g.m_anion);
+      const double q = (sp == 1) ? kQe : -kQe;
+      const double acc[3] = {q * Ef[0] / m, q * Ef[1] / m, q * Ef[2] / m};
+      const double numax = (sp == 0) ? g.nu_e : g.nu_i;
+      double tau;
+      uint4 w = make_uint4(0, 0, 0, 0);
+      bool last = false;
+      if (ballistic || k >= p.max_coll || numax <= 0.0) {
+        if (!ballistic && numax > 0.0 && k >= p.max_coll) cnt[C_CAP] += 1;
+        tau = p.dt - t;
+        last = true;
+      } else {
+        w = philox10(make_uint4((uint32_t)pid, (uint32_t)(pid >> 32), p.step, 2u * (uint32_t)k), key);
+        tau = -log(u01(w.x)) / numax;
+        if (t + tau >= p.dt) {
+          tau = p.dt - t;
+          last = true;
+        }
+      }
+      double Xn[3], Vn[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        Xn[d] = X[d] + Vv[d] * tau + 0.5 * acc[d] * tau * tau;
+        Vn[d] = Vv[d] + acc[d] * tau;
+      }
+      const int h = first_hit(G, X, Xn);
+      if (h >= 0) {
+        st = 1;
+        hcell = h;
+        break;
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        X[d] = Xn[d];
+        Vv[d] = Vn[d];
+      }
+      if (X[0] < p.lo[0] || X[0] > p.hi[0] || X[1] < p.lo[1] || X[1] > p.hi[1] || X[2] < p.lo[2] || X[2] > p.hi[2]) {
+        st = 2;
+        break;
+      }
+      if (last) break;
+      t += tau;
+      const double v2 = Vv[0] * Vv[0] + Vv[1] * Vv[1] + Vv[2] * Vv[2];
+      const double vm = sqrt(v2);
+      const double u1 = u01(w.y), u2 = u01(w.z), u3 = u01(w.w);
+      if (sp == 0) {
+        const double eps = 0.5 * kMe * v2 / kQe;
+        double nuk[5], tot = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < 5; ++kk) {
+          nuk[kk] = g.density * xs_at(g, kk, eps) * vm;
+          tot += nuk[kk];
+        }
+        double lim = numax;
+        if (tot > numax) {
+          cnt[C_OVF] += 1;
+          lim = tot;
+        }
+        const double sel = u1 * lim;
+        double cum = 0.0;
+        int proc = -1;
+#pragma unroll
+        for (int kk = 0; kk < 5; ++kk) {
+          cum += nuk[kk];
+          if (proc < 0 && sel < cum) proc = kk;
+        }
+        if (proc < 0) {
+          cnt[C_NULL] += 1;
+          continue;
+        }
+        cnt[C_EL + proc] += 1;
+        double dir[3];
+        if (proc == 0) {
+          iso_dir(u2, u3, dir);
+          const double ct = (vm > 0.0) ? (dir[0] * Vv[0] + dir[1] * Vv[1] + dir[2] * Vv[2]) / vm : 1.0;
+          const double e2 = eps * (1.0 - 2.0 * kMe / g.m_gas * (1.0 - ct));
+          const double s = sqrt(2.0 * e2 * kQe / kMe);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) Vv[d] = s * dir[d];
+        } else if (proc <= 3) {
+          const double e_res = (proc == 3) ? eps - g.thr[3] - e_therm / kQe : -1.0;
+          if (proc != 3 || e_res <= 0.0) {
+            double e2 = eps - g.thr[proc];
+            if (e2 < 0.0) e2 = 0.0;
+            iso_dir(u2, u3, dir);
+            const double s = sqrt(2.0 * e2 * kQe / kMe);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Vv[d] = s * dir[d];
+          } else {  // ionisation, eq. (distIoni)
+            const uint4 w2 =
+                philox10(make_uint4((uint32_t)pid, (uint32_t)(pid >> 32), p.step, 2u * (uint32_t)k + 1u), key);
+            double uh[3], ud[3];
+            iso_dir(u01(w2.x), u01(w2.y), uh);
+            iso_dir(u01(w2.z), u01(w2.w), ud);
+            const double eres_j = e_res * kQe;
+            // energy in eV (volts): r = k_e e / (2 E_res[eV]) = k_e e^2 / (2 E_res[J])
+            const double r = kKe * kQe * kQe / (2.0 * eres_j);
+            const double s = sqrt(2.0 * (0.5 * eres_j) / kMe);
+            const double si = sqrt(2.0 * e_therm / g.m_cation);
+            if (nc < p.max_ion) {
+              double *ce = child + (((size_t)i * p.max_ion + nc) * 2 + 0) * 6;
+              double *ci = child + (((size_t)i * p.max_ion + nc) * 2 + 1) * 6;
+#pragma unroll
+              for (int d = 0; d < 3; ++d) {
+                ce[d] = X[d] - r * uh[d];
+                ce[3 + d] = -s * uh[d];
+                ci[d] = X[d];
+                ci[3 + d] = si * ud[d];
+              }
+              ++nc;
+            } else {
+              cnt[C_DROP] += 2;
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              X[d] += r * uh[d];
+              Vv[d] = s * uh[d];
+            }
+          }
+        } else {  // attachment: anion, momentum conserved with the gas at rest
+          sp = 2;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) Vv[d] *= kMe / g.m_anion;
+          ballistic = true;
+        }
+      } else {
+        const double nui = g.density * g.ion_iso * vm, nub = g.density * g.ion_back * vm;
+        double lim = numax;
+        if (nui + nub > numax) {
+          cnt[C_OVF] += 1;
+          lim = nui + nub;
+        }
+        const double sel = u1 * lim;
+        if (sel < nui) {  // isotropic in the centre of mass, gas at rest
+          const double mion = (sp == 1) ? g.m_cation : g.m_anion;
+          const double fm = mion / (mion + g.m_gas), fM = g.m_gas / (mion + g.m_gas);
+          double dir[3];
+          iso_dir(u2, u3, dir);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) Vv[d] = fm * Vv[d] + fM * vm * dir[d];
+          cnt[C_ION] += 1;
+        } else if (sel < nui + nub) {  // backscatter: thermal velocity of the gas
+          const uint4 w2 =
+              philox10(make_uint4((uint32_t)pid, (uint32_t)(pid >> 32), p.step, 2u * (uint32_t)k + 1u), key);
+          const double sd = sqrt(kKb * g.temperature / g.m_gas);
+          const double r1 = sqrt(-2.0 * log(u01(w2.x))), r2 = sqrt(-2.0 * log(u01(w2.z)));
+          Vv[0] = sd * r1 * cos(2.0 * kPi * u01(w2.y));
+          Vv[1] = sd * r1 * sin(2.0 * kPi * u01(w2.y));
+          Vv[2] = sd * r2 * cos(2.0 * kPi * u01(w2.w));
+          cnt[C_ION] += 1;
+        } else {
+          cnt[C_NULL] += 1;
+        }
+      }
+    }
+    X0[i] = X[0];
+    X1[i] = X[1];
+    X2[i] = X[2];
+    V0[i] = Vv[0];
+    V1[i] = Vv[1];
+    V2[i] = Vv[2];
+    species[i] = (int8_t)sp;
+    status[i] = (int8_t)st;
+    hit[i] = hcell;
+    n_child[i] = nc;
+    if (st == 1) {
+      cnt[C_ABS] += 1;
+      if (G.kind[hcell] == 1) {
+        atomicAdd((unsigned long long *)&dd_counts[hcell], (unsigned long long)(long long)(sp == 1 ? 1 : -1));
+        cnt[C_DD] += 1;
+      }
+    } else if (st == 2) {
+      cnt[C_LEFT] += 1;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NCNT; ++k)
+    if (cnt[k]) atomicAdd(&sc[k], (unsigned long long)cnt[k]);
+  __syncthreads();
+  if (threadIdx.x < NCNT && sc[threadIdx.x]) atomicAdd(&counters[threadIdx.x], sc[threadIdx.x]);
+}
+
+// ---------------------------------------------------------------------------
+// Small helper kernels
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_build_rhs(int N, const double *__restrict__ rhs0, const int64_t *__restrict__ cnt,
+                                                   const int8_t *__restrict__ kind, const double *__restrict__ f,
+                                                   double *rhs) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  double r = rhs0[i];
+  if (kind[i] == 1 && cnt) r += kQe * (double)cnt[i] / f[(size_t)MF_AREA * N + i];  // eq. (charge-up)
+  rhs[i] = r;
+}
+
+__global__ __launch_bounds__(256) void k_charges(int n, const int8_t *__restrict__ sp, double *q) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) q[i] = (sp[i] == 1) ? kQe : -kQe;
+}
+
+__global__ __launch_bounds__(256) void k_scatter_nn(int n, const int32_t *__restrict__ perm,
+                                                    const int32_t *__restrict__ nn_s, int32_t *nn) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) nn[perm[i]] = nn_s[i];
+}
+
+__global__ __launch_bounds__(256) void k_fill_u64(int n, unsigned long long *p, unsigned long long v) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u8(int n, uint8_t *p) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// Recombination (section 3.4.3): each electron proposes to its nearest cation
+// within r_rec; each cation accepts the nearest proposer, ties to the lower
+// id.  key1 = bits of the FP64 squared distance (ordered like the values),
+// key2 = proposer id among those at the minimum distance.
+__device__ __forceinline__ bool proposal(int i, const int8_t *sp, const int32_t *nn, const double *X0,
+                                         const double *X1, const double *X2, double r2, double *d2) {
+  if (sp[i] != 0 || nn[i] < 0) return false;
+  const int c = nn[i];
+  const double dx = X0[i] - X0[c], dy = X1[i] - X1[c], dz = X2[i] - X2[c];
+  *d2 = dx * dx + dy * dy + dz * dz;
+  return *d2 <= r2;
+}
+
+__global__ __launch_bounds__(256) void k_recomb_a(int n, const int8_t *sp, const int32_t *nn, const double *X0,
+                                                  const double *X1, const double *X2, double r2,
+                                                  unsigned long long *key1) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double d2;
+  if (i < n && proposal(i, sp, nn, X0, X1, X2, r2, &d2))
+    atomicMin(&key1[nn[i]], (unsigned long long)__double_as_longlong(d2));
+}
+
+__global__ __launch_bounds__(256) void k_recomb_b(int n, const int8_t *sp, const int32_t *nn, const double *X0,
+                                                  const double *X1, const double *X2, double r2, const int64_t *id,
+                                                  const unsigned long long *key1, unsigned long long *key2) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double d2;
+  if (i < n && proposal(i, sp, nn, X0, X1, X2, r2, &d2) &&
+      key1[nn[i]] == (unsigned long long)__double_as_longlong(d2))
+    atomicMin(&key2[nn[i]], (unsigned long long)id[i]);
+}
+
+__global__ __launch_bounds__(256) void k_recomb_c(int n, const int8_t *sp, const int32_t *nn, const double *X0,
+                                                  const double *X1, const double *X2, double r2, const int64_t *id,
+                                                  const unsigned long long *key2, uint8_t *dead) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double d2;
+  if (i < n && proposal(i, sp, nn, X0, X1, X2, r2, &d2) && key2[nn[i]] == (unsigned long long)id[i]) {
+    dead[i] = 1;
+    dead[nn[i]] = 1;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_keep(int n, const uint8_t *dead, const int8_t *status, const int32_t *n_child,
+                                              int32_t *keep, int32_t *kids) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  keep[i] = (!dead[i] && status[i] == 0) ? 1 : 0;
+  kids[i] = 2 * n_child[i];
+}
+
+struct SoA {
+  double *c[6];
+  int8_t *sp;
+  int64_t *id;
+};
+
+__global__ __launch_bounds__(256) void k_compact(int n, SoA in, const int32_t *keep, const int32_t *kpos,
+                                                 const int32_t *kids, const int32_t *cpos, const double *child,
+                                                 int max_ion, int n_surv, int take, int64_t next_id, SoA out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  if (keep[i]) {
+    const int o = kpos[i];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) out.c[c][o] = in.c[c][i];
+    out.sp[o] = in.sp[i];
+    out.id[o] = in.id[i];
+  }
+  for (int c = 0; c < kids[i]; ++c) {
+    const int k = cpos[i] + c;
+    if (k >= take) break;
+    const double *rec = child + (((size_t)i * max_ion + c / 2) * 2 + (c & 1)) * 6;
+    const int o = n_surv + k;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) out.c[d][o] = rec[d];
+    out.sp[o] = (c & 1) ? 1 : 0;
+    out.id[o] = next_id + k;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Absorption grid (built once per mesh on the host from the cell bounding
+// boxes: a CSR list of cells per grid box).
+// ---------------------------------------------------------------------------
+static obem_status build_grid(obem_ctx *ctx, obem_meshh *m) {
+  if (m->grid_start) return OBEM_OK;
+  const int64_t N = m->n;
+  std::vector<double> v((size_t)N * 9), diam((size_t)N);
+  OBEM_HIP(ctx, hipMemcpyAsync(v.data(), m->f, sizeof(double) * 9 * N, hipMemcpyDeviceToHost, ctx->stream));
+  OBEM_HIP(ctx, hipMemcpyAsync(diam.data(), m->field(MF_DIAM), sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+  OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  std::vector<double> ds = diam;
+  std::nth_element(ds.begin(), ds.begin() + N / 2, ds.end());
+  const double med = ds[N / 2];
+  double ext[3], vol = 1.0;
+  for (int c = 0; c < 3; ++c) {
+    ext[c] = std::max(m->bbox_hi[c] - m->bbox_lo[c], 1e-3 * med);
+    vol *= ext[c];
+  }
+  const double hmin = std::cbrt(vol / (double)(1 << 21));
+  const double h = std::max(med, hmin) * (1.0 + 1e-12);
+  int nn[3];
+  for (int c = 0; c < 3; ++c) {
+    nn[c] = std::max(1, (int)std::ceil(ext[c] / h));
+    m->grid_n[c] = nn[c];
+    m->grid_h[c] = ext[c] / nn[c] * (1.0 + 1e-12);
+    m->grid_lo[c] = m->bbox_lo[c] - 1e-9 * m->grid_h[c];
+  }
+  const size_t ncell = (size_t)nn[0] * nn[1] * nn[2];
+  std::vector<int32_t> count(ncell + 1, 0);
+  auto range = [&](int64_t k, int lo[3], int hi[3]) {
+    for (int c = 0; c < 3; ++c) {
+      double a = INFINITY, b = -INFINITY;
+      for (int vtx = 0; vtx < 3; ++vtx) {
+        const double x = v[(size_t)(3 * vtx + c) * N + k];
+        a = std::min(a, x);
+        b = std::max(b, x);
+      }
+      lo[c] = std::max(0, std::min(nn[c] - 1, (int)std::floor((a - m->grid_lo[c]) / m->grid_h[c])));
+      hi[c] = std::max(0, std::min(nn[c] - 1, (int)std::floor((b - m->grid_lo[c]) / m->grid_h[c])));
+    }
+  };
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<int32_t> fillp;
+    if (pass == 1) {
+      for (size_t c = 0; c < ncell; ++c) count[c + 1] += count[c];
+      fillp.assign(count.begin(), count.end() - 1);
+    }
+    std::vector<int32_t> items(pass == 1 ? count[ncell] : 0);
+    for (int64_t k = 0; k < N; ++k) {
+      int lo[3], hi[3];
+      range(k, lo, hi);
+      for (int z = lo[2]; z <= hi[2]; ++z)
+        for (int y = lo[1]; y <= hi[1]; ++y)
+          for (int x = lo[0]; x <= hi[0]; ++x) {
+            const size_t cell = ((size_t)z * nn[1] + y) * nn[0] + x;
+            if (pass == 0)
+              count[cell + 1]++;
+            else
+              items[fillp[cell]++] = (int32_t)k;
+          }
+    }
+    if (pass == 1) {
+      if (hipMalloc(&m->grid_start, sizeof(int32_t) * (ncell + 1)) != hipSuccess ||
+          hipMalloc(&m->grid_items, sizeof(int32_t) * std::max<size_t>(1, items.size())) != hipSuccess) {
+        hipGetLastError();
+        return fail(ctx, OBEM_ENOMEM, "absorption grid allocation failed");
+      }
+      OBEM_HIP(ctx, hipMemcpy(m->grid_start, count.data(), sizeof(int32_t) * (ncell + 1), hipMemcpyHostToDevice));
+      if (!items.empty())
+        OBEM_HIP(ctx, hipMemcpy(m->grid_items, items.data(), sizeof(int32_t) * items.size(), hipMemcpyHostToDevice));
+    }
+  }
+  return OBEM_OK;
+}
+
+static inline int nbt(int64_t n) { return (int)((n + 255) / 256); }
+
+}  // namespace obem
+
+using namespace obem;
+
+extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particles *S, const obem_gas *gas,
+                                  const obem_step_params *p, int64_t *dd_counts, double *sigma,
+                                  obem_step_stats *stats) {
+  if (!ctx) return OBEM_EINVAL;
+  if (ctx->sticky) return OBEM_ESTATE;
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    hipGetLastError();
+    return fail(ctx, OBEM_EDEVICE, "hipSetDevice failed");
+  }
+  if (!S || !gas || !p) return fail(ctx, OBEM_EINVAL, "state / gas / params is NULL");
+  if (S->capacity <= 0 || S->capacity >= ((int64_t)1 << 31) || S->n_live < 0 || S->n_live > S->capacity)
+    return fail(ctx, OBEM_EINVAL, "bad capacity / n_live");
+  if (!(p->dt > 0.0) || p->max_coll < 0 || p->max_ion_per_step < 0 || p->max_ion_per_step > 64 ||
+      !(p->soft >= 0.0) || !(p->r_rec >= 0.0) || !(p->ion_v_cap >= 0.0))
+    return fail(ctx, OBEM_EINVAL, "bad step parameters");
+  if (p->precision != OBEM_FP64 && p->precision != OBEM_MIXED) return fail(ctx, OBEM_EINVAL, "bad precision");
+  if (gas->n_nodes < 2 || !(gas->e_max > gas->e_min) || !(gas->e_min > 0.0) || !is_device_ptr(gas->xs))
+    return fail(ctx, OBEM_EINVAL, "bad gas tables");
+  void *arrs[] = {S->x, S->y, S->z, S->vx, S->vy, S->vz, S->species, S->id};
+  for (void *a : arrs)
+    if (!is_device_ptr(a)) return fail(ctx, OBEM_EINVAL, "particle arrays must be device memory");
+  if (mesh) {
+    if (!is_device_ptr(sigma)) return fail(ctx, OBEM_EINVAL, "sigma must be device memory");
+    if (mesh->n_dd && !is_device_ptr(dd_counts)) return fail(ctx, OBEM_EINVAL, "dd_counts must be device memory");
+    if (p->resolve && !is_device_ptr(p->rhs0)) return fail(ctx, OBEM_EINVAL, "rhs0 must be device memory");
+  }
+  obem_status st;
+  const int n = (int)S->n_live;
+  obem_step_stats out = {};
+  // 1. charging-up right-hand side and re-solve
+  if (mesh && p->resolve) {
+    const int N = (int)mesh->n;
+    double *rhs = (double *)ws_get(ctx, WS_MISC6, sizeof(double) * N);
+    if (!rhs) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+    hipLaunchKernelGGL(k_build_rhs, dim3(nbt(N)), dim3(256), 0, ctx->stream, N, p->rhs0,
+                       mesh->n_dd ? dd_counts : nullptr, mesh->kind, mesh->f, rhs);
+    OBEM_HIP(ctx, hipGetLastError());
+    st = bem_solve(ctx, mesh, rhs, sigma, 2, nullptr);
+    if (st) return st;
+  }
+  if (mesh) {
+    st = build_grid(ctx, mesh);
+    if (st) return st;
+  }
+  if (n == 0) {
+    if (stats) *stats = out;
+    return OBEM_OK;
+  }
+  // scratch
+  const int mi = p->max_ion_per_step;
+  const size_t nz = (size_t)n;
+  double *q = (double *)ws_get(ctx, WS_MISC4, sizeof(double) * nz);
+  double *E = (double *)ws_get(ctx, WS_MISC5, sizeof(double) * 3 * nz);
+  int32_t *nn_s = (int32_t *)ws_get(ctx, WS_MISC0, sizeof(int32_t) * nz);
+  double *nnd = (double *)ws_get(ctx, WS_MISC3, sizeof(double) * nz);
+  int32_t *nn = (int32_t *)ws_get(ctx, WS_MISC1, sizeof(int32_t) * nz * 4 + 64);
+  if (!q || !E || !nn_s || !nnd || !nn) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  int32_t *keep = nn + nz, *kids = nn + 2 * nz, *hitv = nn + 3 * nz;
+  // 2. field at every particle (cells + all other particles) and nearest partner
+  hipLaunchKernelGGL(k_charges, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->species, q);
+  TargetOrder to;
+  st = order_targets(ctx, n, S->x, S->y, S->z, &to);
+  if (st) return st;
+  double *acc = (double *)ws_get(ctx, WS_ACC, sizeof(double) * 4 * nz);
+  if (!acc) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  st = mesh ? launch_panel_field(ctx, mesh, sigma, to, p->precision, false, acc) : launch_fill(ctx, acc, 4 * nz, 0.0);
+  if (st) return st;
+  st = launch_pair_field(ctx, n, S->x, S->y, S->z, q, to, p->soft, p->precision, true, false, S->species, acc, nn_s,
+                         nnd);
+  if (st) return st;
+  st = launch_scatter(ctx, to, acc, kKe, E, E + nz, E + 2 * nz, nullptr);
+  if (st) return st;
+  hipLaunchKernelGGL(k_scatter_nn, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, to.perm, nn_s, nn);
+  // 3. recombination
+  unsigned long long *key = (unsigned long long *)ws_get(ctx, WS_MISC2, sizeof(unsigned long long) * 2 * nz);
+  uint8_t *dead = (uint8_t *)ws_get(ctx, WS_MISC6, nz + 64);
+  if (!key || !dead) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  hipLaunchKernelGGL(k_fill_u64, dim3(nbt(2 * n)), dim3(256), 0, ctx->stream, 2 * n, key, ~0ull);
+  hipLaunchKernelGGL(k_fill_u8, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, dead);
+  const double r2 = p->r_rec * p->r_rec;
+  hipLaunchKernelGGL(k_recomb_a, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->species, nn, S->x, S->y, S->z, r2, key);
+  hipLaunchKernelGGL(k_recomb_b, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->species, nn, S->x, S->y, S->z, r2,
+                     S->id, key, key + nz);
+  hipLaunchKernelGGL(k_recomb_c, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->species, nn, S->x, S->y, S->z, r2,
+                     S->id, key + nz, dead);
+  OBEM_HIP(ctx, hipGetLastError());
+  // 4. push + null-collision MC + absorption
+  GasDev g;
+  g.n = gas->n_nodes;
+  g.e_min = gas->e_min;
+  g.e_max = gas->e_max;
+  g.xs = gas->xs;
+  for (int k = 0; k < 5; ++k) g.thr[k] = gas->thr[k];
+  g.density = gas->density;
+  g.temperature = gas->temperature;
+  g.m_gas = gas->m_gas;
+  g.m_cation = gas->m_cation;
+  g.m_anion = gas->m_anion;
+  g.ion_iso = gas->ion_xs_iso;
+  g.ion_back = gas->ion_xs_back;
+  double *nu_dev = (double *)ws_get(ctx, WS_SOLVE2 + 0, 64);
+  unsigned long long *cnt_dev = (unsigned long long *)ws_get(ctx, WS_SOLVE1 + 0, 256);
+  if (!nu_dev || !cnt_dev) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  hipLaunchKernelGGL(k_nu_max, dim3(1), dim3(256), 0, ctx->stream, g, nu_dev);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, ctx->stream, NCNT, cnt_dev, 0ull);
+  OBEM_HIP(ctx, hipGetLastError());
+  OBEM_HIP(ctx, hipMemcpyAsync(&g.nu_e, nu_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  g.nu_i = gas->density * (gas->ion_xs_iso + gas->ion_xs_back) * p->ion_v_cap;
+  StepDev sd;
+  sd.dt = p->dt;
+  sd.step = p->step;
+  sd.key0 = (uint32_t)(p->seed & 0xffffffffu);
+  sd.key1 = (uint32_t)(p->seed >> 32);
+  sd.max_coll = p->max_coll;
+  sd.max_ion = mi;
+  for (int c = 0; c < 3; ++c) {
+    sd.lo[c] = p->box_lo[c];
+    sd.hi[c] = p->box_hi[c];
+  }
+  GridDev G = {};
+  if (mesh) {
+    G.nx = mesh->grid_n[0];
+    G.ny = mesh->grid_n[1];
+    G.nz = mesh->grid_n[2];
+    for (int c = 0; c < 3; ++c) {
+      G.lo[c] = mesh->grid_lo[c];
+      G.h[c] = mesh->grid_h[c];
+    }
+    G.start = mesh->grid_start;
+    G.items = mesh->grid_items;
+    G.N = (int)mesh->n;
+    G.f = mesh->f;
+    G.kind = mesh->kind;
+  }
+  int8_t *status = (int8_t *)ws_get(ctx, WS_MISC7, nz + 64);
+  double *child = (double *)ws_get(ctx, WS_PART, sizeof(double) * 12 * (size_t)std::max(mi, 1) * nz);
+  int32_t *nchild = (int32_t *)ws_get(ctx, WS_NN, sizeof(int32_t) * nz + 64);
+  if (!status || !child || !nchild) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  hipLaunchKernelGGL(k_push_mc, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->x, S->y, S->z, S->vx, S->vy, S->vz,
+                     S->species, S->id, E, E + nz, E + 2 * nz, dead, g, sd, G, status, hitv, nchild, child,
+                     dd_counts, cnt_dev);
+  OBEM_HIP(ctx, hipGetLastError());
+  // 5. compaction: survivors in id order, then children in parent order
+  hipLaunchKernelGGL(k_keep, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, dead, status, nchild, keep, kids);
+  int32_t *kpos = (int32_t *)ws_get(ctx, WS_KEYS0, sizeof(int32_t) * nz);
+  int32_t *cpos = (int32_t *)ws_get(ctx, WS_KEYS1, sizeof(int32_t) * nz);
+  if (!kpos || !cpos) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  size_t tb = 0, tb2 = 0;
+  OBEM_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb, keep, kpos, n, ctx->stream));
+  OBEM_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, tb2, kids, cpos, n, ctx->stream));
+  void *tmp = ws_get(ctx, WS_SORT_TMP, std::max(tb, tb2) + 256);
+  if (!tmp) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  OBEM_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(tmp, tb, keep, kpos, n, ctx->stream));
+  OBEM_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(tmp, tb2, kids, cpos, n, ctx->stream));
+  int32_t tail[4];
+  OBEM_HIP(ctx, hipMemcpyAsync(&tail[0], kpos + n - 1, 4, hipMemcpyDeviceToHost, ctx->stream));
+  OBEM_HIP(ctx, hipMemcpyAsync(&tail[1], keep + n - 1, 4, hipMemcpyDeviceToHost, ctx->stream));
+  OBEM_HIP(ctx, hipMemcpyAsync(&tail[2], cpos + n - 1, 4, hipMemcpyDeviceToHost, ctx->stream));
+  OBEM_HIP(ctx, hipMemcpyAsync(&tail[3], kids + n - 1, 4, hipMemcpyDeviceToHost, ctx->stream));
+  unsigned long long hc[NCNT];
+  OBEM_HIP(ctx, hipMemcpyAsync(hc, cnt_dev, sizeof(hc), hipMemcpyDeviceToHost, ctx->stream));
+  OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const int64_t n_surv = (int64_t)tail[0] + tail[1];
+  const int64_t n_new = (int64_t)tail[2] + tail[3];
+  const int64_t take = std::min<int64_t>(n_new, S->capacity - n_surv);
+  // output buffers
+  const size_t cap = (size_t)(n_surv + take);
+  double *ob = (double *)ws_get(ctx, WS_SOLVE0, sizeof(double) * 6 * std::max<size_t>(cap, 1) + 16 * cap + 64);
+  if (!ob) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  SoA in, o;
+  double *ic[6] = {S->x, S->y, S->z, S->vx, S->vy, S->vz};
+  for (int c = 0; c < 6; ++c) {
+    in.c[c] = ic[c];
+    o.c[c] = ob + (size_t)c * cap;
+  }
+  in.sp = S->species;
+  in.id = S->id;
+  o.id = (int64_t *)(ob + 6 * cap);
+  o.sp = (int8_t *)(ob + 7 * cap);
+  if (cap > 0) {
+    hipLaunchKernelGGL(k_compact, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, in, keep, kpos, kids, cpos, child, mi,
+                       (int)n_surv, (int)take, S->next_id, o);
+    OBEM_HIP(ctx, hipGetLastError());
+    for (int c = 0; c < 6; ++c)
+      OBEM_HIP(ctx, hipMemcpyAsync(ic[c], o.c[c], sizeof(double) * cap, hipMemcpyDeviceToDevice, ctx->stream));
+    OBEM_HIP(ctx, hipMemcpyAsync(S->id, o.id, sizeof(int64_t) * cap, hipMemcpyDeviceToDevice, ctx->stream));
+    OBEM_HIP(ctx, hipMemcpyAsync(S->species, o.sp, cap, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  // recombined count: n - survivors - absorbed - left (children not counted)
+  out.absorbed = (int64_t)hc[C_ABS];
+  out.left_world = (int64_t)hc[C_LEFT];
+  out.recombined = n - n_surv - out.absorbed - out.left_world;
+  out.children = take;
+  out.children_dropped = (int64_t)hc[C_DROP] + (n_new - take);
+  for (int k = 0; k < 5; ++k) out.real_collisions[k] = (int64_t)hc[C_EL + k];
+  out.null_collisions = (int64_t)hc[C_NULL];
+  out.ion_collisions = (int64_t)hc[C_ION];
+  out.rate_overflow = (int64_t)hc[C_OVF];
+  out.flight_cap = (int64_t)hc[C_CAP];
+  out.dd_charge_deposited = (int64_t)hc[C_DD];
+  S->n_live = n_surv + take;
+  S->next_id += take;
+  out.n_live = S->n_live;
+  if (stats) *stats = out;
+  if (n_new > take) return fail(ctx, OBEM_ECAPACITY, "capacity %lld reached: %lld children dropped",
+                                (long long)S->capacity, (long long)(n_new - take));
+  return OBEM_OK;
 }

@@ -1,0 +1,125 @@
+"""GPU parity of track_step against the oracle's step (sections 3.3-3.4):
+in FP64 mode the random streams and every decision are the same, so the
+particle sets (ids, species), positions, velocities, charging counts and
+event counts must agree step by step; mixed mode is checked statistically."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2110_09214_amd import binding as B
+from paper_2110_09214_amd import workloads as W
+from gpu_helpers import bind, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _scenario(seed=0):
+    rng = np.random.default_rng(seed)
+    m = W.plates_with_slab_mesh(n=4, half=1e-3, gap=1e-3, t=0.4e-3)
+    ne, ni = 900, 400
+    x, q, sp = W.gaussian_clouds(ne, ni, (0, 0, 6e-4), (0, 0, 6e-4), 3e-5, rng)
+    # electron-cation pairs closer than the recombination radius
+    pe = rng.normal(size=(20, 3)) * 2e-5 + np.array([0, 0, 7e-4])
+    d = rng.normal(size=(20, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    pi = pe + d * rng.uniform(0.2e-6, 0.9e-6, size=(20, 1))
+    # electrons just above the slab moving down (absorbed on dd cells)
+    pd = np.stack([rng.uniform(-8e-4, 8e-4, 30), rng.uniform(-8e-4, 8e-4, 30), 4e-4 + rng.uniform(1e-7, 1e-6, 30)], 1)
+    x = np.concatenate([x, pe, pi, pd])
+    sp = np.concatenate([sp, np.zeros(20, np.int8), np.ones(20, np.int8), np.zeros(30, np.int8)])
+    n = len(sp)
+    k = W.E_CHARGE
+    eps = rng.uniform(1.0, 60.0, n)                          # electron energies, eV
+    v = rng.normal(size=(n, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    v *= np.where(sp == 0, np.sqrt(2 * eps * k / W.M_ELECTRON), 300.0)[:, None]
+    v[-30:] = np.array([0, 0, -2e6])
+    ids = np.arange(n, dtype=np.int64)
+    return m, dict(x=x, v=v, species=sp.astype(np.int8), id=ids, next_id=n)
+
+
+def _params(step, prec, cap=20000):
+    return dict(dt=1e-12, step=step, seed=5, max_coll=64, max_ion_per_step=4, ion_v_cap=2e4,
+                box_lo=(-1e-3, -1e-3, 0.0), box_hi=(1e-3, 1e-3, 1e-3), soft=1e-7, r_rec=1e-6, capacity=cap,
+                precision=prec, resolve=1 if step > 0 else 0)
+
+
+def test_track_step_fp64_exact_stream(ctx, orc):
+    m, st0 = _scenario()
+    gas = W.synthetic_ar_co2()
+    _, area, _, _ = orc.tri_geometry(m.a, m.b, m.c)
+    sig_o, A = orc.bem_solve(m)
+    counts_o = np.zeros(m.n, np.int64)
+    bm = bind(ctx, m)
+    rhs0 = dev(m.rhs)
+    sig_g, _ = B.bem_solve_charges(ctx, bm, rhs0)
+    parts = B.Particles(20000, "cuda", dev(st0["x"]), dev(st0["v"]), dev(st0["species"], torch.int8),
+                        dev(st0["id"], torch.int64), st0["next_id"])
+    counts_g = torch.zeros(m.n, dtype=torch.int64, device="cuda")
+    gas_s, keep = B.gas_struct(gas, "cuda")
+    state = st0
+    for s in range(3):
+        p = _params(s, B.OBEM_FP64)
+        state, sig_o, counts_o, so, _ = orc.track_step(state, m, sig_o, gas, p, counts_o, rhs0=m.rhs, area=area,
+                                                       A=A, resolve=bool(p["resolve"]))
+        sg = B.track_step(ctx, bm, parts, gas_s, p, counts_g, sig_g, rhs0)
+        g = parts.state()
+        print("step", s, "oracle", so, "gpu", sg)
+        assert parts.n_live == so["n_live"]
+        assert np.array_equal(host(g["id"]), state["id"])
+        assert np.array_equal(host(g["species"]), state["species"])
+        assert parts.next_id == state["next_id"]
+        assert np.abs(host(g["x"]) - state["x"]).max() <= 1e-10 * 1e-3
+        vs = np.abs(state["v"]).max()
+        assert np.abs(host(g["v"]) - state["v"]).max() <= 1e-8 * vs
+        assert np.array_equal(host(counts_g), counts_o)
+        for k, name in enumerate(["elastic", "exc1", "exc2", "ionisation", "attachment"]):
+            assert sg["real_collisions"][k] == so[name]
+        assert sg["null_collisions"] == so["null"]
+        assert sg["recombined"] == so["recombined"]
+        assert sg["absorbed"] == so["absorbed"]
+        assert sg["children"] == so["children"]
+    assert so["recombined"] >= 0 and counts_o.any()
+    # sigma after the last re-solve agrees
+    assert np.abs(host(sig_g) - sig_o).max() <= 1e-10 * np.abs(sig_o).max()
+
+
+def test_track_step_mixed_consistent_with_fp64(ctx):
+    m, st0 = _scenario(1)
+    gas = W.synthetic_ar_co2()
+    gas_s, keep = B.gas_struct(gas, "cuda")
+    res = {}
+    for prec in (B.OBEM_FP64, B.OBEM_MIXED):
+        bm = bind(ctx, m)
+        rhs0 = dev(m.rhs)
+        sig, _ = B.bem_solve_charges(ctx, bm, rhs0)
+        parts = B.Particles(20000, "cuda", dev(st0["x"]), dev(st0["v"]), dev(st0["species"], torch.int8),
+                            dev(st0["id"], torch.int64), st0["next_id"])
+        counts = torch.zeros(m.n, dtype=torch.int64, device="cuda")
+        tot = np.zeros(5)
+        for s in range(4):
+            sg = B.track_step(ctx, bm, parts, gas_s, _params(s, prec), counts, sig, rhs0)
+            tot += np.array(sg["real_collisions"])
+        res[prec] = (parts.n_live, tot)
+    (n64, t64), (n32, t32) = res[B.OBEM_FP64], res[B.OBEM_MIXED]
+    assert abs(n32 - n64) <= 0.02 * n64
+    assert np.all(np.abs(t32 - t64) <= 0.05 * t64 + 10)
+
+
+def test_track_step_capacity_overflow(ctx):
+    m, st0 = _scenario(2)
+    gas = W.synthetic_ar_co2()
+    gas_s, keep = B.gas_struct(gas, "cuda")
+    bm = bind(ctx, m)
+    rhs0 = dev(m.rhs)
+    sig, _ = B.bem_solve_charges(ctx, bm, rhs0)
+    n0 = len(st0["id"])
+    parts = B.Particles(n0 + 4, "cuda", dev(st0["x"]), dev(st0["v"]), dev(st0["species"], torch.int8),
+                        dev(st0["id"], torch.int64), st0["next_id"])
+    counts = torch.zeros(m.n, dtype=torch.int64, device="cuda")
+    sg = B.track_step(ctx, bm, parts, gas_s, _params(0, B.OBEM_FP64, cap=n0 + 4), counts, sig, rhs0)
+    assert sg["status"] == -6
+    assert sg["children_dropped"] > 0
+    assert parts.n_live <= n0 + 4
+    ids = host(parts.state()["id"])
+    assert np.all(np.diff(ids) > 0)

@@ -165,7 +165,8 @@ def test_elastic_recoil_loss_per_collision(orc):
 def test_ionisation_energy_and_separation(orc):
     """A 100 eV electron that ionises: parent and child electron share
     E_res = E - E_ioni - 3/2 kT equally, the cation carries 3/2 kT, the child
-    electron sits r = k_e e / (2 E_res) from the cation (eq. (distIoni))."""
+    electron sits r = k_e e / (2 E_res) from the cation (eq. (distIoni), energy
+    in eV as in the paper)."""
     k = orc.constants()
     gas = W.constant_nu_gas(1.0)
     v_nodes = np.sqrt(2 * gas.energies * k["e"] / k["m_e"])
@@ -187,7 +188,11 @@ def test_ionisation_energy_and_separation(orc):
     assert np.allclose(ke_c, eres / 2, rtol=1e-12)
     assert np.allclose(ke_i, eth, rtol=1e-12)
     r = np.linalg.norm(cx[:, 0, 0] - cx[:, 0, 1], axis=1)
-    assert np.allclose(r, k["k_e"] * k["e"] / (2 * eres), rtol=1e-12)
+    # the pair's Coulomb energy at that separation is 2 E_res
+    assert np.allclose(k["k_e"] * k["e"] ** 2 / r, 2 * eres, rtol=1e-12)
+    # with energies in eV the paper's recombination radius at 15.7 eV is 4.59e-11 m;
+    # the same expression gives the separation here
+    assert np.allclose(r, 4.59e-11 * 15.7 / (eres / k["e"]), rtol=2e-3)
     # opposite velocities of the two electrons right after the collision
     assert np.allclose(np.cross(v, cv[:, 0, 0]), 0.0, atol=1e-6 * s * s)
 
