@@ -10,7 +10,9 @@ from paper_2110_09214_amd import workloads as W
 from gpu_helpers import bind, dev, host, rel_l2, synthetic_sigma
 
 pytestmark = pytest.mark.gpu
-TOL = {B.OBEM_FP64: 1e-11, B.OBEM_MIXED: 1e-5}
+# gradients: relative L2 <= 1e-4 against the FP64 reference in mixed mode (the
+# adjoint's contract), FP64 mode limited by the FP64 rounding of 1/d^3 sums
+TOL = {B.OBEM_FP64: 1e-11, B.OBEM_MIXED: 1e-4}
 
 
 @pytest.mark.parametrize("prec", [B.OBEM_FP64, B.OBEM_MIXED])
@@ -73,10 +75,14 @@ def test_adjoint_matches_gpu_forward_fd(ctx):
         E = B.field_eval(ctx, bm, ss, xx, Q, xx, 1e-7, B.OBEM_FP64, tgt_is_src=True)
         return float((E * Wt).sum())
 
+    def L_cells(ss):
+        E = B.field_eval(ctx, bm, ss, None, None, X, 0.0, B.OBEM_FP64)
+        return float((E * Wt).sum())
+
     for k in (0, 33, 200):
         e = torch.zeros_like(S)
         e[k] = 1.0
-        assert L(X, e) == pytest.approx(gs[k], rel=1e-10)
+        assert L_cells(e) == pytest.approx(gs[k], rel=1e-10)     # L is affine in sigma
     for i, ax in ((0, 0), (77, 2), (119, 1)):
         h = 1e-6 * 5e-5
         xp, xm = X.clone(), X.clone()
