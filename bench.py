@@ -1,0 +1,262 @@
+#!/usr/bin/env python
+"""Benchmark of the space-charge field path on one MI355X (gfx950).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Primary line (one JSON object on stdout): the space-charge avalanche cloud --
+4,000,000 point charges (2M electrons, 2M cations, Gaussian clouds of sigma
+50 um) above the single-GEM cell mesh (40,776 cells).  One step is the
+per-tracking-step field re-evaluation of the dynamic option: the cell charges
+are re-solved from the right-hand side with the cached LU factors (plus
+compensated refinement), then the field at every charge is summed over all
+cells and all other charges in mixed precision.  `value` is
+(pair + charge-cell interactions) per second of that step.
+
+`extra` carries the other measurements of the same metric: the GEM cell with
+1M field points in mixed precision and in FP64 (interactions/s each, and the
+relative L2 difference between the two), and the adjoint's backward/forward
+time ratio on 1M charges with the refined (49,128-cell) mesh.
+
+`roofline` is for the dominant kernel (the pairwise sum): 20 flop per pair
+interaction (3 sub, 3 FMA for |d|^2 + s^2, 1 rsqrt, 2 mul for the cube, 1 mul
+by q, 3 FMA into E) divided by that kernel's average duration, measured with
+HIP events on the library's stream inside the timed region, against the
+published FP32 vector peak.  `cpu_baseline` times the CPU oracle on a sample
+of the same workload (its error against the GPU result is reported too).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
+FLOP_PER_PAIR = 20
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("field.hip", "cellmath.hpp", "obem_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2110_09214_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles():
+    """HBM bytes per launch of the pairwise kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "pair_mixed_cloud4M_traffic.json")
+    try:
+        with open(p) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path shards by targets across "
+              f"GPUs, which this build does not run", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2110_09214_amd import binding as B
+    from paper_2110_09214_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+
+    def dev(a, dtype=torch.float64):
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+    def bind(ctx, m):
+        return B.BoundMesh(ctx, dev(m.a), dev(m.b), dev(m.c), dev(m.kind, torch.int8), dev(m.eps1), dev(m.eps2))
+
+    ctx = B.Context(0)
+    stream = ctx.stream
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        return e0.elapsed_time(e1) / steps, prof
+
+    # ------------------------------------------------------------------ primary
+    t0 = time.time()
+    mesh = W.gem_cell_mesh()
+    x, q, sp = W.space_charge_cloud()
+    n, N = len(q), mesh.n
+    log(f"[bench] space-charge cloud: {n} charges, {N} cells (inputs {time.time() - t0:.1f}s)")
+    bm = bind(ctx, mesh)
+    rhs = dev(mesh.rhs)
+    t0 = time.time()
+    sigma, info = B.bem_solve_charges(ctx, bm, rhs, max_refine=3)
+    torch.cuda.synchronize()
+    log(f"[bench] assembly + LU + solve of {N} cells: {time.time() - t0:.1f}s, backward error {info['backward_error']:.2e}")
+    X, Q = dev(x), dev(q)
+    E = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+
+    def step():
+        B.bem_solve_charges(ctx, bm, rhs, sigma, max_refine=2, want_info=False)
+        B.field_eval(ctx, bm, sigma, X, Q, X, 1e-7, B.OBEM_MIXED, tgt_is_src=True, out=E)
+
+    log(f"[bench] timing {args.steps} steps after {args.warmup} warm-up")
+    ms, prof = timed(step, args.steps, args.warmup)
+    pairs = n * (n - 1)
+    inter = pairs + n * N
+    value = inter / (ms / 1e3)
+    pair_ms = prof["pair"][0] / prof["pair"][1]
+    achieved = FLOP_PER_PAIR * pairs / (pair_ms / 1e3) / 1e12
+    log(f"[bench] step {ms:.1f} ms, {value:.3e} interactions/s; kernels: " +
+        ", ".join(f"{k} {v[0] / max(v[1], 1):.2f}ms x{v[1]}" for k, v in prof.items()))
+    traffic = traffic_from_profiles()
+    out = {
+        "metric": "particle-source interactions/s, mixed vs FP64 at 1e-5 rel err; bwd/fwd ratio",
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "mixed-f32/f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "space-charge avalanche cloud: 4,000,000 point charges (2M electrons + 2M cations, "
+                        "Gaussian sigma 50 um) above the single-GEM cell mesh of 40,776 cells; per step the FP64 "
+                        "cell-charge re-solve (cached LU + refinement) and the mixed-precision field at every charge",
+            "n_charges": n, "n_cells": N, "softening_m": 1e-7, "precision": "mixed",
+            "interactions_per_step": inter, "pair_interactions_per_step": pairs,
+        },
+        "roofline": {
+            "kernel": "k_pair_mixed",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS,
+            "traffic": traffic,
+            "flop_per_interaction": FLOP_PER_PAIR,
+            "launch_ms": pair_ms,
+        },
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+    }
+
+    # ------------------------------------------------------------ cpu baseline
+    if not args.no_cpu_baseline:
+        import oracle
+
+        cores = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+        rng = np.random.default_rng(11)
+        it = rng.choice(n, 384, replace=False)
+        ic = it[:192]
+        sig_h = sigma.cpu().numpy()
+        t0 = time.time()
+        Ep = oracle.pair_field(x[it], x, q, 1e-7)        # own term: zero field at zero distance
+        tp = time.time() - t0
+        t0 = time.time()
+        Ec = oracle.panel_field(x[ic], mesh.a, mesh.b, mesh.c, sig_h)
+        tc = time.time() - t0
+        rate_p = len(it) * n / tp
+        rate_c = len(ic) * N / tc
+        t_full = pairs / rate_p + n * N / rate_c
+        Eg = torch.stack(E, 1).cpu().numpy()
+        # oracle total field on the targets that have both parts
+        ref = Ep[:len(ic)] + Ec
+        err = float(np.linalg.norm(Eg[ic] - ref) / np.linalg.norm(ref))
+        out["cpu_baseline"] = {
+            "value": inter / t_full, "unit": "interactions/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(it)} of the {n} charges against all {n} charges ({tp:.1f}s) and {len(ic)} against all "
+                      f"{N} cells ({tc:.1f}s); long-double brute force; per-part rates combined over the full step",
+            "gpu_vs_oracle_rel_l2_on_sample": err,
+        }
+        log(f"[bench] cpu oracle: {inter / t_full:.3e} interactions/s on {cores} cores; GPU vs oracle rel L2 {err:.2e}")
+
+    # ------------------------------------------------------------------ extras
+    if not args.no_extra:
+        extra = {}
+        # GEM cell, 1M field points: mixed vs FP64
+        pts = dev(W.gem_cell_points())
+        npts = int(pts.shape[0])
+        outs = {}
+        for name, prec in (("mixed", B.OBEM_MIXED), ("fp64", B.OBEM_FP64)):
+            res = {}
+
+            def fe(prec=prec, res=res):
+                res["E"] = B.field_eval(ctx, bm, sigma, None, None, pts, 0.0, prec)
+
+            ms_g, pr = timed(fe, 2, 1)
+            outs[name] = res["E"]
+            extra[f"gem_cell_{name}_interactions_per_s"] = npts * N / (ms_g / 1e3)
+            extra[f"gem_cell_{name}_ms"] = ms_g
+        d = (outs["mixed"] - outs["fp64"]).norm() / outs["fp64"].norm()
+        extra["gem_cell_mixed_vs_fp64_rel_l2"] = float(d)
+        extra["gem_cell_workload"] = f"{npts} field points x {N} cells, cell charges from the FP64 solve"
+        log(f"[bench] gem cell: mixed {extra['gem_cell_mixed_interactions_per_s']:.3e}/s, "
+            f"fp64 {extra['gem_cell_fp64_interactions_per_s']:.3e}/s, rel L2 {float(d):.2e}")
+        del outs, pts
+        # adjoint bwd/fwd on 1M charges + refined mesh (synthetic cell charges)
+        m4 = W.gem_cell_mesh(W.gem_cell_refined_geometry())
+        x4, q4, sp4, w4 = W.adjoint_workload()
+        bm4 = bind(ctx, m4)
+        c4 = (m4.a + m4.b + m4.c) / 3
+        s4 = dev(1e-6 * np.sin(c4 @ np.array([3e4, 2e4, 1e4])))
+        X4, Q4, W4 = dev(x4), dev(q4), dev(w4)
+
+        def fwd():
+            B.field_eval(ctx, bm4, s4, X4, Q4, X4, 1e-7, B.OBEM_MIXED, tgt_is_src=True)
+
+        def bwd():
+            B.field_eval_backward(ctx, bm4, s4, X4, Q4, X4, 1e-7, W4, B.OBEM_MIXED, tgt_is_src=True)
+
+        ms_f, _ = timed(fwd, 2, 1)
+        ms_b, pb = timed(bwd, 2, 1)
+        extra["adjoint_fwd_ms"] = ms_f
+        extra["adjoint_bwd_ms"] = ms_b
+        extra["adjoint_bwd_fwd_ratio"] = ms_b / ms_f
+        extra["adjoint_workload"] = f"{len(q4)} charges (targets = sources) + {m4.n} cells, mixed precision"
+        log(f"[bench] adjoint: fwd {ms_f:.1f} ms, bwd {ms_b:.1f} ms, ratio {ms_b / ms_f:.2f}")
+        out["extra"] = extra
+
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -93,6 +93,17 @@ const char *obem_last_error(const obem_ctx *ctx);
  * eps0, k_e = 1/(4 pi eps0), e, m_e, k_B, atomic mass unit.  No GPU work. */
 void obem_constants(double *out);
 
+/* Kernel timing.  While enabled, the main kernels of every call are bracketed
+ * with HIP events on the context stream (names: "order", "panel", "pair",
+ * "pair_reduce", "scatter", "assemble", "lu", "solve", "panel_bwd",
+ * "pair_bwd", "push_mc", "recombine", "compact").  obem_profile_read
+ * synchronises the stream, writes up to max_entries (name, total ms,
+ * launches) triples into host arrays names[max_entries][32], ms[], launches[]
+ * in first-seen order, stores the count in *n_out and clears the record. */
+obem_status obem_profile_enable(obem_ctx *ctx, int enable);
+obem_status obem_profile_read(obem_ctx *ctx, int max_entries, char *names, double *ms, int64_t *launches,
+                              int *n_out);
+
 /* Bind a mesh: copies the cell data into the handle and derives normals,
  * areas, centroids, diameters and the far-field quadrature points.  The
  * collocation matrix is assembled lazily by the first bem_solve_charges. */

@@ -68,7 +68,8 @@ class StepStats_t(C.Structure):
                 ("dd_charge_deposited", C.c_int64)]
 
 
-SYMBOLS = ["obem_create", "obem_destroy", "obem_last_error", "obem_constants", "obem_mesh_bind",
+SYMBOLS = ["obem_create", "obem_destroy", "obem_last_error", "obem_constants", "obem_profile_enable",
+           "obem_profile_read", "obem_mesh_bind",
            "obem_mesh_release", "obem_mesh_geometry", "bem_solve_charges", "field_eval", "field_eval_backward",
            "track_step"]
 
@@ -90,6 +91,8 @@ def load(path: str = LIB_PATH):
     lib.obem_last_error.restype = C.c_char_p
     lib.obem_constants.argtypes = [vp]
     lib.obem_constants.restype = None
+    lib.obem_profile_enable.argtypes = [vp, i32]
+    lib.obem_profile_read.argtypes = [vp, i32, vp, vp, vp, C.POINTER(C.c_int)]
     lib.obem_mesh_bind.argtypes = [vp, C.POINTER(Mesh_t), C.POINTER(vp)]
     lib.obem_mesh_release.argtypes = [vp, vp]
     lib.obem_mesh_geometry.argtypes = [vp, vp, vp, vp, vp, vp, vp]
@@ -145,6 +148,21 @@ class Context:
         if st != 0:
             raise ObemError(st, self.lib.obem_last_error(self.h).decode())
         return st
+
+    def profile(self, enable: bool = True):
+        """Enable or disable per-kernel event timing on this context."""
+        self.check(self.lib.obem_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{name: (total ms, launches)} since the last read (synchronises)."""
+        m = 64
+        names = C.create_string_buffer(32 * m)
+        ms = (C.c_double * m)()
+        cnt = (C.c_int64 * m)()
+        n = C.c_int()
+        self.check(self.lib.obem_profile_read(self.h, m, names, ms, cnt, C.byref(n)))
+        raw = names.raw
+        return {raw[32 * k:32 * k + 32].split(b"\0")[0].decode(): (ms[k], cnt[k]) for k in range(n.value)}
 
     def close(self):
         if getattr(self, "h", None):

@@ -648,6 +648,7 @@ extern "C" obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh
     const int N = (int)mesh->n;
     double *gsp = (double *)ws_get(ctx, WS_MISC2, sizeof(double) * (size_t)bt * N);
     if (!gsp) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed (%d x %d partials)", bt, N);
+    OBEM_PROF(ctx, "panel_bwd");
     if (precision == OBEM_MIXED)
       hipLaunchKernelGGL(k_panel_bwd_mixed, dim3(bt), dim3(kT), 0, ctx->stream, n_t, to.xs, wsrt, N, mesh->f, sigma,
                          1, gx, gsp);
@@ -669,6 +670,7 @@ extern "C" obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh
     double *part = (double *)ws_get(ctx, WS_PART, sizeof(double) * 3 * (size_t)n_t * nsplit);
     if (!part) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
     dim3 grid(bt, nsplit);
+    OBEM_PROF(ctx, "pair_bwd");
 #define BWD_T(TIS, EX)                                                                                            \
   if (tis == TIS && excl == EX) {                                                                                 \
     if (precision == OBEM_MIXED)                                                                                  \
@@ -704,6 +706,7 @@ extern "C" obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh
     double *acc = (double *)ws_get(ctx, WS_MISC4, sizeof(double) * 3 * (size_t)n_s);
     if (!part || !acc) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
     dim3 grid(bs, nsplit);
+    OBEM_PROF(ctx, "pair_bwd");
     if (precision == OBEM_MIXED) {
       if (excl)
         hipLaunchKernelGGL((k_pair_bwd_s<1, true>), grid, dim3(kT), 0, ctx->stream, n_s, sx, sy, sz, sq, n_t, to.xs,

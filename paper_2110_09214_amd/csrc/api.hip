@@ -55,6 +55,35 @@ void *ws_get(obem_ctx *ctx, int slot, size_t bytes) {
   return b.p;
 }
 
+static hipEvent_t prof_event(obem_ctx *ctx) {
+  if (!ctx->prof_pool.empty()) {
+    hipEvent_t e = ctx->prof_pool.back();
+    ctx->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+int prof_begin(obem_ctx *ctx, const char *name) {
+  if (!ctx || !ctx->prof) return -1;
+  obem_prof_rec r{name, prof_event(ctx), prof_event(ctx)};
+  if (!r.start || !r.stop) return -1;
+  hipEventRecord(r.start, ctx->stream);
+  hipEventRecord(r.stop, ctx->stream);  // overwritten by prof_end
+  ctx->prof_recs.push_back(r);
+  return (int)ctx->prof_recs.size() - 1;
+}
+
+void prof_end(obem_ctx *ctx, int idx) {
+  if (!ctx || idx < 0 || idx >= (int)ctx->prof_recs.size()) return;
+  hipEventRecord(ctx->prof_recs[idx].stop, ctx->stream);
+}
+
 bool is_device_ptr(const void *p) {
   if (!p) return false;
   hipPointerAttribute_t attr;
@@ -184,11 +213,62 @@ obem_status obem_destroy(obem_ctx *ctx) {
   if (!ctx) return OBEM_EINVAL;
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
+  for (auto &r : ctx->prof_recs) {
+    hipEventDestroy(r.start);
+    hipEventDestroy(r.stop);
+  }
+  for (auto e : ctx->prof_pool) hipEventDestroy(e);
   for (auto &b : ctx->ws)
     if (b.p) hipFree(b.p);
   solver_release(ctx);
   hipGetLastError();
   delete ctx;
+  return OBEM_OK;
+}
+
+obem_status obem_profile_enable(obem_ctx *ctx, int enable) {
+  if (!ctx) return OBEM_EINVAL;
+  ctx->prof = enable != 0;
+  return OBEM_OK;
+}
+
+obem_status obem_profile_read(obem_ctx *ctx, int max_entries, char *names, double *ms, int64_t *launches,
+                              int *n_out) {
+  if (!ctx || !n_out || max_entries < 0 || (max_entries > 0 && (!names || !ms || !launches))) return OBEM_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    hipGetLastError();
+    return fail(ctx, OBEM_EDEVICE, "synchronisation failed while reading the profile");
+  }
+  std::vector<std::string> keys;
+  std::vector<double> tot;
+  std::vector<int64_t> cnt;
+  for (auto &r : ctx->prof_recs) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.start, r.stop) != hipSuccess) {
+      hipGetLastError();
+      t = 0.f;
+    }
+    size_t k = 0;
+    while (k < keys.size() && keys[k] != r.name) ++k;
+    if (k == keys.size()) {
+      keys.push_back(r.name);
+      tot.push_back(0.0);
+      cnt.push_back(0);
+    }
+    tot[k] += t;
+    cnt[k] += 1;
+    ctx->prof_pool.push_back(r.start);
+    ctx->prof_pool.push_back(r.stop);
+  }
+  ctx->prof_recs.clear();
+  const int n = (int)std::min<size_t>(keys.size(), (size_t)max_entries);
+  for (int k = 0; k < n; ++k) {
+    std::strncpy(names + 32 * k, keys[k].c_str(), 31);
+    names[32 * k + 31] = 0;
+    ms[k] = tot[k];
+    launches[k] = cnt[k];
+  }
+  *n_out = n;
   return OBEM_OK;
 }
 

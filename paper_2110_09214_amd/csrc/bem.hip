@@ -258,7 +258,10 @@ obem_status bem_factor(obem_ctx *ctx, obem_meshh *m) {
     }
   }
   const int gy = std::min(N, 65535);
-  hipLaunchKernelGGL(k_bem_assemble, dim3(nb(N), gy), dim3(256), 0, ctx->stream, N, m->f, m->kind, m->A);
+  {
+    OBEM_PROF(ctx, "assemble");
+    hipLaunchKernelGGL(k_bem_assemble, dim3(nb(N), gy), dim3(256), 0, ctx->stream, N, m->f, m->kind, m->A);
+  }
   OBEM_HIP(ctx, hipGetLastError());
   // infinity norm of A (for the backward error)
   {
@@ -278,8 +281,11 @@ obem_status bem_factor(obem_ctx *ctx, obem_meshh *m) {
   rocblas_handle h;
   obem_status st = handle(ctx, &h);
   if (st) return st;
-  if (rocsolver_dgetrf(h, N, N, m->LU, N, m->ipiv, m->info) != rocblas_status_success)
-    return fail(ctx, OBEM_EDEVICE, "rocsolver_dgetrf failed");
+  {
+    OBEM_PROF(ctx, "lu");
+    if (rocsolver_dgetrf(h, N, N, m->LU, N, m->ipiv, m->info) != rocblas_status_success)
+      return fail(ctx, OBEM_EDEVICE, "rocsolver_dgetrf failed");
+  }
   int32_t info = 0;
   double *dm = (double *)ws_get(ctx, WS_MISC5, 2 * sizeof(double));
   if (!dm) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
@@ -313,6 +319,7 @@ obem_status bem_solve(obem_ctx *ctx, obem_meshh *m, const double *rhs, double *s
                       obem_solve_info *info) {
   obem_status st = bem_factor(ctx, m);
   if (st) return st;
+  OBEM_PROF(ctx, "solve");
   const int N = (int)m->n;
   double *w = (double *)ws_get(ctx, WS_SOLVE0, sizeof(double) * (size_t)(3 * N + 8));
   if (!w) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");

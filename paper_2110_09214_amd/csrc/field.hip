@@ -127,6 +127,7 @@ obem_status order_targets(obem_ctx *ctx, int64_t n64, const double *tx, const do
   int n = (int)n64;
   out->n = n;
   if (n == 0) return OBEM_OK;
+  OBEM_PROF(ctx, "order");
   const int nb = 256;
   double *bbox = (double *)ws_get(ctx, WS_BBOX, sizeof(double) * (6 * nb + 6));
   uint32_t *k0 = (uint32_t *)ws_get(ctx, WS_KEYS0, sizeof(uint32_t) * n);
@@ -345,6 +346,7 @@ obem_status launch_panel_field(obem_ctx *ctx, const obem_meshh *m, const double 
   if (n_t == 0) return OBEM_OK;
   const int N = (int)m->n;
   dim3 grid(nblk(n_t)), block(kThreads);
+  OBEM_PROF(ctx, "panel");
   if (prec == OBEM_MIXED) {
     if (want_v)
       hipLaunchKernelGGL(k_panel_mixed<true>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, acc);
@@ -598,6 +600,8 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
   else if (tgt_is_src && want_v)
     excl = 2;
   dim3 grid(bt, nsplit);
+  {
+  OBEM_PROF(ctx, "pair");
 #define PAIR_CASE(V, N, Z)                                                                                   \
   if (want_v == V && nn == N && excl == Z)                                                                   \
     launch_pair_t<V, N, Z>(ctx, grid, n_t, to.xs, to.perm, n_s, sx, sy, sz, sq, species, soft, prec, chunk,  \
@@ -615,8 +619,10 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
   PAIR_CASE(true, true, 1)
   PAIR_CASE(true, true, 2)
 #undef PAIR_CASE
+  }
   OBEM_HIP(ctx, hipGetLastError());
   // the accumulator already holds the cell field when the panel kernel ran
+  OBEM_PROF(ctx, "pair_reduce");
   if (prec == OBEM_MIXED)
     hipLaunchKernelGGL(k_pair_reduce<float>, dim3(nblk(n_t)), dim3(256), 0, ctx->stream, n_t, nsplit, part, 1, acc,
                        (const float *)nnd, nni, nn_d2, nn_idx);
@@ -649,6 +655,7 @@ __global__ __launch_bounds__(256) void k_fill(size_t n, double *p, double v) {
 obem_status launch_scatter(obem_ctx *ctx, const TargetOrder &to, const double *acc, double scale, double *Ex,
                            double *Ey, double *Ez, double *V) {
   if (to.n == 0) return OBEM_OK;
+  OBEM_PROF(ctx, "scatter");
   hipLaunchKernelGGL(k_scatter, dim3(nblk(to.n)), dim3(256), 0, ctx->stream, to.n, to.perm, acc, scale, Ex, Ey,
                      Ez, V);
   OBEM_HIP(ctx, hipGetLastError());

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "obem.h"
 
@@ -72,6 +73,11 @@ struct obem_meshh {
   const double *field(int k) const { return f + (size_t)k * (size_t)n; }
 };
 
+struct obem_prof_rec {
+  const char *name;
+  hipEvent_t start, stop;
+};
+
 struct obem_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -79,6 +85,9 @@ struct obem_ctx {
   std::string err;
   obem::DevBuf ws[24];
   void *rocblas = nullptr;   // rocblas_handle, created on first solve
+  bool prof = false;         // per-kernel event timing
+  std::vector<obem_prof_rec> prof_recs;
+  std::vector<hipEvent_t> prof_pool;
 };
 
 namespace obem {
@@ -94,6 +103,18 @@ bool is_device_ptr(const void *p);
     hipError_t e_ = (call);                                          \
     if (e_ != hipSuccess) return obem::hip_fail(ctx, e_, #call, __LINE__); \
   } while (0)
+
+// Kernel timing: PROF_BEGIN/PROF_END bracket a launch with HIP events on the
+// context stream when profiling is enabled (obem_profile_enable).
+int prof_begin(obem_ctx *ctx, const char *name);
+void prof_end(obem_ctx *ctx, int idx);
+struct ProfScope {
+  obem_ctx *c;
+  int idx;
+  ProfScope(obem_ctx *ctx, const char *name) : c(ctx), idx(prof_begin(ctx, name)) {}
+  ~ProfScope() { prof_end(c, idx); }
+};
+#define OBEM_PROF(ctx, name) obem::ProfScope obem_prof_scope_(ctx, name)
 
 // Workspace slots.
 enum WsSlot {

@@ -657,11 +657,14 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
   hipLaunchKernelGGL(k_fill_u64, dim3(nbt(2 * n)), dim3(256), 0, ctx->stream, 2 * n, key, ~0ull);
   hipLaunchKernelGGL(k_fill_u8, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, dead);
   const double r2 = p->r_rec * p->r_rec;
+  {
+  OBEM_PROF(ctx, "recombine");
   hipLaunchKernelGGL(k_recomb_a, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->species, nn, S->x, S->y, S->z, r2, key);
   hipLaunchKernelGGL(k_recomb_b, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->species, nn, S->x, S->y, S->z, r2,
                      S->id, key, key + nz);
   hipLaunchKernelGGL(k_recomb_c, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->species, nn, S->x, S->y, S->z, r2,
                      S->id, key + nz, dead);
+  }
   OBEM_HIP(ctx, hipGetLastError());
   // 4. push + null-collision MC + absorption
   GasDev g;
@@ -716,9 +719,12 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
   double *child = (double *)ws_get(ctx, WS_PART, sizeof(double) * 12 * (size_t)std::max(mi, 1) * nz);
   int32_t *nchild = (int32_t *)ws_get(ctx, WS_NN, sizeof(int32_t) * nz + 64);
   if (!status || !child || !nchild) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  {
+  OBEM_PROF(ctx, "push_mc");
   hipLaunchKernelGGL(k_push_mc, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->x, S->y, S->z, S->vx, S->vy, S->vz,
                      S->species, S->id, E, E + nz, E + 2 * nz, dead, g, sd, G, status, hitv, nchild, child,
                      dd_counts, cnt_dev);
+  }
   OBEM_HIP(ctx, hipGetLastError());
   // 5. compaction: survivors in id order, then children in parent order
   hipLaunchKernelGGL(k_keep, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, dead, status, nchild, keep, kids);
@@ -758,6 +764,7 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
   o.id = (int64_t *)(ob + 6 * cap);
   o.sp = (int8_t *)(ob + 7 * cap);
   if (cap > 0) {
+    OBEM_PROF(ctx, "compact");
     hipLaunchKernelGGL(k_compact, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, in, keep, kpos, kids, cpos, child, mi,
                        (int)n_surv, (int)take, S->next_id, o);
     OBEM_HIP(ctx, hipGetLastError());
