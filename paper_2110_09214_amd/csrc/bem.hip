@@ -1,12 +1,15 @@
 // Collocation system of eq. (matrixBEM) on the GPU: FP64 assembly from the
-// analytic cell integrals, LU with partial pivoting (rocSOLVER), solves with
-// the cached factors and iterative refinement driven by a compensated FP64
-// residual.
+// analytic cell integrals, LU with partial pivoting (rocSOLVER getrf), the
+// inverse formed from the factors (getri), and solves as one matrix-vector
+// product followed by iterative refinement driven by a compensated FP64
+// residual against the stored A.
 //
-// The paper assembles the dense matrix on the GPU and inverts it with cuBLAS,
-// then reuses the inverse whenever voltages or free charges change.  Here the
-// factors are kept instead (same reuse, half the flops of an inverse and a
-// backward-stable solve), and each solve is refined against the stored A.
+// The paper assembles the dense matrix on the GPU, inverts it with cuBLAS and
+// reuses the inverse whenever voltages or free charges change.  A triangular
+// solve with one right-hand side is latency-bound on the GPU (hundreds of ms
+// at 40k unknowns), whereas a product with the inverse reads the matrix once
+// at HBM bandwidth; the refinement restores the backward error that an
+// explicit inverse alone would lose.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -301,17 +304,32 @@ obem_status bem_factor(obem_ctx *ctx, obem_meshh *m) {
   if (!(hd[0] > (double)N * 2.220446049250313e-16 * hd[1]))
     return fail(ctx, OBEM_ESINGULAR, "pivot ratio min|U_ii|/max|U_ii| = %.3e: collocation matrix is numerically singular",
                 hd[1] > 0 ? hd[0] / hd[1] : 0.0);
+  // Inverse from the LU factors, in place (the paper likewise keeps the
+  // inverse to re-solve cheaply whenever voltages or free charges change):
+  // every later solve is one bandwidth-bound matrix-vector product, refined
+  // against the stored A.
+  {
+    OBEM_PROF(ctx, "lu");
+    if (rocsolver_dgetri(h, N, m->LU, N, m->ipiv, m->info) != rocblas_status_success)
+      return fail(ctx, OBEM_EDEVICE, "rocsolver_dgetri failed");
+  }
+  OBEM_HIP(ctx, hipMemcpyAsync(&info, m->info, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (info != 0) return fail(ctx, OBEM_ESINGULAR, "inversion failed at U(%d,%d)", info, info);
   m->factored = true;
   return OBEM_OK;
 }
 
-static obem_status lu_solve(obem_ctx *ctx, obem_meshh *m, double *x) {
+// out = A^{-1} in (in and out distinct)
+static obem_status inv_apply(obem_ctx *ctx, obem_meshh *m, const double *in, double *out) {
   rocblas_handle h;
   obem_status st = handle(ctx, &h);
   if (st) return st;
   const int N = (int)m->n;
-  if (rocsolver_dgetrs(h, rocblas_operation_none, N, 1, m->LU, N, m->ipiv, x, N) != rocblas_status_success)
-    return fail(ctx, OBEM_EDEVICE, "rocsolver_dgetrs failed");
+  const double one = 1.0, zero = 0.0;
+  if (rocblas_set_pointer_mode(h, rocblas_pointer_mode_host) != rocblas_status_success ||
+      rocblas_dgemv(h, rocblas_operation_none, N, N, &one, m->LU, N, in, 1, &zero, out, 1) != rocblas_status_success)
+    return fail(ctx, OBEM_EDEVICE, "rocblas_dgemv failed");
   return OBEM_OK;
 }
 
@@ -323,11 +341,10 @@ obem_status bem_solve(obem_ctx *ctx, obem_meshh *m, const double *rhs, double *s
   const int N = (int)m->n;
   double *w = (double *)ws_get(ctx, WS_SOLVE0, sizeof(double) * (size_t)(3 * N + 8));
   if (!w) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
-  double *b = w, *r = w + N, *stats = w + 3 * N;
+  double *b = w, *r = w + N, *d = w + 2 * N, *stats = w + 3 * N;
   // keep b (rhs may alias sigma)
   OBEM_HIP(ctx, hipMemcpyAsync(b, rhs, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
-  OBEM_HIP(ctx, hipMemcpyAsync(sigma, b, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
-  st = lu_solve(ctx, m, sigma);
+  st = inv_apply(ctx, m, b, sigma);
   if (st) return st;
   double best_err = INFINITY;
   int it = 0;
@@ -350,9 +367,9 @@ obem_status bem_solve(obem_ctx *ctx, obem_meshh *m, const double *rhs, double *s
     } else if (it >= max_refine) {
       break;
     }
-    st = lu_solve(ctx, m, r);
+    st = inv_apply(ctx, m, r, d);
     if (st) return st;
-    hipLaunchKernelGGL(k_axpy1, dim3(nb(N)), dim3(256), 0, ctx->stream, N, r, sigma);
+    hipLaunchKernelGGL(k_axpy1, dim3(nb(N)), dim3(256), 0, ctx->stream, N, d, sigma);
     OBEM_HIP(ctx, hipGetLastError());
     ++it;
   }
