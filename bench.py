@@ -76,7 +76,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path shards by targets across "
-              f"GPUs, which this build does not run", file=sys.stderr)
+              f"GPUs (an all-gather of positions per step), which is not implemented here", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -173,7 +173,7 @@ def _wall(cx, cy, rz, n_theta, theta0=0.0):
 
 
 # --------------------------------------------------------------------------
-# Config 1: parallel-plate counter
+# Parallel-plate counter
 # --------------------------------------------------------------------------
 def parallel_plate_mesh(n=32, half=5e-3, gap=1e-3, v_bottom=0.0, v_top=-500.0):
     """Two square plates [-half, half]^2 at z = 0 (v_bottom) and z = gap
@@ -197,7 +197,7 @@ def parallel_plate_electrons(n=4096, seed=0, half=2.5e-3, gap=1e-3):
 
 
 # --------------------------------------------------------------------------
-# Config 2-5: GEM geometries
+# GEM geometries
 # --------------------------------------------------------------------------
 @dataclasses.dataclass
 class GemGeometry:
@@ -372,7 +372,7 @@ def space_charge_cloud(n_e=2_000_000, n_i=2_000_000, seed=2):
 
 
 def adjoint_workload(n_e=500_000, n_i=500_000, seed=3):
-    """Cloud as the space-charge config (positions first), then loss weights
+    """Clouds as in space_charge_cloud (positions first), then loss weights
     w ~ N(0,1)^(n x 3), all from seed 3."""
     rng = np.random.default_rng(seed)
     x, q, sp = gaussian_clouds(n_e, n_i, (0, 0, 230e-6), (0, 0, 210e-6), 50e-6, rng)

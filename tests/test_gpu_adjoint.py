@@ -92,7 +92,7 @@ def test_adjoint_matches_gpu_forward_fd(ctx):
         assert fd == pytest.approx(gt[i, ax], rel=1e-4, abs=1e-6 * np.abs(gt).max())
 
 
-def test_adjoint_config4_full_size(ctx, orc):
+def test_adjoint_1M_charges_49k_cells(ctx, orc):
     """1M particles (targets = sources) and the refined GEM mesh (~50k cells),
     mixed precision: 64 sampled charge-gradient components against the
     oracle's analytic gradient and 64 position components against the
@@ -114,6 +114,6 @@ def test_adjoint_config4_full_size(ctx, orc):
     fd = np.array([orc.fd_particle(x, q, w, 1e-7, m, sig, i, ax, 1e-6 * 5e-5) for i, ax in comps])
     got = np.array([gt[i, ax] for i, ax in comps])
     e_x = rel_l2(got, fd)
-    print("config4 adjoint: sigma", e_sig, "x", e_x)
+    print("1M-charge adjoint: sigma", e_sig, "x", e_x)
     assert e_sig <= 1e-4
     assert e_x <= 1e-4

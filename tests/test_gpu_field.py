@@ -22,7 +22,7 @@ def plates(orc):
 
 
 @pytest.mark.parametrize("prec", [B.OBEM_FP64, B.OBEM_MIXED])
-def test_pairwise_config1_electrons(ctx, orc, prec):
+def test_pairwise_parallel_plate_electrons(ctx, orc, prec):
     x, q = W.parallel_plate_electrons()
     E_ref, V_ref = orc.pair_field(x, x, q, 1e-7, tgt_is_src=True, want_v=True)
     E, V = B.field_eval(ctx, None, None, dev(x), dev(q), dev(x), 1e-7, prec, tgt_is_src=True, want_v=True)
@@ -85,7 +85,7 @@ def test_panel_field_parallel_plates(ctx, orc, plates, prec):
 
 
 @pytest.mark.parametrize("prec", [B.OBEM_FP64, B.OBEM_MIXED])
-def test_config1_cells_plus_electrons(ctx, orc, plates, prec):
+def test_parallel_plate_cells_plus_electrons(ctx, orc, plates, prec):
     """The parallel-plate workload: cells + 4095 other electrons at each of
     the 4096 electrons."""
     m, sig = plates
@@ -94,7 +94,7 @@ def test_config1_cells_plus_electrons(ctx, orc, plates, prec):
     bm = bind(ctx, m)
     E = B.field_eval(ctx, bm, dev(sig), dev(x), dev(q), dev(x), 1e-7, prec, tgt_is_src=True)
     err = rel_l2(host(E), E_ref)
-    print("config1 total", prec, err)
+    print("plates+electrons", prec, err)
     assert err <= TOL[prec]
     # deterministic: a second call is bitwise identical
     E2 = B.field_eval(ctx, bm, dev(sig), dev(x), dev(q), dev(x), 1e-7, prec, tgt_is_src=True)

@@ -32,7 +32,7 @@ def test_dirichlet_rows_reproduced_by_field_evaluation(orc, plates):
 
 
 def test_parallel_plate_centre_field(orc):
-    """Config-1 geometry: centre field close to V/d = 5e5 V/m (fringing and
+    """4096-cell parallel-plate counter: centre field close to V/d = 5e5 V/m (fringing and
     discretisation keep it within 1e-2)."""
     m = W.parallel_plate_mesh(n=32)
     sig, _ = orc.bem_solve(m, refine=1)
