@@ -73,6 +73,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="run one plain 1 GiB device copy and one pairwise launch on the 4M-charge cloud "
+                         "(for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs), print the sizes and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path shards by targets across "
@@ -97,6 +100,22 @@ def main():
 
     ctx = B.Context(0)
     stream = ctx.stream
+
+    if args.pmc_probe:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)                                     # reads and writes 1 GiB each
+        torch.cuda.synchronize()
+        x, q, sp = W.space_charge_cloud()
+        X, Q = dev(x), dev(q)
+        B.field_eval(ctx, None, None, X, Q, X, 1e-7, B.OBEM_MIXED, tgt_is_src=True)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "n_charges": len(q),
+                          "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
+        ctx.close()
+        return
 
     def timed(fn, steps, warmup):
         for _ in range(warmup):

@@ -134,6 +134,16 @@ obem_status obem_mesh_geometry(obem_ctx *ctx, const obem_meshh *mesh, double *ar
 obem_status bem_solve_charges(obem_ctx *ctx, obem_meshh *mesh, const double *rhs, double *sigma_out,
                               int max_refine, obem_solve_info *info);
 
+/* Adjoint of the collocation solve (not in the paper): g_rhs = A^{-T} g_sigma,
+ * the gradient of a loss L(sigma) with respect to the left-hand side of eq.
+ * (matrixBEM) given dL/dsigma: g_rhs_i = dL/dV_i on ed rows (sum over an
+ * electrode's cells for dL/dV_electrode) and dL/dsigma_F,i on dd rows.  Uses
+ * the cached inverse (assembling and factoring first if needed) and refines
+ * against A^T with compensated residuals.  Arguments and errors as for
+ * bem_solve_charges; the backward error in info refers to A^T. */
+obem_status bem_solve_charges_adjoint(obem_ctx *ctx, obem_meshh *mesh, const double *g_sigma, double *g_rhs,
+                                      int max_refine, obem_solve_info *info);
+
 /* Field at targets, eqs. (BEM3) and (nbody):
  *   E(x_t) = k_e sum_k sigma_k int_{C_k} (x_t - r')/|x_t - r'|^3 dS'
  *          + k_e sum_s q_s (x_t - x_s) / (|x_t - x_s|^2 + soft^2)^{3/2}

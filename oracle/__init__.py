@@ -414,3 +414,17 @@ def fd_particle(x, q, w, soft, mesh, sigma, m, axis, h):
     lib().oc_fd_particle.restype = C.c_double
     return lib().oc_fd_particle(C.c_int64(x.shape[0]), _p(x), _p(_f64(q)), _p(w), C.c_double(soft), C.c_int64(N),
                                 _p(a), _p(b), _p(c), _p(sg), C.c_int64(m), C.c_int(axis), C.c_double(h))
+
+
+def bem_solve_adjoint(mesh, g_sigma, A=None, refine=2):
+    """lambda with A^T lambda = g_sigma (LAPACK dgesv on A^T plus refinement
+    with a long-double residual): the gradient with respect to the
+    left-hand side of eq. (matrixBEM)."""
+    if A is None:
+        A = bem_matrix(mesh)
+    At = np.ascontiguousarray(A.T)
+    g = _f64(g_sigma)
+    lam = np.linalg.solve(At, g)
+    for _ in range(refine):
+        lam = lam + np.linalg.solve(At, residual_dense(At, lam, g))
+    return lam

@@ -70,8 +70,8 @@ class StepStats_t(C.Structure):
 
 SYMBOLS = ["obem_create", "obem_destroy", "obem_last_error", "obem_constants", "obem_profile_enable",
            "obem_profile_read", "obem_mesh_bind",
-           "obem_mesh_release", "obem_mesh_geometry", "bem_solve_charges", "field_eval", "field_eval_backward",
-           "track_step"]
+           "obem_mesh_release", "obem_mesh_geometry", "bem_solve_charges", "bem_solve_charges_adjoint", "field_eval",
+           "field_eval_backward", "track_step"]
 
 _lib = None
 
@@ -97,6 +97,7 @@ def load(path: str = LIB_PATH):
     lib.obem_mesh_release.argtypes = [vp, vp]
     lib.obem_mesh_geometry.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.bem_solve_charges.argtypes = [vp, vp, vp, vp, i32, C.POINTER(SolveInfo_t)]
+    lib.bem_solve_charges_adjoint.argtypes = [vp, vp, vp, vp, i32, C.POINTER(SolveInfo_t)]
     lib.field_eval.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, d, i32, C.c_uint, vp, vp, vp, vp]
     lib.field_eval_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, d, i32, C.c_uint,
                                         vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -218,6 +219,19 @@ def bem_solve_charges(ctx: Context, mesh: BoundMesh, rhs, sigma_out=None, max_re
                                         max_refine, C.byref(info) if want_info else None))
     return sigma_out, (dict(iterations=info.iterations, backward_error=info.backward_error,
                             residual_inf=info.residual_inf) if want_info else None)
+
+
+def bem_solve_charges_adjoint(ctx: Context, mesh: BoundMesh, g_sigma, g_rhs=None, max_refine=3, want_info=True):
+    """g_rhs = A^{-T} g_sigma (gradient with respect to the left-hand side of
+    the collocation system)."""
+    n = mesh.n
+    if g_rhs is None:
+        g_rhs = torch.empty(n, dtype=torch.float64, device=g_sigma.device)
+    info = SolveInfo_t()
+    ctx.check(ctx.lib.bem_solve_charges_adjoint(ctx.h, mesh.h, _ptr(g_sigma, n=n, name="g_sigma"),
+                                                _ptr(g_rhs, n=n), max_refine, C.byref(info) if want_info else None))
+    return g_rhs, (dict(iterations=info.iterations, backward_error=info.backward_error,
+                        residual_inf=info.residual_inf) if want_info else None)
 
 
 def _soa(x):

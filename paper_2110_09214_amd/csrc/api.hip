@@ -150,6 +150,32 @@ __global__ __launch_bounds__(256) void k_mesh_derive(int n, double *f, const int
   }
 }
 
+// Near-zone bounding spheres of consecutive 64-cell tiles: centre = mean
+// centroid, radius = max_k (|c_k - centre| + 3 D_k), inflated by 1e-6
+// relative so FP32 rounding of the per-pair test cannot escape it.
+__global__ __launch_bounds__(64) void k_tile_spheres(int n, const double *f, double *tiles) {
+  const int t = blockIdx.x;
+  const int k = t * 64 + threadIdx.x;
+  const bool ok = k < n;
+  double c[3] = {0, 0, 0};
+  const int cnt = min(64, n - t * 64);
+  for (int j = 0; j < cnt; ++j)
+    for (int d = 0; d < 3; ++d) c[d] += f[(size_t)(MF_GX + d) * n + t * 64 + j];
+  for (int d = 0; d < 3; ++d) c[d] /= cnt;
+  double r = 0.0;
+  if (ok) {
+    double dx = f[(size_t)MF_GX * n + k] - c[0], dy = f[(size_t)MF_GY * n + k] - c[1], dz = f[(size_t)MF_GZ * n + k] - c[2];
+    r = sqrt(dx * dx + dy * dy + dz * dz) + 3.0 * f[(size_t)MF_DIAM * n + k];
+  }
+  for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o));
+  if (threadIdx.x == 0) {
+    tiles[4 * t] = c[0];
+    tiles[4 * t + 1] = c[1];
+    tiles[4 * t + 2] = c[2];
+    tiles[4 * t + 3] = r * (1.0 + 1e-6) + 1e-12;
+  }
+}
+
 }  // namespace obem
 
 using namespace obem;
@@ -316,6 +342,13 @@ obem_status obem_mesh_bind(obem_ctx *ctx, const obem_mesh *mesh, obem_meshh **ou
   hipLaunchKernelGGL(k_mesh_derive, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, (int)n, m->f,
                      m->kind, mesh->eps_r1, mesh->eps_r2, bad);
   OBEM_HIP(ctx, hipGetLastError());
+  const int ntile = (int)((n + 63) / 64);
+  if (hipMalloc(&m->tiles, sizeof(double) * 4 * ntile) != hipSuccess) {
+    hipGetLastError();
+    return fail(ctx, OBEM_ENOMEM, "mesh allocation failed");
+  }
+  hipLaunchKernelGGL(k_tile_spheres, dim3(ntile), dim3(64), 0, ctx->stream, (int)n, m->f, m->tiles);
+  OBEM_HIP(ctx, hipGetLastError());
   int hbad = 0;
   OBEM_HIP(ctx, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   // host copies for the bounding box and diameters
@@ -327,6 +360,7 @@ obem_status obem_mesh_bind(obem_ctx *ctx, const obem_mesh *mesh, obem_meshh **ou
   if (hbad) {
     hipFree(m->f);
     hipFree(m->kind);
+    hipFree(m->tiles);
     delete m;
     return fail(ctx, OBEM_EINVAL, "mesh has %d degenerate or non-finite cells", hbad);
   }
@@ -352,6 +386,7 @@ obem_status obem_mesh_release(obem_ctx *ctx, obem_meshh *m) {
   hipStreamSynchronize(ctx->stream);
   hipFree(m->f);
   hipFree(m->kind);
+  hipFree(m->tiles);
   bem_release(m);
   hipFree(m->grid_start);
   hipFree(m->grid_items);
@@ -415,8 +450,8 @@ obem_status field_eval(obem_ctx *ctx, const obem_meshh *mesh, const double *sigm
   }
   if (st) return st;
   if (n_src > 0) {
-    st = launch_pair_field(ctx, n_src, sx, sy, sz, sq, to, soft, precision, tis, want_v, nullptr, acc, nullptr,
-                           nullptr);
+    st = launch_pair_field(ctx, n_src, sx, sy, sz, sq, to, soft, precision, tis, want_v, nullptr, nullptr, acc,
+                           nullptr, nullptr);
     if (st) return st;
   }
   return launch_scatter(ctx, to, acc, kKe, Ex, Ey, Ez, want_v ? V : nullptr);

@@ -138,6 +138,40 @@ __global__ __launch_bounds__(256) void k_residual_final(int N, int nch, const do
   r[i] = s + c;
 }
 
+// Transposed compensated residual r_j = g_j - sum_i A_ij l_i: one wave per
+// column of the column-major A (contiguous), Dot2 per lane, then a fixed
+// shuffle tree that carries the TwoSum errors.
+__global__ __launch_bounds__(256) void k_residual_t(int N, const double *__restrict__ A, const double *__restrict__ l,
+                                                    const double *__restrict__ g, double *r) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= N) return;  // whole wave exits together
+  const double *col = A + (size_t)j * N;
+  double s = 0.0, c = 0.0;
+  for (int i = lane; i < N; i += 64) {
+    const double a = col[i], li = l[i];
+    const double p = a * li;
+    const double pe = fma(a, li, -p);
+    double t, e;
+    two_sum(s, p, t, e);
+    s = t;
+    c += e + pe;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double s2 = __shfl_xor(s, o), c2 = __shfl_xor(c, o);
+    double t, e;
+    two_sum(s, s2, t, e);
+    s = t;
+    c = c + c2 + e;
+  }
+  if (lane == 0) {
+    double t, e;
+    two_sum(g[j], -s, t, e);
+    r[j] = t + (e - c);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_rowsum_final(int N, int nch, const double *__restrict__ hi, double *out) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= N) return;
@@ -320,21 +354,22 @@ obem_status bem_factor(obem_ctx *ctx, obem_meshh *m) {
   return OBEM_OK;
 }
 
-// out = A^{-1} in (in and out distinct)
-static obem_status inv_apply(obem_ctx *ctx, obem_meshh *m, const double *in, double *out) {
+// out = A^{-1} in, or A^{-T} in when trans (in and out distinct)
+static obem_status inv_apply(obem_ctx *ctx, obem_meshh *m, const double *in, double *out, bool trans = false) {
   rocblas_handle h;
   obem_status st = handle(ctx, &h);
   if (st) return st;
   const int N = (int)m->n;
   const double one = 1.0, zero = 0.0;
   if (rocblas_set_pointer_mode(h, rocblas_pointer_mode_host) != rocblas_status_success ||
-      rocblas_dgemv(h, rocblas_operation_none, N, N, &one, m->LU, N, in, 1, &zero, out, 1) != rocblas_status_success)
+      rocblas_dgemv(h, trans ? rocblas_operation_transpose : rocblas_operation_none, N, N, &one, m->LU, N, in, 1,
+                    &zero, out, 1) != rocblas_status_success)
     return fail(ctx, OBEM_EDEVICE, "rocblas_dgemv failed");
   return OBEM_OK;
 }
 
 obem_status bem_solve(obem_ctx *ctx, obem_meshh *m, const double *rhs, double *sigma, int max_refine,
-                      obem_solve_info *info) {
+                      obem_solve_info *info, bool trans) {
   obem_status st = bem_factor(ctx, m);
   if (st) return st;
   OBEM_PROF(ctx, "solve");
@@ -344,14 +379,19 @@ obem_status bem_solve(obem_ctx *ctx, obem_meshh *m, const double *rhs, double *s
   double *b = w, *r = w + N, *d = w + 2 * N, *stats = w + 3 * N;
   // keep b (rhs may alias sigma)
   OBEM_HIP(ctx, hipMemcpyAsync(b, rhs, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
-  st = inv_apply(ctx, m, b, sigma);
+  st = inv_apply(ctx, m, b, sigma, trans);
   if (st) return st;
   double best_err = INFINITY;
   int it = 0;
   double h[3] = {0, 0, 0};
   for (;;) {
-    st = residual(ctx, m, sigma, b, r);
-    if (st) return st;
+    if (trans) {
+      hipLaunchKernelGGL(k_residual_t, dim3((N + 3) / 4), dim3(256), 0, ctx->stream, N, m->A, sigma, b, r);
+      OBEM_HIP(ctx, hipGetLastError());
+    } else {
+      st = residual(ctx, m, sigma, b, r);
+      if (st) return st;
+    }
     if (info) {
       hipLaunchKernelGGL(k_absmax3, dim3(1), dim3(256), 0, ctx->stream, N, r, sigma, b, stats);
       OBEM_HIP(ctx, hipGetLastError());
@@ -367,7 +407,7 @@ obem_status bem_solve(obem_ctx *ctx, obem_meshh *m, const double *rhs, double *s
     } else if (it >= max_refine) {
       break;
     }
-    st = inv_apply(ctx, m, r, d);
+    st = inv_apply(ctx, m, r, d, trans);
     if (st) return st;
     hipLaunchKernelGGL(k_axpy1, dim3(nb(N)), dim3(256), 0, ctx->stream, N, d, sigma);
     OBEM_HIP(ctx, hipGetLastError());
@@ -394,5 +434,20 @@ extern "C" obem_status bem_solve_charges(obem_ctx *ctx, obem_meshh *mesh, const 
   if (max_refine < 0 || max_refine > 100) return fail(ctx, OBEM_EINVAL, "max_refine must be in [0, 100]");
   if (!is_device_ptr(rhs) || !is_device_ptr(sigma_out))
     return fail(ctx, OBEM_EINVAL, "rhs / sigma_out must be device arrays");
-  return bem_solve(ctx, mesh, rhs, sigma_out, max_refine, info);
+  return bem_solve(ctx, mesh, rhs, sigma_out, max_refine, info, false);
+}
+
+extern "C" obem_status bem_solve_charges_adjoint(obem_ctx *ctx, obem_meshh *mesh, const double *g_sigma,
+                                                 double *g_rhs, int max_refine, obem_solve_info *info) {
+  if (!ctx) return OBEM_EINVAL;
+  if (ctx->sticky) return OBEM_ESTATE;
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    hipGetLastError();
+    return fail(ctx, OBEM_EDEVICE, "hipSetDevice failed");
+  }
+  if (!mesh) return fail(ctx, OBEM_EINVAL, "mesh is NULL");
+  if (max_refine < 0 || max_refine > 100) return fail(ctx, OBEM_EINVAL, "max_refine must be in [0, 100]");
+  if (!is_device_ptr(g_sigma) || !is_device_ptr(g_rhs))
+    return fail(ctx, OBEM_EINVAL, "g_sigma / g_rhs must be device arrays");
+  return bem_solve(ctx, mesh, g_sigma, g_rhs, max_refine, info, true);
 }

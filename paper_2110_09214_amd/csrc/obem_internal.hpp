@@ -58,6 +58,7 @@ struct obem_meshh {
   int8_t *kind = nullptr;
   double bbox_lo[3], bbox_hi[3];
   double max_diam = 0;
+  double *tiles = nullptr;    // per 64-cell tile: centre (3), near-zone radius
   // collocation system (lazy)
   double *A = nullptr;        // n x n column-major
   double *LU = nullptr;       // n x n column-major
@@ -120,7 +121,7 @@ struct ProfScope {
 enum WsSlot {
   WS_BBOX = 0, WS_KEYS0, WS_KEYS1, WS_IDX0, WS_IDX1, WS_SORT_TMP, WS_TSORT, WS_ACC, WS_PART,
   WS_NN, WS_MISC0, WS_MISC1, WS_MISC2, WS_MISC3, WS_MISC4, WS_MISC5, WS_MISC6, WS_MISC7,
-  WS_SOLVE0, WS_SOLVE1, WS_SOLVE2
+  WS_SOLVE0, WS_SOLVE1, WS_SOLVE2, WS_SRC, WS_SRCPERM, WS_SRCKEY, WS_SORT_TMP2
 };
 
 // Target ordering (Morton keys) used by the field kernels.
@@ -136,10 +137,12 @@ obem_status order_targets(obem_ctx *ctx, int64_t n, const double *tx, const doub
 // (Ex, Ey, Ez, V) in units of 1/k_e.
 obem_status launch_panel_field(obem_ctx *ctx, const obem_meshh *m, const double *sigma,
                                const TargetOrder &to, obem_precision prec, bool want_v, double *acc);
+// species_t (caller order of the targets) and species_s (source order) are
+// needed only for the nearest opposite-species search (nn_idx != NULL).
 obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, const double *sy,
                               const double *sz, const double *sq, const TargetOrder &to, double soft,
-                              obem_precision prec, bool tgt_is_src, bool want_v, const int8_t *species,
-                              double *acc, int32_t *nn_idx, double *nn_d2);
+                              obem_precision prec, bool tgt_is_src, bool want_v, const int8_t *species_t,
+                              const int8_t *species_s, double *acc, int32_t *nn_idx, double *nn_d2);
 obem_status launch_scatter(obem_ctx *ctx, const TargetOrder &to, const double *acc, double scale,
                            double *Ex, double *Ey, double *Ez, double *V);
 obem_status launch_fill(obem_ctx *ctx, double *p, size_t n, double v);
@@ -147,7 +150,7 @@ obem_status launch_fill(obem_ctx *ctx, double *p, size_t n, double v);
 // Collocation system (bem.hip).
 obem_status bem_factor(obem_ctx *ctx, obem_meshh *m);
 obem_status bem_solve(obem_ctx *ctx, obem_meshh *m, const double *rhs, double *sigma, int max_refine,
-                      obem_solve_info *info);
+                      obem_solve_info *info, bool trans = false);
 void bem_release(obem_meshh *m);
 void solver_release(obem_ctx *ctx);
 

@@ -398,10 +398,42 @@ __global__ __launch_bounds__(256) void k_charges(int n, const int8_t *__restrict
   if (i < n) q[i] = (sp[i] == 1) ? kQe : -kQe;
 }
 
+// nearest partner: sorted-target order -> caller order, source-copy index ->
+// caller index
 __global__ __launch_bounds__(256) void k_scatter_nn(int n, const int32_t *__restrict__ perm,
-                                                    const int32_t *__restrict__ nn_s, int32_t *nn) {
+                                                    const int32_t *__restrict__ nn_s,
+                                                    const int32_t *__restrict__ src_perm, int32_t *nn) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) nn[perm[i]] = nn_s[i];
+  if (i < n) {
+    const int j = nn_s[i];
+    nn[perm[i]] = j >= 0 ? src_perm[j] : -1;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_species_key(int n, const int8_t *__restrict__ sp, uint8_t *key,
+                                                     int32_t *idx) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    key[i] = sp[i] == 1 ? 1 : 0;
+    idx[i] = i;
+  }
+}
+
+// Source copy grouped by charge (electrons and anions, then cations; stable):
+// its 256-source tiles each carry one charge, which the pairwise kernel
+// takes out of the inner loop.
+__global__ __launch_bounds__(256) void k_gather_sources(int n, const int32_t *__restrict__ perm,
+                                                        const double *__restrict__ x, const double *__restrict__ y,
+                                                        const double *__restrict__ z, const int8_t *__restrict__ sp,
+                                                        double *out, int8_t *sp_out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int j = perm[i];
+  out[i] = x[j];
+  out[(size_t)n + i] = y[j];
+  out[2 * (size_t)n + i] = z[j];
+  out[3 * (size_t)n + i] = (sp[j] == 1) ? kQe : -kQe;
+  sp_out[i] = sp[j];
 }
 
 __global__ __launch_bounds__(256) void k_fill_u64(int n, unsigned long long *p, unsigned long long v) {
@@ -636,7 +668,26 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
   if (!q || !E || !nn_s || !nnd || !nn) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
   int32_t *keep = nn + nz, *kids = nn + 2 * nz, *hitv = nn + 3 * nz;
   // 2. field at every particle (cells + all other particles) and nearest partner
-  hipLaunchKernelGGL(k_charges, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->species, q);
+  (void)q;
+  uint8_t *skey = (uint8_t *)ws_get(ctx, WS_SRCKEY, 2 * nz + 64);
+  int32_t *sperm = (int32_t *)ws_get(ctx, WS_SRCPERM, sizeof(int32_t) * 2 * nz);
+  double *srcb = (double *)ws_get(ctx, WS_SRC, sizeof(double) * 4 * nz + nz + 64);
+  if (!skey || !sperm || !srcb) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  int8_t *ssp = (int8_t *)(srcb + 4 * nz);
+  {
+    hipLaunchKernelGGL(k_species_key, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->species, skey, sperm);
+    size_t tb = 0;
+    OBEM_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, tb, skey, skey + nz, sperm, sperm + nz, n, 0, 1,
+                                                     ctx->stream));
+    void *tmp = ws_get(ctx, WS_SORT_TMP2, tb + 256);
+    if (!tmp) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+    OBEM_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(tmp, tb, skey, skey + nz, sperm, sperm + nz, n, 0, 1,
+                                                     ctx->stream));
+    hipLaunchKernelGGL(k_gather_sources, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, sperm + nz, S->x, S->y, S->z,
+                       S->species, srcb, ssp);
+    OBEM_HIP(ctx, hipGetLastError());
+  }
+  const int32_t *src_perm = sperm + nz;
   TargetOrder to;
   st = order_targets(ctx, n, S->x, S->y, S->z, &to);
   if (st) return st;
@@ -644,12 +695,12 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
   if (!acc) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
   st = mesh ? launch_panel_field(ctx, mesh, sigma, to, p->precision, false, acc) : launch_fill(ctx, acc, 4 * nz, 0.0);
   if (st) return st;
-  st = launch_pair_field(ctx, n, S->x, S->y, S->z, q, to, p->soft, p->precision, true, false, S->species, acc, nn_s,
-                         nnd);
+  st = launch_pair_field(ctx, n, srcb, srcb + nz, srcb + 2 * nz, srcb + 3 * nz, to, p->soft, p->precision, true,
+                         false, S->species, ssp, acc, nn_s, nnd);
   if (st) return st;
   st = launch_scatter(ctx, to, acc, kKe, E, E + nz, E + 2 * nz, nullptr);
   if (st) return st;
-  hipLaunchKernelGGL(k_scatter_nn, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, to.perm, nn_s, nn);
+  hipLaunchKernelGGL(k_scatter_nn, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, to.perm, nn_s, src_perm, nn);
   // 3. recombination
   unsigned long long *key = (unsigned long long *)ws_get(ctx, WS_MISC2, sizeof(unsigned long long) * 2 * nz);
   uint8_t *dead = (uint8_t *)ws_get(ctx, WS_MISC6, nz + 64);

@@ -117,3 +117,24 @@ def test_adjoint_1M_charges_49k_cells(ctx, orc):
     print("1M-charge adjoint: sigma", e_sig, "x", e_x)
     assert e_sig <= 1e-4
     assert e_x <= 1e-4
+
+
+def test_autograd_function(ctx):
+    """FieldEval's gradients equal field_eval_backward's (separate sources:
+    sigma, target and source positions)."""
+    from paper_2110_09214_amd.autograd import field
+
+    m = W.parallel_plate_mesh(n=8, half=1e-3, gap=0.5e-3)
+    rng = np.random.default_rng(9)
+    sig = dev(synthetic_sigma(m, seed=9)).requires_grad_(True)
+    xs = dev(rng.normal(size=(300, 3)) * 5e-5 + np.array([0, 0, 2.5e-4])).requires_grad_(True)
+    xt = dev(rng.normal(size=(200, 3)) * 5e-5 + np.array([0, 0, 2.5e-4])).requires_grad_(True)
+    q = dev(rng.choice([-1.0, 1.0], size=300) * W.E_CHARGE)
+    w = dev(rng.normal(size=(200, 3)))
+    bm = bind(ctx, m)
+    E = field(ctx, bm, sig, xs, q, xt, 1e-7, B.OBEM_FP64)
+    (E * w).sum().backward()
+    gs, gt, gsrc = B.field_eval_backward(ctx, bm, sig.detach(), xs.detach(), q, xt.detach(), 1e-7, w, B.OBEM_FP64)
+    assert torch.allclose(sig.grad, gs, rtol=1e-12, atol=0)
+    assert torch.allclose(xt.grad, gt, rtol=1e-12, atol=0)
+    assert torch.allclose(xs.grad, gsrc, rtol=1e-12, atol=0)

@@ -102,3 +102,40 @@ def test_invalid_arguments(ctx):
         ctx.check(ctx.lib.bem_solve_charges(ctx.h, bm.h, host_rhs.ctypes.data, out.data_ptr(), 1, None))
     with pytest.raises(B.ObemError):
         B.field_eval(ctx, None, None, None, None, dev(np.zeros((4, 3))), -1.0, B.OBEM_FP64)
+
+
+def test_adjoint_solve_against_oracle(ctx, orc):
+    """g_rhs = A^{-T} g_sigma on the plates-with-slab mesh (ed and dd rows)."""
+    m = W.plates_with_slab_mesh(n=12)
+    A = orc.bem_matrix(m)
+    g = np.random.default_rng(5).normal(size=m.n)
+    ref = orc.bem_solve_adjoint(m, g, A=A)
+    bm = bind(ctx, m)
+    lam, info = B.bem_solve_charges_adjoint(ctx, bm, dev(g))
+    print("adjoint solve", rel_l2(host(lam), ref), info)
+    assert info["backward_error"] <= 1e-15
+    assert rel_l2(host(lam), ref) <= 1e-10
+
+
+def test_voltage_gradient_through_solve_and_field(ctx):
+    """End to end: L = w . E(x; sigma(V)) -- dL/dV of the top plate (sum of
+    g_rhs over its cells) equals the exact difference of L (linear in V)."""
+    from paper_2110_09214_amd.autograd import field, solve_charges
+
+    m = W.parallel_plate_mesh(n=8, half=1e-3, gap=0.5e-3)
+    bm = bind(ctx, m)
+    rng = np.random.default_rng(6)
+    x = dev(rng.uniform([-5e-4, -5e-4, 1e-4], [5e-4, 5e-4, 4e-4], size=(50, 3)))
+    w = dev(rng.normal(size=(50, 3)))
+    top = dev((m.a[:, 2] > 1e-4).astype(np.float64))
+    v = torch.tensor(-500.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    rhs = top * v
+    sig = solve_charges(ctx, bm, rhs)
+    L = (field(ctx, bm, sig, None, None, x, 0.0, B.OBEM_FP64) * w).sum()
+    L.backward()
+    with torch.no_grad():
+        def Lv(vv):
+            s, _ = B.bem_solve_charges(ctx, bm, top * vv)
+            return float((B.field_eval(ctx, bm, s, None, None, x, 0.0, B.OBEM_FP64) * w).sum())
+        d = (Lv(-400.0) - Lv(-600.0)) / 200.0
+    assert float(v.grad) == pytest.approx(d, rel=1e-9)

@@ -118,3 +118,19 @@ def test_matrix_free_residual_rows(orc, plates):
     res, absr = orc.bem_residual_rows(m, sig, m.rhs, rows)
     assert np.allclose(absr, np.abs(A[rows]).sum(axis=1), rtol=1e-14)
     assert np.abs(res).max() <= 1e-15 * absr.max() * np.abs(sig).max()
+
+
+def test_adjoint_solve_is_gradient_of_linear_functional(orc):
+    """For L = c . sigma(rhs) (sigma = A^{-1} rhs), dL/drhs = A^{-T} c: checked
+    by exact differences (L is linear in rhs)."""
+    m = W.plates_with_slab_mesh(n=6)
+    A = orc.bem_matrix(m)
+    rng = np.random.default_rng(4)
+    c = rng.normal(size=m.n)
+    lam = orc.bem_solve_adjoint(m, c, A=A)
+    s0, _ = orc.bem_solve(m, m.rhs, A=A)
+    for k in (0, 40, m.n - 1):
+        r = m.rhs.copy()
+        r[k] += 1.0
+        s1, _ = orc.bem_solve(m, r, A=A)
+        assert c @ (s1 - s0) == pytest.approx(lam[k], rel=1e-9, abs=1e-12 * np.abs(lam).max())
