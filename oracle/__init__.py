@@ -428,3 +428,17 @@ def bem_solve_adjoint(mesh, g_sigma, A=None, refine=2):
     for _ in range(refine):
         lam = lam + np.linalg.solve(At, residual_dense(At, lam, g))
     return lam
+
+
+def influence(mesh, rhs, x, q):
+    """Left-hand side modified by the charges q at x (eqs. potpart, fldpart,
+    BEMpotpart, BEMfldpart); returns (rhs_out, Vbar (N,), Ebar (N,3))."""
+    x = _f64(x).reshape(-1, 3)
+    N = mesh.n
+    out = np.zeros(N)
+    vb = np.zeros(N)
+    eb = np.zeros((N, 3))
+    lib().oc_influence(C.c_int64(N), _p(_f64(mesh.a)), _p(_f64(mesh.b)), _p(_f64(mesh.c)),
+                       _p(np.ascontiguousarray(mesh.kind, np.int8)), _p(_f64(mesh.eps1)), _p(_f64(mesh.eps2)),
+                       _p(_f64(rhs)), C.c_int64(x.shape[0]), _p(x), _p(_f64(q)), _p(out), _p(vb), _p(eb))
+    return out, vb, eb

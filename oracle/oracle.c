@@ -776,3 +776,39 @@ double oc_fd_particle(int64_t n, const double *x, const double *q, const double 
   }
   return (double)(ke * (acc + acc2 + acc3) / (2.0L * (real)h));
 }
+
+/* Influence of point charges on the collocation equations (section 3.3.2,
+ * eqs. (potpart), (fldpart), (BEMpotpart), (BEMfldpart)).  The charges'
+ * potential and field averaged over cell i,
+ *   Vbar_i = k_e / A_i sum_p q_p int_{C_i} dS / |r - x_p|      = k_e/A_i sum_p q_p IV_i(x_p)
+ *   Ebar_i = k_e / A_i sum_p q_p int_{C_i} (r - x_p)/|r - x_p|^3 dS = -k_e/A_i sum_p q_p IE_i(x_p)
+ * modify the left-hand side: ed rows V_i - Vbar_i, dd rows
+ * sigma_F,i - (eps_2 - eps_1) Ebar_i . n_i with absolute permittivities
+ * eps = eps0 eps_r. */
+void oc_influence(int64_t N, const double *a, const double *b, const double *c, const int8_t *kind,
+                  const double *eps1, const double *eps2, const double *rhs, int64_t n, const double *x,
+                  const double *q, double *rhs_out, double *vbar, double *ebar) {
+  real ke = k_e();
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < N; ++i) {
+    tri_t T;
+    tri_setup(a + 3 * i, b + 3 * i, c + 3 * i, &T);
+    real sv = 0, ex = 0, ey = 0, ez = 0;
+    for (int64_t p = 0; p < n; ++p) {
+      real iv;
+      v3 ie;
+      tri_IV_IE(&T, ld(x + 3 * p), &iv, &ie);
+      real qp = q[p];
+      sv += qp * iv;
+      ex += qp * ie.x; ey += qp * ie.y; ez += qp * ie.z;
+    }
+    real vb = ke * sv / T.area;
+    v3 eb = scl(mk(ex, ey, ez), -ke / T.area);
+    if (vbar) vbar[i] = (double)vb;
+    if (ebar) { ebar[3 * i] = (double)eb.x; ebar[3 * i + 1] = (double)eb.y; ebar[3 * i + 2] = (double)eb.z; }
+    if (kind[i] == 0)
+      rhs_out[i] = (double)((real)rhs[i] - vb);
+    else
+      rhs_out[i] = (double)((real)rhs[i] - EPS0 * ((real)eps2[i] - (real)eps1[i]) * dot(eb, T.n));
+  }
+}

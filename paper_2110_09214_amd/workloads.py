@@ -459,6 +459,17 @@ def plates_with_slab_mesh(n=24, half=5e-3, gap=1e-3, t=0.4e-3, eps=3.0, v_top=-5
     return Mesh.concat([bot, top, slab], name="plates_with_slab")
 
 
+def dielectric_box_mesh(half=5e-3, depth=5e-3, eps=4.0, n=24, nz=12):
+    """Closed dielectric box [-half, half]^2 x [-depth, 0] in vacuum: all dd
+    cells, outward normals (dielectric on the -n side)."""
+    L = 2 * half
+    top = _rect((-half, -half, 0.0), (L, 0, 0), (0, L, 0), n, n)
+    bot = _rect((-half, -half, -depth), (0, L, 0), (L, 0, 0), n, n)
+    geo = GemGeometry(half_x=half, half_y=half)
+    sides = _side_strips(geo, -depth, 0.0, nz, L / n)
+    return _make(np.concatenate([top, bot, sides]), KIND_DD, 0.0, eps1=eps, eps2=1.0)
+
+
 # --------------------------------------------------------------------------
 # Synthetic gas
 # --------------------------------------------------------------------------

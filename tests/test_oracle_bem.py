@@ -134,3 +134,37 @@ def test_adjoint_solve_is_gradient_of_linear_functional(orc):
         r[k] += 1.0
         s1, _ = orc.bem_solve(m, r, A=A)
         assert c @ (s1 - s0) == pytest.approx(lam[k], rel=1e-9, abs=1e-12 * np.abs(lam).max())
+
+
+def _point_charge_problem(orc, m, eps_image):
+    d = 1e-3
+    xp = np.array([[0.0, 0.0, d]])
+    q = np.array([1e-15])
+    rhs, _, _ = orc.influence(m, m.rhs, xp, q)
+    sig, _ = orc.bem_solve(m, rhs, refine=1)
+    pts = np.array([[0, 0, 0.5e-3], [3e-4, -2e-4, 0.3e-3]])
+    E = orc.panel_field(pts, m.a, m.b, m.c, sig) + orc.pair_field(pts, xp, q, 0.0)
+    img = orc.pair_field(pts, np.array([[0, 0, d], [0, 0, -d]]), np.array([q[0], eps_image * q[0]]), 0.0)
+    return np.linalg.norm(E - img, axis=1) / np.linalg.norm(img, axis=1)
+
+
+def test_influence_grounded_plate_image_charge(orc):
+    """Influence of a point charge on the Dirichlet rows (eqs. potpart,
+    BEMpotpart): a charge 1 mm above a grounded 1 cm plate induces the image
+    field of -q at the mirror point near the plate centre."""
+    m = W.parallel_plate_mesh(n=16, v_bottom=0.0, v_top=0.0)
+    keep = np.arange(m.n // 2)
+    m = W.Mesh(a=m.a[keep], b=m.b[keep], c=m.c[keep], kind=m.kind[keep], eps1=m.eps1[keep], eps2=m.eps2[keep],
+               rhs=m.rhs[keep])
+    err = _point_charge_problem(orc, m, -1.0)
+    assert err.max() < 0.02
+
+
+def test_influence_dielectric_image_charge(orc):
+    """Influence on the Neumann rows (eqs. fldpart, BEMfldpart): a charge 1 mm
+    above a thick dielectric block (eps 4) sees the image -q (eps-1)/(eps+1)
+    at the mirror point (without the term, or with its sign flipped, the
+    error would be ~60 %)."""
+    m = W.dielectric_box_mesh(n=16, nz=8)
+    err = _point_charge_problem(orc, m, -(4.0 - 1.0) / (4.0 + 1.0))
+    assert err.max() < 0.025
