@@ -144,6 +144,28 @@ obem_status bem_solve_charges(obem_ctx *ctx, obem_meshh *mesh, const double *rhs
 obem_status bem_solve_charges_adjoint(obem_ctx *ctx, obem_meshh *mesh, const double *g_sigma, double *g_rhs,
                                       int max_refine, obem_solve_info *info);
 
+/* Influence of point charges on the collocation equations, section 3.3.2
+ * (eqs. (potpart), (fldpart), (BEMpotpart), (BEMfldpart)): the charges'
+ * potential and field averaged over each cell,
+ *   Vbar_i = k_e/A_i sum_p q_p int_{C_i} dS/|r - x_p|
+ *   Ebar_i = k_e/A_i sum_p q_p int_{C_i} (r - x_p)/|r - x_p|^3 dS
+ * move to the left-hand side of eq. (matrixBEM):
+ *   rhs_out_i = rhs_i - Vbar_i                                  (ed rows)
+ *   rhs_out_i = rhs_i - eps0 (eps_r2 - eps_r1) Ebar_i . n_i     (dd rows)
+ * so that bem_solve_charges(rhs_out) gives the cell charges in the presence
+ * of the space charge.  sx, sy, sz, sq (charges in C): n_src device entries
+ * (n_src may be 0: rhs_out = rhs).  rhs, rhs_out: n_panels device entries
+ * (they may alias).  vbar and ebar_x/y/z (n_panels device entries each) are
+ * optional outputs, NULL to skip; the three ebar arrays are given together
+ * or not at all.  precision as for field_eval (cell/charge pairs within 3
+ * cell diameters are always FP64 closed forms).  A charge exactly in a
+ * cell's plane inside the cell contributes the principal value of the normal
+ * field (0).  Sums are deterministic. */
+obem_status bem_influence(obem_ctx *ctx, const obem_meshh *mesh, int64_t n_src, const double *sx,
+                          const double *sy, const double *sz, const double *sq, const double *rhs,
+                          double *rhs_out, obem_precision precision, double *vbar, double *ebar_x,
+                          double *ebar_y, double *ebar_z);
+
 /* Field at targets, eqs. (BEM3) and (nbody):
  *   E(x_t) = k_e sum_k sigma_k int_{C_k} (x_t - r')/|x_t - r'|^3 dS'
  *          + k_e sum_s q_s (x_t - x_s) / (|x_t - x_s|^2 + soft^2)^{3/2}

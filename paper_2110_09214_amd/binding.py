@@ -70,8 +70,8 @@ class StepStats_t(C.Structure):
 
 SYMBOLS = ["obem_create", "obem_destroy", "obem_last_error", "obem_constants", "obem_profile_enable",
            "obem_profile_read", "obem_mesh_bind",
-           "obem_mesh_release", "obem_mesh_geometry", "bem_solve_charges", "bem_solve_charges_adjoint", "field_eval",
-           "field_eval_backward", "track_step"]
+           "obem_mesh_release", "obem_mesh_geometry", "bem_solve_charges", "bem_solve_charges_adjoint", "bem_influence",
+           "field_eval", "field_eval_backward", "track_step"]
 
 _lib = None
 
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
     lib.obem_mesh_geometry.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.bem_solve_charges.argtypes = [vp, vp, vp, vp, i32, C.POINTER(SolveInfo_t)]
     lib.bem_solve_charges_adjoint.argtypes = [vp, vp, vp, vp, i32, C.POINTER(SolveInfo_t)]
+    lib.bem_influence.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp]
     lib.field_eval.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, d, i32, C.c_uint, vp, vp, vp, vp]
     lib.field_eval_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, d, i32, C.c_uint,
                                         vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -236,6 +237,28 @@ def bem_solve_charges_adjoint(ctx: Context, mesh: BoundMesh, g_sigma, g_rhs=None
 
 def _soa(x):
     return [x[:, k].contiguous() for k in range(3)]
+
+
+def bem_influence(ctx: Context, mesh: BoundMesh, rhs, xs, q, precision=OBEM_MIXED, rhs_out=None, want_bar=False):
+    """Left-hand side of the collocation system with the influence of the
+    point charges q at xs (n_s, 3) moved onto it (section 3.3.2).  Returns
+    rhs_out, or (rhs_out, Vbar, Ebar (n, 3)) with want_bar."""
+    n = mesh.n
+    n_s = 0 if xs is None else int(xs.shape[0])
+    sx = _soa(xs) if n_s else [None] * 3
+    if rhs_out is None:
+        rhs_out = torch.empty(n, dtype=torch.float64, device=rhs.device)
+    vb = eb = None
+    if want_bar:
+        vb = torch.empty(n, dtype=torch.float64, device=rhs.device)
+        eb = [torch.empty(n, dtype=torch.float64, device=rhs.device) for _ in range(3)]
+    ctx.check(ctx.lib.bem_influence(ctx.h, mesh.h, n_s, *[_ptr(a, n=n_s) for a in sx],
+                                    _ptr(q, n=n_s, name="q") if n_s else None, _ptr(rhs, n=n, name="rhs"),
+                                    _ptr(rhs_out, n=n), int(precision), _ptr(vb, n=n),
+                                    *([_ptr(a, n=n) for a in eb] if want_bar else [None] * 3)))
+    if want_bar:
+        return rhs_out, vb, torch.stack(eb, dim=1)
+    return rhs_out
 
 
 def field_eval(ctx: Context, mesh, sigma, xs, q, xt, soft, precision=OBEM_MIXED, tgt_is_src=False, want_v=False,

@@ -34,6 +34,7 @@ obem_status hip_fail(obem_ctx *ctx, hipError_t e, const char *what, int line) {
 }
 
 void *ws_get(obem_ctx *ctx, int slot, size_t bytes) {
+  if (slot < 0 || slot >= WS_COUNT) return nullptr;
   DevBuf &b = ctx->ws[slot];
   if (bytes == 0) bytes = 1;
   if (b.bytes >= bytes) return b.p;
@@ -349,6 +350,17 @@ obem_status obem_mesh_bind(obem_ctx *ctx, const obem_mesh *mesh, obem_meshh **ou
   }
   hipLaunchKernelGGL(k_tile_spheres, dim3(ntile), dim3(64), 0, ctx->stream, (int)n, m->f, m->tiles);
   OBEM_HIP(ctx, hipGetLastError());
+  if (hipMalloc(&m->order, sizeof(int32_t) * n) != hipSuccess) {
+    hipGetLastError();
+    return fail(ctx, OBEM_ENOMEM, "mesh allocation failed");
+  }
+  {
+    TargetOrder co;
+    obem_status st = order_targets(ctx, n, m->f + (size_t)MF_GX * n, m->f + (size_t)MF_GY * n,
+                                   m->f + (size_t)MF_GZ * n, &co);
+    if (st) return st;
+    OBEM_HIP(ctx, hipMemcpyAsync(m->order, co.perm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, ctx->stream));
+  }
   int hbad = 0;
   OBEM_HIP(ctx, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   // host copies for the bounding box and diameters
@@ -361,6 +373,7 @@ obem_status obem_mesh_bind(obem_ctx *ctx, const obem_mesh *mesh, obem_meshh **ou
     hipFree(m->f);
     hipFree(m->kind);
     hipFree(m->tiles);
+    hipFree(m->order);
     delete m;
     return fail(ctx, OBEM_EINVAL, "mesh has %d degenerate or non-finite cells", hbad);
   }
@@ -387,6 +400,7 @@ obem_status obem_mesh_release(obem_ctx *ctx, obem_meshh *m) {
   hipFree(m->f);
   hipFree(m->kind);
   hipFree(m->tiles);
+  hipFree(m->order);
   bem_release(m);
   hipFree(m->grid_start);
   hipFree(m->grid_items);

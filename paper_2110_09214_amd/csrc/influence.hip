@@ -1,0 +1,304 @@
+// Influence of the point charges on the collocation equations (section
+// 3.3.2, eqs. (potpart), (fldpart), (BEMpotpart), (BEMfldpart)): the charges'
+// potential and field averaged over each cell,
+//   Vbar_i = k_e/A_i sum_p q_p IV_i(x_p),   Ebar_i = -k_e/A_i sum_p q_p IE_i(x_p),
+// change the left-hand side of the system before it is solved:
+//   ed rows V_i - Vbar_i,   dd rows sigma_F,i - eps0 (eps_r2 - eps_r1) Ebar_i . n_i.
+//
+// It is the transpose of the cell field: one thread per cell, cells taken in
+// the mesh's Morton order of centroids (a workgroup's cells are spatially
+// close and are recentred on its first centroid), charges staged in LDS
+// tiles, gridDim.y chunks of charges with per-chunk partial sums reduced in
+// chunk order.  Precision
+// regimes as in the field: FP64 closed form within 3 diameters, FP32 7-point
+// rule within 64, 3-point rule beyond (mixed); closed form within 48
+// diameters, FP64 7-point rule beyond (FP64).
+#include <algorithm>
+#include <cmath>
+
+#include "cellmath.hpp"
+#include "obem_internal.hpp"
+
+namespace obem {
+
+constexpr int kTI = 256;
+
+__device__ __forceinline__ void neum_i(float &s, float &c, float v) {
+  float t = s + v;
+  if (fabsf(s) >= fabsf(v))
+    c += (s - t) + v;
+  else
+    c += (v - t) + s;
+  s = t;
+}
+
+// FP64 closed form of one cell at one charge: q IV and q IE.
+__device__ __forceinline__ void infl_closed(const double *__restrict__ f, int N, int k, double px, double py,
+                                            double pz, double q, double &sv, double &ex, double &ey, double &ez) {
+  d3 P[3];
+  P[0] = mk3(f[(size_t)MF_AX * N + k] - px, f[(size_t)MF_AY * N + k] - py, f[(size_t)MF_AZ * N + k] - pz);
+  P[1] = mk3(f[(size_t)MF_BX * N + k] - px, f[(size_t)MF_BY * N + k] - py, f[(size_t)MF_BZ * N + k] - pz);
+  P[2] = mk3(f[(size_t)MF_CX * N + k] - px, f[(size_t)MF_CY * N + k] - py, f[(size_t)MF_CZ * N + k] - pz);
+  const d3 n = mk3(f[(size_t)MF_NX * N + k], f[(size_t)MF_NY * N + k], f[(size_t)MF_NZ * N + k]);
+  d3 IE;
+  double IV;
+  cell_closed_form<true>(P, n, 2.0 * f[(size_t)MF_AREA * N + k], IE, IV);
+  sv = fma(q, IV, sv);
+  ex = fma(q, IE.x, ex);
+  ey = fma(q, IE.y, ey);
+  ez = fma(q, IE.z, ez);
+}
+
+__global__ __launch_bounds__(kTI) void k_influence_mixed(int N, const double *__restrict__ f,
+                                                         const int32_t *__restrict__ ord, int n_s,
+                                                         const double *__restrict__ sx,
+                                                         const double *__restrict__ sy,
+                                                         const double *__restrict__ sz,
+                                                         const double *__restrict__ sq, int chunk, double *part) {
+  __shared__ float4 P[kTI];
+  const int tid = threadIdx.x;
+  const int k = blockIdx.x * kTI + tid;  // sorted position
+  const bool active = k < N;
+  const int kk = ord[active ? k : N - 1];  // cell index
+  const int k0 = ord[blockIdx.x * kTI];
+  const double c0 = f[(size_t)MF_GX * N + k0], c1 = f[(size_t)MF_GY * N + k0], c2 = f[(size_t)MF_GZ * N + k0];
+  // own cell, FP32 relative to the workgroup centre
+  const float g0 = (float)(f[(size_t)MF_GX * N + kk] - c0), g1 = (float)(f[(size_t)MF_GY * N + kk] - c1),
+              g2 = (float)(f[(size_t)MF_GZ * N + kk] - c2);
+  float q7[21], q3[9];
+#pragma unroll
+  for (int m = 0; m < 21; ++m)
+    q7[m] = (float)(f[(size_t)(MF_Q7 + m) * N + kk] - (m % 3 == 0 ? c0 : (m % 3 == 1 ? c1 : c2)));
+#pragma unroll
+  for (int m = 0; m < 9; ++m)
+    q3[m] = (float)(f[(size_t)(MF_Q3 + m) * N + kk] - (m % 3 == 0 ? c0 : (m % 3 == 1 ? c1 : c2)));
+  const double area = f[(size_t)MF_AREA * N + kk], D = f[(size_t)MF_DIAM * N + kk];
+  const float w0 = (float)(area * Rule7::w0), wa = (float)(area * Rule7::wa), wb = (float)(area * Rule7::wb),
+              w3 = (float)(area / 3.0);
+  const float lim_near = (float)(kNearMixed * kNearMixed * D * D), lim_far = (float)(kFar3Mixed * kFar3Mixed * D * D);
+  float hv = 0, hx = 0, hy = 0, hz = 0, lv = 0, lx = 0, ly = 0, lz = 0;
+  double nv = 0, nx = 0, ny = 0, nz = 0;
+  const int jb = blockIdx.y * chunk, je = min(n_s, jb + chunk);
+  for (int jt = jb; jt < je; jt += kTI) {
+    const int cnt = min(kTI, je - jt);
+    __syncthreads();
+    if (tid < cnt) {
+      const int j = jt + tid;
+      P[tid] = make_float4((float)(sx[j] - c0), (float)(sy[j] - c1), (float)(sz[j] - c2), (float)sq[j]);
+    }
+    __syncthreads();
+    float pv = 0, px = 0, py = 0, pz = 0;
+    for (int jj = 0; jj < cnt; ++jj) {
+      const float4 p = P[jj];
+      const float dx = p.x - g0, dy = p.y - g1, dz = p.z - g2;
+      const float R2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+      const bool nearp = R2 < lim_near;
+      if (__any(nearp)) {
+        if (nearp && active) {
+          const int j = jt + jj;
+          infl_closed(f, N, kk, sx[j], sy[j], sz[j], sq[j], nv, nx, ny, nz);
+        }
+      }
+      const bool need7 = !nearp && R2 < lim_far;
+      float sv = 0, ex = 0, ey = 0, ez = 0;
+      if (__any(need7)) {
+        if (!nearp) {
+#pragma unroll
+          for (int m = 0; m < 7; ++m) {
+            const float w = (m == 0) ? w0 : (m < 4 ? wa : wb);
+            const float ax = p.x - q7[3 * m], ay = p.y - q7[3 * m + 1], az = p.z - q7[3 * m + 2];
+            const float rr = fmaf(ax, ax, fmaf(ay, ay, az * az));
+            const float ri = __builtin_amdgcn_rsqf(rr);
+            const float wr = w * ri;
+            const float s = wr * (ri * ri);
+            sv += wr;
+            ex = fmaf(s, ax, ex);
+            ey = fmaf(s, ay, ey);
+            ez = fmaf(s, az, ez);
+          }
+        }
+      } else if (!nearp) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const float ax = p.x - q3[3 * m], ay = p.y - q3[3 * m + 1], az = p.z - q3[3 * m + 2];
+          const float rr = fmaf(ax, ax, fmaf(ay, ay, az * az));
+          const float ri = __builtin_amdgcn_rsqf(rr);
+          const float wr = w3 * ri;
+          const float s = wr * (ri * ri);
+          sv += wr;
+          ex = fmaf(s, ax, ex);
+          ey = fmaf(s, ay, ey);
+          ez = fmaf(s, az, ez);
+        }
+      }
+      pv = fmaf(p.w, sv, pv);
+      px = fmaf(p.w, ex, px);
+      py = fmaf(p.w, ey, py);
+      pz = fmaf(p.w, ez, pz);
+    }
+    neum_i(hv, lv, pv);
+    neum_i(hx, lx, px);
+    neum_i(hy, ly, py);
+    neum_i(hz, lz, pz);
+  }
+  if (active) {
+    const size_t o = (size_t)blockIdx.y * 4 * N;
+    part[o + k] = ((double)hv + (double)lv) + nv;
+    part[o + (size_t)N + k] = ((double)hx + (double)lx) + nx;
+    part[o + 2 * (size_t)N + k] = ((double)hy + (double)ly) + ny;
+    part[o + 3 * (size_t)N + k] = ((double)hz + (double)lz) + nz;
+  }
+}
+
+__global__ __launch_bounds__(kTI) void k_influence_fp64(int N, const double *__restrict__ f,
+                                                        const int32_t *__restrict__ ord, int n_s,
+                                                        const double *__restrict__ sx,
+                                                        const double *__restrict__ sy,
+                                                        const double *__restrict__ sz,
+                                                        const double *__restrict__ sq, int chunk, double *part) {
+  __shared__ double4 P[kTI];
+  const int tid = threadIdx.x;
+  const int k = blockIdx.x * kTI + tid;  // sorted position
+  const bool active = k < N;
+  const int kk = ord[active ? k : N - 1];  // cell index
+  const double g0 = f[(size_t)MF_GX * N + kk], g1 = f[(size_t)MF_GY * N + kk], g2 = f[(size_t)MF_GZ * N + kk];
+  const double area = f[(size_t)MF_AREA * N + kk], D = f[(size_t)MF_DIAM * N + kk];
+  const double lim = kQuadFp64 * kQuadFp64 * D * D;
+  double q7[21];
+#pragma unroll
+  for (int m = 0; m < 21; ++m) q7[m] = f[(size_t)(MF_Q7 + m) * N + kk];
+  double sv = 0, ex = 0, ey = 0, ez = 0;
+  const int jb = blockIdx.y * chunk, je = min(n_s, jb + chunk);
+  for (int jt = jb; jt < je; jt += kTI) {
+    const int cnt = min(kTI, je - jt);
+    __syncthreads();
+    if (tid < cnt) {
+      const int j = jt + tid;
+      P[tid] = make_double4(sx[j], sy[j], sz[j], sq[j]);
+    }
+    __syncthreads();
+    for (int jj = 0; jj < cnt; ++jj) {
+      const double4 p = P[jj];
+      const double dx = p.x - g0, dy = p.y - g1, dz = p.z - g2;
+      const bool quad = fma(dx, dx, fma(dy, dy, dz * dz)) >= lim;
+      if (!__all(quad)) {
+        if (!quad && active) infl_closed(f, N, kk, p.x, p.y, p.z, p.w, sv, ex, ey, ez);
+      }
+      if (__any(quad)) {
+        if (quad) {
+#pragma unroll
+          for (int m = 0; m < 7; ++m) {
+            const double w = area * ((m == 0) ? Rule7::w0 : (m < 4 ? Rule7::wa : Rule7::wb));
+            const double ax = p.x - q7[3 * m], ay = p.y - q7[3 * m + 1], az = p.z - q7[3 * m + 2];
+            const double ri = 1.0 / sqrt(fma(ax, ax, fma(ay, ay, az * az)));
+            const double wr = p.w * w * ri;
+            const double s = wr * ri * ri;
+            sv += wr;
+            ex = fma(s, ax, ex);
+            ey = fma(s, ay, ey);
+            ez = fma(s, az, ez);
+          }
+        }
+      }
+    }
+  }
+  if (active) {
+    const size_t o = (size_t)blockIdx.y * 4 * N;
+    part[o + k] = sv;
+    part[o + (size_t)N + k] = ex;
+    part[o + 2 * (size_t)N + k] = ey;
+    part[o + 3 * (size_t)N + k] = ez;
+  }
+}
+
+// Sum of the chunks in order, then the modified left-hand side.
+__global__ __launch_bounds__(256) void k_influence_rhs(int N, int nch, const double *__restrict__ part,
+                                                       const int32_t *__restrict__ ord,
+                                                       const double *__restrict__ f, const int8_t *__restrict__ kind,
+                                                       const double *__restrict__ rhs, double *rhs_out, double *vbar,
+                                                       double *ebx, double *eby, double *ebz) {
+  const int k = blockIdx.x * 256 + threadIdx.x;  // sorted position
+  if (k >= N) return;
+  const int i = ord[k];
+  double s[4] = {0, 0, 0, 0};
+  for (int c = 0; c < nch; ++c)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) s[m] += part[(size_t)c * 4 * N + (size_t)m * N + k];
+  const double area = f[(size_t)MF_AREA * N + i];
+  const double vb = kKe * s[0] / area;
+  const double eb[3] = {-kKe * s[1] / area, -kKe * s[2] / area, -kKe * s[3] / area};
+  if (vbar) vbar[i] = vb;
+  if (ebx) {
+    ebx[i] = eb[0];
+    eby[i] = eb[1];
+    ebz[i] = eb[2];
+  }
+  if (kind[i] == 0) {
+    rhs_out[i] = rhs[i] - vb;
+  } else {
+    const double en = eb[0] * f[(size_t)MF_NX * N + i] + eb[1] * f[(size_t)MF_NY * N + i] +
+                      eb[2] * f[(size_t)MF_NZ * N + i];
+    rhs_out[i] = rhs[i] - kEps0 * (f[(size_t)MF_EPS2 * N + i] - f[(size_t)MF_EPS1 * N + i]) * en;
+  }
+}
+
+obem_status influence_rhs(obem_ctx *ctx, const obem_meshh *m, int64_t n_src, const double *sx, const double *sy,
+                          const double *sz, const double *sq, const double *rhs, double *rhs_out, obem_precision prec,
+                          double *vbar, double *ebx, double *eby, double *ebz) {
+  const int N = (int)m->n, n_s = (int)n_src;
+  const int bc = (N + kTI - 1) / kTI;
+  int nsplit = 1, chunk = std::max(n_s, 1);
+  if (n_s > 0) {
+    nsplit = std::max(1, std::min((2048 + bc - 1) / bc, (n_s + 1023) / 1024));
+    nsplit = std::min(nsplit, 64);
+    chunk = (n_s + nsplit - 1) / nsplit;
+    chunk = (chunk + kTI - 1) / kTI * kTI;
+    nsplit = (n_s + chunk - 1) / chunk;
+  }
+  double *part = (double *)ws_get(ctx, WS_MISC3, sizeof(double) * 4 * (size_t)N * nsplit);
+  if (!part) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  OBEM_PROF(ctx, "influence");
+  if (n_s == 0) {
+    obem_status st = launch_fill(ctx, part, 4 * (size_t)N, 0.0);
+    if (st) return st;
+  } else if (prec == OBEM_MIXED) {
+    hipLaunchKernelGGL(k_influence_mixed, dim3(bc, nsplit), dim3(kTI), 0, ctx->stream, N, m->f, m->order, n_s, sx, sy,
+                       sz, sq, chunk, part);
+  } else {
+    hipLaunchKernelGGL(k_influence_fp64, dim3(bc, nsplit), dim3(kTI), 0, ctx->stream, N, m->f, m->order, n_s, sx, sy,
+                       sz, sq, chunk, part);
+  }
+  OBEM_HIP(ctx, hipGetLastError());
+  hipLaunchKernelGGL(k_influence_rhs, dim3(bc), dim3(256), 0, ctx->stream, N, nsplit, part, m->order, m->f, m->kind, rhs, rhs_out,
+                     vbar, ebx, eby, ebz);
+  OBEM_HIP(ctx, hipGetLastError());
+  return OBEM_OK;
+}
+
+}  // namespace obem
+
+using namespace obem;
+
+extern "C" obem_status bem_influence(obem_ctx *ctx, const obem_meshh *mesh, int64_t n_src, const double *sx,
+                                     const double *sy, const double *sz, const double *sq, const double *rhs,
+                                     double *rhs_out, obem_precision precision, double *vbar, double *ebar_x,
+                                     double *ebar_y, double *ebar_z) {
+  if (!ctx) return OBEM_EINVAL;
+  if (ctx->sticky) return OBEM_ESTATE;
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    hipGetLastError();
+    return fail(ctx, OBEM_EDEVICE, "hipSetDevice failed");
+  }
+  if (!mesh) return fail(ctx, OBEM_EINVAL, "mesh is NULL");
+  if (n_src < 0 || n_src >= ((int64_t)1 << 31)) return fail(ctx, OBEM_EINVAL, "n_src out of range");
+  if (precision != OBEM_FP64 && precision != OBEM_MIXED) return fail(ctx, OBEM_EINVAL, "bad precision");
+  if (!is_device_ptr(rhs) || !is_device_ptr(rhs_out)) return fail(ctx, OBEM_EINVAL, "rhs / rhs_out must be device");
+  if (n_src > 0 && (!is_device_ptr(sx) || !is_device_ptr(sy) || !is_device_ptr(sz) || !is_device_ptr(sq)))
+    return fail(ctx, OBEM_EINVAL, "source arrays must be device memory");
+  const bool eb = ebar_x || ebar_y || ebar_z;
+  if (eb && !(ebar_x && ebar_y && ebar_z)) return fail(ctx, OBEM_EINVAL, "ebar_x/y/z: all or none");
+  const void *outs[] = {vbar, ebar_x, ebar_y, ebar_z};
+  for (const void *p : outs)
+    if (p && !is_device_ptr(p)) return fail(ctx, OBEM_EINVAL, "outputs must be device memory");
+  return influence_rhs(ctx, mesh, n_src, sx, sy, sz, sq, rhs, rhs_out, precision, vbar, ebar_x, ebar_y, ebar_z);
+}

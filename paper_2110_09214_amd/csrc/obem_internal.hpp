@@ -38,6 +38,14 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Workspace slots.
+enum WsSlot {
+  WS_BBOX = 0, WS_KEYS0, WS_KEYS1, WS_IDX0, WS_IDX1, WS_SORT_TMP, WS_TSORT, WS_ACC, WS_PART,
+  WS_NN, WS_MISC0, WS_MISC1, WS_MISC2, WS_MISC3, WS_MISC4, WS_MISC5, WS_MISC6, WS_MISC7,
+  WS_SOLVE0, WS_SOLVE1, WS_SOLVE2, WS_SRC, WS_SRCPERM, WS_SRCKEY, WS_SORT_TMP2,
+  WS_COUNT
+};
+
 }  // namespace obem
 
 // Number of per-cell FP64 SoA arrays kept by a bound mesh.
@@ -59,6 +67,7 @@ struct obem_meshh {
   double bbox_lo[3], bbox_hi[3];
   double max_diam = 0;
   double *tiles = nullptr;    // per 64-cell tile: centre (3), near-zone radius
+  int32_t *order = nullptr;   // cell indices in Morton order of the centroids
   // collocation system (lazy)
   double *A = nullptr;        // n x n column-major
   double *LU = nullptr;       // n x n column-major
@@ -84,7 +93,7 @@ struct obem_ctx {
   hipStream_t stream = nullptr;
   bool sticky = false;
   std::string err;
-  obem::DevBuf ws[24];
+  obem::DevBuf ws[obem::WS_COUNT];
   void *rocblas = nullptr;   // rocblas_handle, created on first solve
   bool prof = false;         // per-kernel event timing
   std::vector<obem_prof_rec> prof_recs;
@@ -117,12 +126,6 @@ struct ProfScope {
 };
 #define OBEM_PROF(ctx, name) obem::ProfScope obem_prof_scope_(ctx, name)
 
-// Workspace slots.
-enum WsSlot {
-  WS_BBOX = 0, WS_KEYS0, WS_KEYS1, WS_IDX0, WS_IDX1, WS_SORT_TMP, WS_TSORT, WS_ACC, WS_PART,
-  WS_NN, WS_MISC0, WS_MISC1, WS_MISC2, WS_MISC3, WS_MISC4, WS_MISC5, WS_MISC6, WS_MISC7,
-  WS_SOLVE0, WS_SOLVE1, WS_SOLVE2, WS_SRC, WS_SRCPERM, WS_SRCKEY, WS_SORT_TMP2
-};
 
 // Target ordering (Morton keys) used by the field kernels.
 struct TargetOrder {
