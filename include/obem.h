@@ -251,6 +251,8 @@ typedef struct {
   obem_precision precision;
   int32_t resolve;      /* 1: rebuild the RHS from rhs0 + charging counts and
                            re-solve sigma before the field evaluation             */
+  int32_t influence;    /* with resolve: also move the live particles' influence
+                           onto the RHS before the solve (as bem_influence)       */
   const double *rhs0;   /* device, n_panels: [V_i ; sigma_F0,i]                    */
 } obem_step_params;
 

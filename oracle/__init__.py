@@ -332,11 +332,14 @@ def recombine(species, ids, nn_idx, nn_d2, r_rec):
     return dead
 
 
-def track_step(state, mesh, sigma, gas, params, dd_counts, rhs0=None, area=None, A=None, resolve=False):
+def track_step(state, mesh, sigma, gas, params, dd_counts, rhs0=None, area=None, A=None, resolve=False,
+               with_influence=False):
     """One tracking step, in the order: (re-)solve for sigma if charge was
-    deposited (eq. (charge-up)), field at the start positions (panels +
-    pairwise), recombination, constant-field flights with null-collision MC
-    and absorption, compaction with appended children, charging-up counts.
+    deposited (eq. (charge-up)), with with_influence after moving the
+    particles' influence onto the left-hand side (section 3.3.2), field at the
+    start positions (panels + pairwise), recombination, constant-field
+    flights with null-collision MC and absorption, compaction with appended
+    children, charging-up counts.
 
     state: dict with x (n,3), v (n,3), species (n,) int8, id (n,) int64,
     next_id int.  Returns (new_state, sigma, stats)."""
@@ -345,12 +348,14 @@ def track_step(state, mesh, sigma, gas, params, dd_counts, rhs0=None, area=None,
     sp = state["species"].copy()
     ids = state["id"].copy()
     e = constants()["e"]
+    q = np.where(sp == 1, e, -e).astype(np.float64)
     if resolve:
         dd = mesh.kind == 1
         rhs = np.array(rhs0, np.float64)
         rhs[dd] += e * dd_counts[dd] / area[dd]
+        if with_influence and x.shape[0]:
+            rhs, _, _ = influence(mesh, rhs, x, q)
         sigma, _ = bem_solve(mesh, rhs, A=A)
-    q = np.where(sp == 1, e, -e).astype(np.float64)
     n = x.shape[0]
     stats = {}
     if n:

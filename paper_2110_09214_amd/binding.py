@@ -57,7 +57,8 @@ class StepParams_t(C.Structure):
     _fields_ = [("dt", C.c_double), ("step", C.c_uint32), ("seed", C.c_uint64), ("max_coll", C.c_int32),
                 ("max_ion_per_step", C.c_int32), ("ion_v_cap", C.c_double), ("box_lo", C.c_double * 3),
                 ("box_hi", C.c_double * 3), ("soft", C.c_double), ("r_rec", C.c_double),
-                ("precision", C.c_int), ("resolve", C.c_int32), ("rhs0", C.c_void_p)]
+                ("precision", C.c_int), ("resolve", C.c_int32), ("influence", C.c_int32),
+                ("rhs0", C.c_void_p)]
 
 
 class StepStats_t(C.Structure):
@@ -352,7 +353,8 @@ def track_step(ctx: Context, mesh: BoundMesh, parts: Particles, gas_s, params: d
     p = StepParams_t(params["dt"], params["step"], params["seed"], params["max_coll"], params["max_ion_per_step"],
                      params["ion_v_cap"], (C.c_double * 3)(*params["box_lo"]), (C.c_double * 3)(*params["box_hi"]),
                      params["soft"], params["r_rec"], int(params.get("precision", OBEM_MIXED)),
-                     int(params.get("resolve", 0)), _ptr(rhs0) if rhs0 is not None else None)
+                     int(params.get("resolve", 0)), int(params.get("influence", 0)),
+                     _ptr(rhs0) if rhs0 is not None else None)
     ps = parts.struct()
     stats = StepStats_t()
     st = ctx.lib.track_step(ctx.h, mesh.h if mesh is not None else None, C.byref(ps), C.byref(gas_s), C.byref(p),

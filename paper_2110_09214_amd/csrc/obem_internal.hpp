@@ -155,6 +155,11 @@ obem_status bem_factor(obem_ctx *ctx, obem_meshh *m);
 obem_status bem_solve(obem_ctx *ctx, obem_meshh *m, const double *rhs, double *sigma, int max_refine,
                       obem_solve_info *info, bool trans = false);
 void bem_release(obem_meshh *m);
+
+// Influence of point charges on the collocation left-hand side (influence.hip).
+obem_status influence_rhs(obem_ctx *ctx, const obem_meshh *m, int64_t n_src, const double *sx, const double *sy,
+                          const double *sz, const double *sq, const double *rhs, double *rhs_out, obem_precision prec,
+                          double *vbar, double *ebx, double *eby, double *ebz);
 void solver_release(obem_ctx *ctx);
 
 }  // namespace obem

@@ -646,6 +646,16 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
     hipLaunchKernelGGL(k_build_rhs, dim3(nbt(N)), dim3(256), 0, ctx->stream, N, p->rhs0,
                        mesh->n_dd ? dd_counts : nullptr, mesh->kind, mesh->f, rhs);
     OBEM_HIP(ctx, hipGetLastError());
+    if (p->influence && n > 0) {
+      // the live particles' influence on the cell equations (section 3.3.2)
+      double *qp = (double *)ws_get(ctx, WS_MISC4, sizeof(double) * (size_t)n);
+      if (!qp) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+      hipLaunchKernelGGL(k_charges, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->species, qp);
+      OBEM_HIP(ctx, hipGetLastError());
+      st = influence_rhs(ctx, mesh, n, S->x, S->y, S->z, qp, rhs, rhs, p->precision, nullptr, nullptr, nullptr,
+                         nullptr);
+      if (st) return st;
+    }
     st = bem_solve(ctx, mesh, rhs, sigma, 2, nullptr);
     if (st) return st;
   }

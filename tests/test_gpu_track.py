@@ -44,7 +44,10 @@ def _params(step, prec, cap=20000):
                 precision=prec, resolve=1 if step > 0 else 0)
 
 
-def test_track_step_fp64_exact_stream(ctx, orc):
+@pytest.mark.parametrize("influence", [False, True])
+def test_track_step_fp64_exact_stream(ctx, orc, influence):
+    """With influence, each re-solve also carries the particles' influence on
+    the cell equations (section 3.3.2)."""
     m, st0 = _scenario()
     gas = W.synthetic_ar_co2()
     _, area, _, _ = orc.tri_geometry(m.a, m.b, m.c)
@@ -60,8 +63,9 @@ def test_track_step_fp64_exact_stream(ctx, orc):
     state = st0
     for s in range(3):
         p = _params(s, B.OBEM_FP64)
+        p["influence"] = int(influence)
         state, sig_o, counts_o, so, _ = orc.track_step(state, m, sig_o, gas, p, counts_o, rhs0=m.rhs, area=area,
-                                                       A=A, resolve=bool(p["resolve"]))
+                                                       A=A, resolve=bool(p["resolve"]), with_influence=influence)
         sg = B.track_step(ctx, bm, parts, gas_s, p, counts_g, sig_g, rhs0)
         g = parts.state()
         print("step", s, "oracle", so, "gpu", sg)
