@@ -1,28 +1,34 @@
 #!/usr/bin/env python
-"""Benchmark of the space-charge field path on one MI355X (gfx950).
+"""Benchmark of the space-charge tracking step on one MI355X (gfx950).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
 Primary line (one JSON object on stdout): the space-charge avalanche cloud --
 4,000,000 point charges (2M electrons, 2M cations, Gaussian clouds of sigma
-50 um) above the single-GEM cell mesh (40,776 cells).  One step is the
-per-tracking-step field re-evaluation of the dynamic option: the cell charges
-are re-solved from the right-hand side with the cached LU factors (plus
-compensated refinement), then the field at every charge is summed over all
-cells and all other charges in mixed precision.  `value` is
+50 um, at rest) in the single-GEM cell (40,776 cells) filled with the
+synthetic Ar/CO2-like gas.  One step is one pass of the whole hot path
+(track_step, dynamic option): right-hand side from the charging counts and
+FP64 re-solve of the cell charges with the cached LU factors, field at every
+charge from all cells and all other charges (mixed precision) with the
+nearest opposite-species partner, recombination, Euler push with
+null-collision Monte Carlo (1 ps), absorption and charging-up, compaction.
+Every timed step starts from the same 4M-charge state (restored by a device
+copy inside the timed region), so each step does the same work.  `value` is
 (pair + charge-cell interactions) per second of that step.
 
-`extra` carries the other measurements of the same metric: the GEM cell with
-1M field points in mixed precision and in FP64 (interactions/s each, and the
-relative L2 difference between the two), and the adjoint's backward/forward
-time ratio on 1M charges with the refined (49,128-cell) mesh.
+`extra` carries the other measurements of the same metric: the field-only
+step (re-solve + field, no transport), the influence of the 4M charges on the
+40,776 cell equations, the GEM cell with 1M field points in mixed precision
+and in FP64 (interactions/s each, and the relative L2 difference between the
+two), and the adjoint's backward/forward time ratio on 1M charges with the
+refined (49,128-cell) mesh.
 
 `roofline` is for the dominant kernel (the pairwise sum): 20 flop per pair
 interaction (3 sub, 3 FMA for |d|^2 + s^2, 1 rsqrt, 2 mul for the cube, 1 mul
 by q, 3 FMA into E) divided by that kernel's average duration, measured with
 HIP events on the library's stream inside the timed region, against the
 published FP32 vector peak.  `cpu_baseline` times the CPU oracle on a sample
-of the same workload (its error against the GPU result is reported too).
+of the same workload (its error against the GPU field is reported too).
 """
 from __future__ import annotations
 
@@ -147,14 +153,37 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] assembly + LU + solve of {N} cells: {time.time() - t0:.1f}s, backward error {info['backward_error']:.2e}")
     X, Q = dev(x), dev(q)
-    E = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    gas = W.synthetic_ar_co2()
+    gas_s, gas_keep = B.gas_struct(gas, "cuda")
+    geo = W.GemGeometry()
+    top = geo.t_kapton / 2 + geo.t_cu
+    params = dict(dt=1e-12, step=0, seed=5, max_coll=64, max_ion_per_step=4, ion_v_cap=2e4,
+                  box_lo=(-geo.half_x, -geo.half_y, -(top + 2e-3)), box_hi=(geo.half_x, geo.half_y, top + 3e-3),
+                  soft=1e-7, r_rec=1e-6, precision=B.OBEM_MIXED, resolve=1, influence=0)
+    ids0 = torch.arange(n, dtype=torch.int64, device="cuda")
+    sp0 = dev(sp, torch.int8)
+    parts = B.Particles(n + n // 4, "cuda", X, torch.zeros_like(X), sp0, ids0, n)
+    counts = torch.zeros(N, dtype=torch.int64, device="cuda")
+    step_stats = []
+
+    def restore():
+        for k in range(3):
+            parts.cols[k][:n].copy_(X[:, k])
+            parts.cols[3 + k][:n].zero_()
+        parts.species[:n].copy_(sp0)
+        parts.id[:n].copy_(ids0)
+        parts.n_live, parts.next_id = n, n
+        counts.zero_()
 
     def step():
-        B.bem_solve_charges(ctx, bm, rhs, sigma, max_refine=2, want_info=False)
-        B.field_eval(ctx, bm, sigma, X, Q, X, 1e-7, B.OBEM_MIXED, tgt_is_src=True, out=E)
+        restore()
+        params["step"] += 1
+        st = B.track_step(ctx, bm, parts, gas_s, params, counts, sigma, rhs)
+        step_stats.append(st)
 
     log(f"[bench] timing {args.steps} steps after {args.warmup} warm-up")
     ms, prof = timed(step, args.steps, args.warmup)
+    last = step_stats[-1]
     pairs = n * (n - 1)
     inter = pairs + n * N
     value = inter / (ms / 1e3)
@@ -162,6 +191,8 @@ def main():
     achieved = FLOP_PER_PAIR * pairs / (pair_ms / 1e3) / 1e12
     log(f"[bench] step {ms:.1f} ms, {value:.3e} interactions/s; kernels: " +
         ", ".join(f"{k} {v[0] / max(v[1], 1):.2f}ms x{v[1]}" for k, v in prof.items()))
+    log(f"[bench] last step: {dict((k, last[k]) for k in ('n_live', 'recombined', 'absorbed', 'left_world', 'children'))}"
+        f" collisions {list(last['real_collisions'])} null {last['null_collisions']}")
     traffic = traffic_from_profiles()
     out = {
         "metric": "particle-source interactions/s, mixed vs FP64 at 1e-5 rel err; bwd/fwd ratio",
@@ -177,10 +208,13 @@ def main():
         "dtype": "mixed-f32/f64",
         "data": "synthetic",
         "config": {
-            "workload": "space-charge avalanche cloud: 4,000,000 point charges (2M electrons + 2M cations, "
-                        "Gaussian sigma 50 um) above the single-GEM cell mesh of 40,776 cells; per step the FP64 "
-                        "cell-charge re-solve (cached LU + refinement) and the mixed-precision field at every charge",
-            "n_charges": n, "n_cells": N, "softening_m": 1e-7, "precision": "mixed",
+            "workload": "space-charge avalanche cloud: 4,000,000 point charges (2M electrons + 2M cations at rest, "
+                        "Gaussian sigma 50 um) in the single-GEM cell of 40,776 cells with a synthetic Ar/CO2-like "
+                        "gas; per step the whole tracking step: FP64 cell-charge re-solve (cached LU + refinement), "
+                        "mixed-precision field at every charge with nearest opposite-species partner, "
+                        "recombination (1 um), 1 ps Euler push with null-collision MC, absorption and charging-up, "
+                        "compaction",
+            "n_charges": n, "n_cells": N, "softening_m": 1e-7, "precision": "mixed", "dt_s": 1e-12,
             "interactions_per_step": inter, "pair_interactions_per_step": pairs,
         },
         "roofline": {
@@ -195,7 +229,10 @@ def main():
             "launch_ms": pair_ms,
         },
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+        "last_step": {k: (list(v) if k == "real_collisions" else v) for k, v in last.items()},
     }
+    E = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    B.field_eval(ctx, bm, sigma, X, Q, X, 1e-7, B.OBEM_MIXED, tgt_is_src=True, out=E)
 
     # ------------------------------------------------------------ cpu baseline
     if not args.no_cpu_baseline:
@@ -214,15 +251,27 @@ def main():
         tc = time.time() - t0
         rate_p = len(it) * n / tp
         rate_c = len(ic) * N / tc
-        t_full = pairs / rate_p + n * N / rate_c
+        # transport: the oracle's push + null-collision MC + absorption (every
+        # flight chord tested against all cells) on a sample of the cloud in
+        # a uniform 1 MV/m drift field
+        im = rng.choice(n, 1024, replace=False)
+        xm, vm, spm = x[im].copy(), np.zeros((len(im), 3)), sp[im].copy()
+        Em = np.zeros((len(im), 3))
+        Em[:, 2] = 1e6
+        t0 = time.time()
+        oracle.mc_step(xm, vm, spm, im.astype(np.int64), Em, gas, params, mesh)
+        tm = time.time() - t0
+        rate_m = len(im) / tm
+        t_full = pairs / rate_p + n * N / rate_c + n / rate_m
         Eg = torch.stack(E, 1).cpu().numpy()
         # oracle total field on the targets that have both parts
         ref = Ep[:len(ic)] + Ec
         err = float(np.linalg.norm(Eg[ic] - ref) / np.linalg.norm(ref))
         out["cpu_baseline"] = {
             "value": inter / t_full, "unit": "interactions/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(it)} of the {n} charges against all {n} charges ({tp:.1f}s) and {len(ic)} against all "
-                      f"{N} cells ({tc:.1f}s); long-double brute force; per-part rates combined over the full step",
+            "sample": f"{len(it)} of the {n} charges against all {n} charges ({tp:.1f}s), {len(ic)} against all "
+                      f"{N} cells ({tc:.1f}s), push + MC + absorption of {len(im)} charges ({tm:.1f}s); per-part "
+                      f"rates combined over the full step (solve, recombination and compaction not sampled)",
             "gpu_vs_oracle_rel_l2_on_sample": err,
         }
         log(f"[bench] cpu oracle: {inter / t_full:.3e} interactions/s on {cores} cores; GPU vs oracle rel L2 {err:.2e}")
@@ -230,6 +279,23 @@ def main():
     # ------------------------------------------------------------------ extras
     if not args.no_extra:
         extra = {}
+
+        def field_step():
+            B.bem_solve_charges(ctx, bm, rhs, sigma, max_refine=2, want_info=False)
+            B.field_eval(ctx, bm, sigma, X, Q, X, 1e-7, B.OBEM_MIXED, tgt_is_src=True, out=E)
+
+        ms_f, _ = timed(field_step, 2, 1)
+        extra["field_only_step_ms"] = ms_f
+        extra["field_only_interactions_per_s"] = inter / (ms_f / 1e3)
+        rhs_i = torch.empty_like(rhs)
+
+        def infl():
+            B.bem_influence(ctx, bm, rhs, X, Q, B.OBEM_MIXED, rhs_out=rhs_i)
+
+        ms_i, _ = timed(infl, 2, 1)
+        extra["influence_ms"] = ms_i
+        extra["influence_interactions_per_s"] = n * N / (ms_i / 1e3)
+        log(f"[bench] field-only step {ms_f:.1f} ms; influence of {n} charges on {N} cells {ms_i:.1f} ms")
         # GEM cell, 1M field points: mixed vs FP64
         pts = dev(W.gem_cell_points())
         npts = int(pts.shape[0])

@@ -478,9 +478,11 @@ __global__ __launch_bounds__(kThreads) void k_pair_mixed(int n_t, const double *
                                                          const int8_t *__restrict__ species,
                                                          const int8_t *__restrict__ species_s, float soft2,
                                                          int chunk, double *part, float *nn_d2p,
-                                                         int32_t *nn_ip) {
+                                                         int32_t *nn_ip, const double *__restrict__ tbox,
+                                                         float nn_cut2) {
   __shared__ float4 S[kThreads];
   __shared__ int K[kThreads];
+  __shared__ float WB[kThreads / 64][6];
   const int tid = threadIdx.x;
   const int i0 = blockIdx.x * kThreads;
   const int i = i0 + tid;
@@ -495,12 +497,50 @@ __global__ __launch_bounds__(kThreads) void k_pair_mixed(int n_t, const double *
   const int self = active ? perm[i] : -1;
   const int jb = blockIdx.y * chunk;
   const int je = min(n_s, jb + chunk);
+  // Nearest-partner search limited to nn_cut: bounding box of the
+  // workgroup's targets (recentred FP32), tested against each source tile's
+  // box (tbox, FP64, 256-source tiles); tiles farther than the cut skip the
+  // search.  Inactive lanes hold the first target, which is inside the box.
+  float bl0 = r0, bl1 = r1, bl2 = r2, bh0 = r0, bh1 = r1, bh2 = r2;
+  if (NN && tbox) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      bl0 = fminf(bl0, __shfl_xor(bl0, o));
+      bl1 = fminf(bl1, __shfl_xor(bl1, o));
+      bl2 = fminf(bl2, __shfl_xor(bl2, o));
+      bh0 = fmaxf(bh0, __shfl_xor(bh0, o));
+      bh1 = fmaxf(bh1, __shfl_xor(bh1, o));
+      bh2 = fmaxf(bh2, __shfl_xor(bh2, o));
+    }
+    if ((tid & 63) == 0) {
+      float *w = WB[tid >> 6];
+      w[0] = bl0; w[1] = bl1; w[2] = bl2; w[3] = bh0; w[4] = bh1; w[5] = bh2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kThreads / 64; ++k) {
+      bl0 = fminf(bl0, WB[k][0]);
+      bl1 = fminf(bl1, WB[k][1]);
+      bl2 = fminf(bl2, WB[k][2]);
+      bh0 = fmaxf(bh0, WB[k][3]);
+      bh1 = fmaxf(bh1, WB[k][4]);
+      bh2 = fmaxf(bh2, WB[k][5]);
+    }
+  }
   float hx = 0.f, hy = 0.f, hz = 0.f, hv = 0.f, lx = 0.f, ly = 0.f, lz = 0.f, lv = 0.f;
   float best = INFINITY;
   int bidx = -1;
   for (int jt = jb; jt < je; jt += kThreads) {
     const int cnt = min(kThreads, je - jt);
     const float q0 = (float)sq[jt];
+    bool nn_tile = NN;
+    if (NN && tbox) {
+      const double *b = tbox + 6 * (size_t)(jt / kThreads);
+      const float g0 = fmaxf(0.f, fmaxf((float)(b[0] - c0) - bh0, bl0 - (float)(b[3] - c0)));
+      const float g1 = fmaxf(0.f, fmaxf((float)(b[1] - c1) - bh1, bl1 - (float)(b[4] - c1)));
+      const float g2 = fmaxf(0.f, fmaxf((float)(b[2] - c2) - bh2, bl2 - (float)(b[5] - c2)));
+      nn_tile = fmaf(g0, g0, fmaf(g1, g1, g2 * g2)) <= nn_cut2;
+    }
     __syncthreads();
     float qj = q0;
     if (tid < cnt) {
@@ -514,13 +554,21 @@ __global__ __launch_bounds__(kThreads) void k_pair_mixed(int n_t, const double *
     const bool uniform = __syncthreads_and(qj == q0);
     float px = 0.f, py = 0.f, pz = 0.f, pv = 0.f;
     if (uniform) {
-      pair_tile<WANT_V, NN, EXCL, true>(S, K, cnt, jt, r0, r1, r2, soft2, self, want, px, py, pz, pv, best, bidx);
+      if (nn_tile)
+        pair_tile<WANT_V, NN, EXCL, true>(S, K, cnt, jt, r0, r1, r2, soft2, self, want, px, py, pz, pv, best, bidx);
+      else
+        pair_tile<WANT_V, false, EXCL, true>(S, K, cnt, jt, r0, r1, r2, soft2, self, want, px, py, pz, pv, best,
+                                             bidx);
       px *= q0;
       py *= q0;
       pz *= q0;
       pv *= q0;
     } else {
-      pair_tile<WANT_V, NN, EXCL, false>(S, K, cnt, jt, r0, r1, r2, soft2, self, want, px, py, pz, pv, best, bidx);
+      if (nn_tile)
+        pair_tile<WANT_V, NN, EXCL, false>(S, K, cnt, jt, r0, r1, r2, soft2, self, want, px, py, pz, pv, best, bidx);
+      else
+        pair_tile<WANT_V, false, EXCL, false>(S, K, cnt, jt, r0, r1, r2, soft2, self, want, px, py, pz, pv, best,
+                                              bidx);
     }
     neumaier(hx, lx, px);
     neumaier(hy, ly, py);
@@ -644,10 +692,10 @@ template <bool WANT_V, bool NN, int CZ>
 static void launch_pair_t(obem_ctx *ctx, dim3 grid, int n_t, const double *xs, const int32_t *perm, int n_s,
                           const double *sx, const double *sy, const double *sz, const double *sq,
                           const int8_t *sp, const int8_t *sps, double soft, obem_precision prec, int chunk,
-                          double *part, void *nnd, int32_t *nni) {
+                          double *part, void *nnd, int32_t *nni, const double *tbox, float nn_cut2) {
   if (prec == OBEM_MIXED)
     hipLaunchKernelGGL((k_pair_mixed<WANT_V, NN, CZ>), grid, dim3(kThreads), 0, ctx->stream, n_t, xs, perm, n_s,
-                       sx, sy, sz, sq, sp, sps, (float)(soft * soft), chunk, part, (float *)nnd, nni);
+                       sx, sy, sz, sq, sp, sps, (float)(soft * soft), chunk, part, (float *)nnd, nni, tbox, nn_cut2);
   else
     hipLaunchKernelGGL((k_pair_fp64<WANT_V, NN, CZ>), grid, dim3(kThreads), 0, ctx->stream, n_t, xs, perm, n_s,
                        sx, sy, sz, sq, sp, sps, soft * soft, chunk, part, (double *)nnd, nni);
@@ -656,7 +704,7 @@ static void launch_pair_t(obem_ctx *ctx, dim3 grid, int n_t, const double *xs, c
 obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, const double *sy, const double *sz,
                               const double *sq, const TargetOrder &to, double soft, obem_precision prec,
                               bool tgt_is_src, bool want_v, const int8_t *species, const int8_t *species_s,
-                              double *acc, int32_t *nn_idx, double *nn_d2) {
+                              double *acc, int32_t *nn_idx, double *nn_d2, const double *tbox, double nn_cut) {
   const int n_t = to.n;
   const int n_s = (int)n_src;
   if (n_t == 0 || n_s == 0) return OBEM_OK;
@@ -687,12 +735,14 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
   else if (tgt_is_src && want_v)
     excl = 2;
   dim3 grid(bt, nsplit);
+  // cut with a margin for the FP32 box coordinates (a larger cut only costs time)
+  const float nn_cut2 = tbox ? (float)std::pow(nn_cut * (1.0 + 1e-4) + 1e-9, 2) : INFINITY;
   {
   OBEM_PROF(ctx, "pair");
 #define PAIR_CASE(V, N, Z)                                                                                   \
   if (want_v == V && nn == N && excl == Z)                                                                   \
     launch_pair_t<V, N, Z>(ctx, grid, n_t, to.xs, to.perm, n_s, sx, sy, sz, sq, species, species_s, soft, prec, \
-                           chunk, part, nnd, nni);
+                           chunk, part, nnd, nni, tbox, nn_cut2);
   PAIR_CASE(false, false, 0)
   PAIR_CASE(false, false, 1)
   PAIR_CASE(false, false, 2)

@@ -410,18 +410,22 @@ __global__ __launch_bounds__(256) void k_scatter_nn(int n, const int32_t *__rest
   }
 }
 
-__global__ __launch_bounds__(256) void k_species_key(int n, const int8_t *__restrict__ sp, uint8_t *key,
-                                                     int32_t *idx) {
+// Species key of the particles taken in the targets' Morton order.
+__global__ __launch_bounds__(256) void k_species_key(int n, const int32_t *__restrict__ perm,
+                                                     const int8_t *__restrict__ sp, uint8_t *key, int32_t *idx) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < n) {
-    key[i] = sp[i] == 1 ? 1 : 0;
-    idx[i] = i;
+    const int j = perm[i];
+    key[i] = (uint8_t)(sp[j] & 3);
+    idx[i] = j;
   }
 }
 
-// Source copy grouped by charge (electrons and anions, then cations; stable):
-// its 256-source tiles each carry one charge, which the pairwise kernel
-// takes out of the inner loop.
+// Source copy grouped by species, Morton order within a species (a stable
+// sort of the Morton-ordered particles by species): its 256-source tiles
+// each carry one charge, which the pairwise kernel takes out of the inner
+// loop, and are spatially compact, so the nearest-partner search can skip
+// tiles farther than the recombination radius.
 __global__ __launch_bounds__(256) void k_gather_sources(int n, const int32_t *__restrict__ perm,
                                                         const double *__restrict__ x, const double *__restrict__ y,
                                                         const double *__restrict__ z, const int8_t *__restrict__ sp,
@@ -434,6 +438,31 @@ __global__ __launch_bounds__(256) void k_gather_sources(int n, const int32_t *__
   out[2 * (size_t)n + i] = z[j];
   out[3 * (size_t)n + i] = (sp[j] == 1) ? kQe : -kQe;
   sp_out[i] = sp[j];
+}
+
+// Bounding box of each 256-source tile of the source copy (lo xyz, hi xyz).
+__global__ __launch_bounds__(256) void k_tile_boxes(int n, const double *__restrict__ src, double *box) {
+  __shared__ double red[6][4];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int k = min(i, n - 1);
+  double v[6];
+  for (int c = 0; c < 3; ++c) v[c] = v[3 + c] = src[(size_t)c * n + k];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      v[c] = fmin(v[c], __shfl_xor(v[c], o));
+      v[3 + c] = fmax(v[3 + c], __shfl_xor(v[3 + c], o));
+    }
+  if ((threadIdx.x & 63) == 0)
+    for (int c = 0; c < 6; ++c) red[c][threadIdx.x >> 6] = v[c];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int c = threadIdx.x;
+    double r = red[c][0];
+    for (int w = 1; w < 4; ++w) r = c < 3 ? fmin(r, red[c][w]) : fmax(r, red[c][w]);
+    box[6 * (size_t)blockIdx.x + c] = r;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_fill_u64(int n, unsigned long long *p, unsigned long long v) {
@@ -684,29 +713,33 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
   double *srcb = (double *)ws_get(ctx, WS_SRC, sizeof(double) * 4 * nz + nz + 64);
   if (!skey || !sperm || !srcb) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
   int8_t *ssp = (int8_t *)(srcb + 4 * nz);
-  {
-    hipLaunchKernelGGL(k_species_key, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->species, skey, sperm);
-    size_t tb = 0;
-    OBEM_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, tb, skey, skey + nz, sperm, sperm + nz, n, 0, 1,
-                                                     ctx->stream));
-    void *tmp = ws_get(ctx, WS_SORT_TMP2, tb + 256);
-    if (!tmp) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
-    OBEM_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(tmp, tb, skey, skey + nz, sperm, sperm + nz, n, 0, 1,
-                                                     ctx->stream));
-    hipLaunchKernelGGL(k_gather_sources, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, sperm + nz, S->x, S->y, S->z,
-                       S->species, srcb, ssp);
-    OBEM_HIP(ctx, hipGetLastError());
-  }
-  const int32_t *src_perm = sperm + nz;
   TargetOrder to;
   st = order_targets(ctx, n, S->x, S->y, S->z, &to);
   if (st) return st;
+  const int ntile = nbt(n);
+  double *tbox = (double *)ws_get(ctx, WS_TBOX, sizeof(double) * 6 * (size_t)ntile);
+  if (!tbox) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  {
+    hipLaunchKernelGGL(k_species_key, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, to.perm, S->species, skey, sperm);
+    size_t tb = 0;
+    OBEM_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, tb, skey, skey + nz, sperm, sperm + nz, n, 0, 2,
+                                                     ctx->stream));
+    void *tmp = ws_get(ctx, WS_SORT_TMP2, tb + 256);
+    if (!tmp) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+    OBEM_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(tmp, tb, skey, skey + nz, sperm, sperm + nz, n, 0, 2,
+                                                     ctx->stream));
+    hipLaunchKernelGGL(k_gather_sources, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, sperm + nz, S->x, S->y, S->z,
+                       S->species, srcb, ssp);
+    hipLaunchKernelGGL(k_tile_boxes, dim3(ntile), dim3(256), 0, ctx->stream, n, srcb, tbox);
+    OBEM_HIP(ctx, hipGetLastError());
+  }
+  const int32_t *src_perm = sperm + nz;
   double *acc = (double *)ws_get(ctx, WS_ACC, sizeof(double) * 4 * nz);
   if (!acc) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
   st = mesh ? launch_panel_field(ctx, mesh, sigma, to, p->precision, false, acc) : launch_fill(ctx, acc, 4 * nz, 0.0);
   if (st) return st;
   st = launch_pair_field(ctx, n, srcb, srcb + nz, srcb + 2 * nz, srcb + 3 * nz, to, p->soft, p->precision, true,
-                         false, S->species, ssp, acc, nn_s, nnd);
+                         false, S->species, ssp, acc, nn_s, nnd, tbox, p->r_rec);
   if (st) return st;
   st = launch_scatter(ctx, to, acc, kKe, E, E + nz, E + 2 * nz, nullptr);
   if (st) return st;

@@ -127,3 +127,41 @@ def test_track_step_capacity_overflow(ctx):
     assert parts.n_live <= n0 + 4
     ids = host(parts.state()["id"])
     assert np.all(np.diff(ids) > 0)
+
+
+@pytest.mark.parametrize("prec", [B.OBEM_FP64, B.OBEM_MIXED])
+def test_recombination_of_planted_pairs(ctx, orc, prec):
+    """Electron-cation pairs 0.2-0.9 um apart on a 10 um lattice (many source
+    tiles, so the mixed kernel's tile-limited partner search is exercised),
+    plus lone particles: exactly the planted pairs recombine (eq.
+    (distRecomb)), as in the oracle's recombination on the same state."""
+    rng = np.random.default_rng(31)
+    g = np.stack(np.meshgrid(*[np.arange(18) * 10e-6] * 3, indexing="ij"), -1).reshape(-1, 3)
+    g = g[rng.permutation(len(g))]
+    n_pair, n_lone = 3000, len(g) - 3000
+    d = rng.normal(size=(n_pair, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    xe = g[:n_pair]
+    xc = xe + d * rng.uniform(0.2e-6, 0.9e-6, size=(n_pair, 1))
+    xl = g[n_pair:]
+    spl = rng.integers(0, 2, size=n_lone).astype(np.int8)
+    x = np.concatenate([xe, xc, xl])
+    sp = np.concatenate([np.zeros(n_pair, np.int8), np.ones(n_pair, np.int8), spl])
+    perm = rng.permutation(len(sp))
+    x, sp = x[perm], sp[perm]
+    n = len(sp)
+    q = np.where(sp == 1, W.E_CHARGE, -W.E_CHARGE)
+    _, nn, d2 = orc.pair_field(x, x, q, 1e-7, tgt_is_src=True, sp_t=sp, sp_s=sp)
+    dead = orc.recombine(sp, np.arange(n), nn, d2, 1e-6)
+    assert dead.sum() == 2 * n_pair
+    gas = W.synthetic_ar_co2()
+    gas_s, keep = B.gas_struct(gas, "cuda")
+    parts = B.Particles(n + 1000, "cuda", dev(x), dev(np.zeros((n, 3))), dev(sp, torch.int8),
+                        dev(np.arange(n), torch.int64), n)
+    p = dict(dt=1e-16, step=0, seed=5, max_coll=64, max_ion_per_step=4, ion_v_cap=2e4,
+             box_lo=(-1e-3, -1e-3, -1e-3), box_hi=(1e-3, 1e-3, 1e-3), soft=1e-7, r_rec=1e-6, precision=prec)
+    sg = B.track_step(ctx, None, parts, gas_s, p, None, None)
+    print("planted pairs", prec, sg["recombined"], "of", 2 * n_pair)
+    assert sg["recombined"] == 2 * n_pair
+    ids = host(parts.state()["id"])
+    assert np.array_equal(np.sort(ids), np.sort(np.arange(n)[~dead]))
