@@ -61,7 +61,7 @@ def kernel_source_hash():
 def traffic_from_profiles():
     """HBM bytes per launch of the pairwise kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "pair_mixed_cloud4M_traffic.json")
+    p = os.path.join(ROOT, "profiles", "pair_mixed_nn_cloud4M_traffic.json")
     try:
         with open(p) as fh:
             d = json.load(fh)
@@ -80,8 +80,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true",
-                    help="run one plain 1 GiB device copy and one pairwise launch on the 4M-charge cloud "
-                         "(for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs), print the sizes and exit")
+                    help="run one plain 1 GiB device copy and one tracking step of the 4M-charge cloud without "
+                         "cells (the same pairwise kernel as the timed step; for rocprofv3 --pmc FETCH_SIZE / "
+                         "WRITE_SIZE runs), print the sizes and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path shards by targets across "
@@ -115,8 +116,12 @@ def main():
         b.copy_(a)                                     # reads and writes 1 GiB each
         torch.cuda.synchronize()
         x, q, sp = W.space_charge_cloud()
-        X, Q = dev(x), dev(q)
-        B.field_eval(ctx, None, None, X, Q, X, 1e-7, B.OBEM_MIXED, tgt_is_src=True)
+        gas_s, gas_keep = B.gas_struct(W.synthetic_ar_co2(), "cuda")
+        parts = B.Particles(len(q) + len(q) // 4, "cuda", dev(x), dev(np.zeros_like(x)), dev(sp, torch.int8),
+                            torch.arange(len(q), dtype=torch.int64, device="cuda"), len(q))
+        B.track_step(ctx, None, parts, gas_s, dict(dt=1e-12, step=1, seed=5, max_coll=64, max_ion_per_step=4,
+                                                   ion_v_cap=2e4, box_lo=(-1.0, -1.0, -1.0), box_hi=(1.0, 1.0, 1.0),
+                                                   soft=1e-7, r_rec=1e-6, precision=B.OBEM_MIXED), None, None)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "n_charges": len(q),
                           "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
@@ -232,7 +237,6 @@ def main():
         "last_step": {k: (list(v) if k == "real_collisions" else v) for k, v in last.items()},
     }
     E = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3)]
-    B.field_eval(ctx, bm, sigma, X, Q, X, 1e-7, B.OBEM_MIXED, tgt_is_src=True, out=E)
 
     # ------------------------------------------------------------ cpu baseline
     if not args.no_cpu_baseline:
@@ -243,6 +247,7 @@ def main():
         it = rng.choice(n, 384, replace=False)
         ic = it[:192]
         sig_h = sigma.cpu().numpy()
+        B.field_eval(ctx, bm, sigma, X, Q, X, 1e-7, B.OBEM_MIXED, tgt_is_src=True, out=E)
         t0 = time.time()
         Ep = oracle.pair_field(x[it], x, q, 1e-7)        # own term: zero field at zero distance
         tp = time.time() - t0
