@@ -447,3 +447,54 @@ def influence(mesh, rhs, x, q):
                        _p(np.ascontiguousarray(mesh.kind, np.int8)), _p(_f64(mesh.eps1)), _p(_f64(mesh.eps2)),
                        _p(_f64(rhs)), C.c_int64(x.shape[0]), _p(x), _p(_f64(q)), _p(out), _p(vb), _p(eb))
     return out, vb, eb
+
+
+# --------------------------------------------------------------------------
+# Static field option (section 3.3.1): field of the cells on a uniform 3D
+# grid, computed once, and trilinear interpolation at the particles.
+# --------------------------------------------------------------------------
+def field_map(mesh, sigma, lo, h, n):
+    """Cell field (eq. (BEM3)) at the nodes lo + (i, j, k) h of a uniform grid
+    with n = (nx, ny, nz) nodes; returns E with shape (nz, ny, nx, 3)."""
+    nx, ny, nz = (int(v) for v in n)
+    gx = lo[0] + h[0] * np.arange(nx)
+    gy = lo[1] + h[1] * np.arange(ny)
+    gz = lo[2] + h[2] * np.arange(nz)
+    Z, Y, X = np.meshgrid(gz, gy, gx, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+    E = panel_field(pts, mesh.a, mesh.b, mesh.c, sigma)
+    return E.reshape(nz, ny, nx, 3)
+
+
+def trilinear(Emap, lo, h, x):
+    """Trilinear interpolation of the node values Emap (nz, ny, nx, 3) at the
+    points x (n, 3).  Reading: the paper leaves points outside the grid open;
+    they are clamped onto the grid box (the field of the nearest boundary
+    point)."""
+    x = _f64(x).reshape(-1, 3)
+    nz, ny, nx = Emap.shape[:3]
+    size = np.array([nx, ny, nz])
+    u = (x - np.asarray(lo, np.float64)) / np.asarray(h, np.float64)
+    u = np.clip(u, 0.0, size - 1.0)
+    i0 = np.minimum(np.floor(u).astype(np.int64), size - 2)
+    f = u - i0
+    out = np.zeros((x.shape[0], 3))
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                w = ((f[:, 0] if dx else 1 - f[:, 0]) * (f[:, 1] if dy else 1 - f[:, 1]) *
+                     (f[:, 2] if dz else 1 - f[:, 2]))
+                out += w[:, None] * Emap[i0[:, 2] + dz, i0[:, 1] + dy, i0[:, 0] + dx]
+    return out
+
+
+# --------------------------------------------------------------------------
+# Signal induction (section 3.5, eq. (ramo))
+# --------------------------------------------------------------------------
+def induced_current(Ew, v, q, species):
+    """Shockley-Ramo current i = sum_p q_p v_p . E_w(x_p) split by species
+    (electrons, cations, anions), given the weighting field Ew (n, 3) at the
+    particles.  Returns (currents[3], per-particle terms)."""
+    terms = q * np.einsum("ij,ij->i", _f64(v).reshape(-1, 3), _f64(Ew).reshape(-1, 3))
+    cur = np.array([terms[species == s].sum() for s in (0, 1, 2)])
+    return cur, terms
