@@ -244,7 +244,8 @@ class _Gas(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("e_min", C.c_double), ("e_max", C.c_double),
                 ("xs", C.c_void_p), ("thr", C.c_double * 5), ("density", C.c_double),
                 ("temperature", C.c_double), ("m_gas", C.c_double), ("m_cation", C.c_double),
-                ("m_anion", C.c_double), ("ion_xs_iso", C.c_double), ("ion_xs_back", C.c_double)]
+                ("m_anion", C.c_double), ("ion_xs_iso", C.c_double), ("ion_xs_back", C.c_double),
+                ("xi", C.c_void_p), ("penning_prob", C.c_double), ("penning_level", C.c_double)]
 
 
 class _Step(C.Structure):
@@ -255,12 +256,15 @@ class _Step(C.Structure):
 
 def _gas_struct(gas):
     xs = np.ascontiguousarray(gas.xs, np.float64)
+    xi = None if getattr(gas, "xi", None) is None else np.ascontiguousarray(gas.xi, np.float64)
     g = _Gas(n_nodes=xs.shape[1], e_min=gas.e_min, e_max=gas.e_max, xs=xs.ctypes.data,
              density=gas.density, temperature=gas.temperature, m_gas=gas.m_gas, m_cation=gas.m_cation,
-             m_anion=gas.m_anion, ion_xs_iso=gas.ion_xs_iso, ion_xs_back=gas.ion_xs_back)
+             m_anion=gas.m_anion, ion_xs_iso=gas.ion_xs_iso, ion_xs_back=gas.ion_xs_back,
+             xi=None if xi is None else xi.ctypes.data, penning_prob=float(getattr(gas, "penning_prob", 0.0)),
+             penning_level=float(getattr(gas, "penning_level", 0.0)))
     for k in range(5):
         g.thr[k] = float(gas.thresholds[k])
-    return g, xs
+    return g, (xs, xi)
 
 
 def nu_max_electron(gas):
@@ -278,7 +282,7 @@ def xs_at(gas, k, eps):
 
 
 COUNTER_NAMES = ["elastic", "exc1", "exc2", "ionisation", "attachment", "null", "ion_collisions",
-                 "rate_overflow", "flight_cap", "children_dropped"]
+                 "rate_overflow", "flight_cap", "children_dropped", "penning"]
 
 
 def mc_step(x, v, species, ids, E, gas, params, mesh=None, skip=None):
@@ -298,7 +302,7 @@ def mc_step(x, v, species, ids, E, gas, params, mesh=None, skip=None):
     n_child = np.zeros(n, np.int32)
     child_x = np.zeros((max(n, 1) * mi * 2, 3))
     child_v = np.zeros((max(n, 1) * mi * 2, 3))
-    counters = np.zeros(10, np.int64)
+    counters = np.zeros(len(COUNTER_NAMES), np.int64)
     if mesh is not None:
         a, b, c = _f64(mesh.a), _f64(mesh.b), _f64(mesh.c)
         N = mesh.n
@@ -310,6 +314,59 @@ def mc_step(x, v, species, ids, E, gas, params, mesh=None, skip=None):
                      C.byref(p), C.c_int64(N), _p(a), _p(b), _p(c), _p(status), _p(hit), _p(n_child),
                      _p(child_x), _p(child_v), _p(counters))
     return status, hit, n_child, child_x.reshape(max(n, 1), mi, 2, 3), child_v.reshape(max(n, 1), mi, 2, 3), counters
+
+
+def _step_struct(params):
+    p = _Step(dt=params["dt"], step=params["step"], seed=params["seed"], max_coll=params["max_coll"],
+              max_ion_per_step=int(params["max_ion_per_step"]), ion_v_cap=params["ion_v_cap"])
+    for k in range(3):
+        p.box_lo[k] = params["box_lo"][k]
+        p.box_hi[k] = params["box_hi"][k]
+    return p
+
+
+def _mesh_arrays(mesh):
+    if mesh is not None:
+        return _f64(mesh.a), _f64(mesh.b), _f64(mesh.c), mesh.n
+    z = np.zeros((1, 3))
+    return z, z, z, 0
+
+
+def aniso_cos(xi, R):
+    """cos theta of eq. (anisotrop) for anisotropy xi and uniform R."""
+    lib().oc_aniso_cos.restype = C.c_double
+    return lib().oc_aniso_cos(C.c_double(xi), C.c_double(R))
+
+
+def flight(x, v, species, E, gas, params, tau, status, hit, mesh=None, skip=None):
+    """Flight of duration tau (constant acceleration qE/m, E None = straight
+    drift) for live particles, with absorption and world-box tests; x, v,
+    status, hit updated in place (section 3.3.5 steppers)."""
+    n = x.shape[0]
+    g, keep = _gas_struct(gas)
+    p = _step_struct(params)
+    a, b, c, N = _mesh_arrays(mesh)
+    sk = None if skip is None else np.ascontiguousarray(skip, np.uint8)
+    Ep = None if E is None else _f64(E)
+    lib().oc_flight(C.c_int64(n), _p(x), _p(v), _p(species), _p(Ep), _p(sk), C.byref(g), C.byref(p),
+                    C.c_double(tau), C.c_int64(N), _p(a), _p(b), _p(c), _p(status), _p(hit))
+
+
+def collide_step(x, v, species, ids, gas, params, status, skip=None):
+    """Per-step collision test of section 3.4.2 for live particles (in place);
+    returns (n_child, child_x, child_v, counters)."""
+    n = x.shape[0]
+    mi = int(params["max_ion_per_step"])
+    g, keep = _gas_struct(gas)
+    p = _step_struct(params)
+    n_child = np.zeros(n, np.int32)
+    child_x = np.zeros((max(n, 1) * mi * 2, 3))
+    child_v = np.zeros((max(n, 1) * mi * 2, 3))
+    counters = np.zeros(len(COUNTER_NAMES), np.int64)
+    sk = None if skip is None else np.ascontiguousarray(skip, np.uint8)
+    lib().oc_collide_step(C.c_int64(n), _p(x), _p(v), _p(species), _p(ids), _p(sk), C.byref(g), C.byref(p),
+                          _p(status), _p(n_child), _p(child_x), _p(child_v), _p(counters))
+    return n_child, child_x.reshape(max(n, 1), mi, 2, 3), child_v.reshape(max(n, 1), mi, 2, 3), counters
 
 
 def recombine(species, ids, nn_idx, nn_d2, r_rec):
@@ -333,13 +390,23 @@ def recombine(species, ids, nn_idx, nn_d2, r_rec):
 
 
 def track_step(state, mesh, sigma, gas, params, dd_counts, rhs0=None, area=None, A=None, resolve=False,
-               with_influence=False):
+               with_influence=False, field_map=None):
     """One tracking step, in the order: (re-)solve for sigma if charge was
     deposited (eq. (charge-up)), with with_influence after moving the
     particles' influence onto the left-hand side (section 3.3.2), field at the
     start positions (panels + pairwise), recombination, constant-field
     flights with null-collision MC and absorption, compaction with appended
-    children, charging-up counts.
+    children, charging-up counts.  field_map = (Emap, lo, h): the static
+    option (section 3.3.1), the field of the set-up interpolated in the map
+    instead of summed over the cells.
+
+    params["stepper"] selects the transport (section 3.3.5 and 3.4.2): 0 =
+    constant-field flights with null collisions (above); 1 = Euler (one
+    constant-field flight over dt in the start field) and 2 = PEFRL (4 force
+    evaluations at the intermediate positions, field of the set-up plus the
+    charges still alive, at those positions), both followed by the per-step
+    collision test.  The start-of-step field evaluation gives the
+    recombination partners in every mode.
 
     state: dict with x (n,3), v (n,3), species (n,) int8, id (n,) int64,
     next_id int.  Returns (new_state, sigma, stats)."""
@@ -360,12 +427,25 @@ def track_step(state, mesh, sigma, gas, params, dd_counts, rhs0=None, area=None,
     stats = {}
     if n:
         E_pair, nn, d2 = pair_field(x, x, q, params["soft"], tgt_is_src=True, sp_t=sp, sp_s=sp)
-        E = E_pair + (panel_field(x, mesh.a, mesh.b, mesh.c, sigma) if mesh is not None else 0.0)
+        if field_map is not None:
+            E = E_pair + trilinear(field_map[0], field_map[1], field_map[2], x)
+        else:
+            E = E_pair + (panel_field(x, mesh.a, mesh.b, mesh.c, sigma) if mesh is not None else 0.0)
         dead = recombine(sp, ids, nn, d2, params["r_rec"])
     else:
         E = np.zeros((0, 3))
         dead = np.zeros(0, bool)
-    status, hit, n_child, cx, cv, counters = mc_step(x, v, sp, ids, E, gas, params, mesh, skip=dead)
+    stepper = int(params.get("stepper", 0))
+    if stepper == 0:
+        status, hit, n_child, cx, cv, counters = mc_step(x, v, sp, ids, E, gas, params, mesh, skip=dead)
+    else:
+        status = np.zeros(n, np.int8)
+        hit = np.full(n, -1, np.int64)
+        if stepper == 1:
+            flight(x, v, sp, E, gas, params, params["dt"], status, hit, mesh, skip=dead)
+        else:
+            _pefrl(x, v, sp, q, dead, status, hit, gas, params, mesh, sigma, field_map)
+        n_child, cx, cv, counters = collide_step(x, v, sp, ids, gas, params, status, skip=dead)
     stats["recombined"] = int(dead.sum())
     stats["absorbed"] = int((status == 1).sum())
     stats["left"] = int((status == 2).sum())
@@ -404,6 +484,37 @@ def track_step(state, mesh, sigma, gas, params, dd_counts, rhs0=None, area=None,
     stats["n_live"] = new_state["x"].shape[0]
     stats["children"] = take
     return new_state, sigma, new_counts, stats, E
+
+
+# Position-extended Forest-Ruth-like integrator (Omelyan, Mryglod, Folk,
+# Comput. Phys. Commun. 146 (2002) 188), the PEFRL of section 3.3.5.
+PEFRL_XI = 0.1786178958448091
+PEFRL_LAMBDA = -0.2123418310626054
+PEFRL_CHI = -0.06626458266981849
+
+
+def _pefrl(x, v, sp, q, dead, status, hit, gas, params, mesh, sigma, field_map):
+    """One PEFRL step in place: drifts (straight, absorption and box tested)
+    and kicks q E(x) / m with E re-evaluated after each drift from the set-up
+    (cells or map) and the charges not yet removed, at their current
+    positions."""
+    dt = params["dt"]
+    masses = np.array([constants()["m_e"], gas.m_cation, gas.m_anion])
+    drifts = [PEFRL_XI, PEFRL_CHI, 1.0 - 2.0 * (PEFRL_CHI + PEFRL_XI), PEFRL_CHI, PEFRL_XI]
+    kicks = [0.5 * (1.0 - 2.0 * PEFRL_LAMBDA), PEFRL_LAMBDA, PEFRL_LAMBDA, 0.5 * (1.0 - 2.0 * PEFRL_LAMBDA)]
+    for s_, cd in enumerate(drifts):
+        flight(x, v, sp, None, gas, params, cd * dt, status, hit, mesh, skip=dead)
+        if s_ == len(kicks):
+            break
+        live = (~dead) & (status == 0)
+        qm = np.where(live, q, 0.0)
+        E = pair_field(x, x, qm, params["soft"], tgt_is_src=True)
+        if field_map is not None:
+            E = E + trilinear(field_map[0], field_map[1], field_map[2], x)
+        elif mesh is not None:
+            E = E + panel_field(x, mesh.a, mesh.b, mesh.c, sigma)
+        acc = (q / masses[sp])[:, None] * E
+        v[live] += kicks[s_] * dt * acc[live]
 
 
 def fd_particle(x, q, w, soft, mesh, sigma, m, axis, h):

@@ -482,6 +482,9 @@ typedef struct {
   const double *xs;        /* [5][n_nodes] m^2 */
   double thr[5];           /* eV */
   double density, temperature, m_gas, m_cation, m_anion, ion_xs_iso, ion_xs_back;
+  const double *xi;        /* [n_nodes] anisotropy xi(E) of eq. (anisotrop), or NULL (isotropic) */
+  double penning_prob;     /* Penning transfer probability (section 3.4.4), 0 = off */
+  double penning_level;    /* ionisation potential of the quenching species, eV */
 } oc_gas;
 
 typedef struct {
@@ -559,32 +562,198 @@ static void isotropic(double u2, double u3, double *d) {
   d[0] = st * cos(ph); d[1] = st * sin(ph); d[2] = ct;
 }
 
+/* Table value at eps (eV), linear in the normalised lethargy of eq. (leth)
+ * between log-spaced nodes, clamped to the end nodes (as xs_at). */
+static double table_at(const oc_gas *g, const double *tab, double eps) {
+  int n = g->n_nodes;
+  if (!(eps > g->e_min)) return tab[0];
+  if (eps >= g->e_max) return tab[n - 1];
+  double p = (double)(n - 1) * (log(eps / g->e_min) / log(g->e_max / g->e_min));
+  int i = (int)floor(p);
+  if (i >= n - 1) i = n - 2;
+  double fr = p - (double)i;
+  return tab[i] * (1.0 - fr) + tab[i + 1] * fr;
+}
+
+/* Scattering angle of eq. (anisotrop) for a uniform R in [0, 1):
+ * cos theta = 1 - 2R(1 - xi)/(1 + xi(1 - 2R)). */
+double oc_aniso_cos(double xi, double R) { return 1.0 - 2.0 * R * (1.0 - xi) / (1.0 + xi * (1.0 - 2.0 * R)); }
+
+/* Unit vector at polar angle theta (cos ct) and azimuth 2 pi u about the unit
+ * vector d: basis e1 = (a x d)/|a x d| with a the z axis (x axis when d is
+ * within 25.8 degrees of z), e2 = d x e1. */
+static void rotate_about(const double *d, double ct, double u, double *out) {
+  double a[3] = {0.0, 0.0, 1.0};
+  if (fabs(d[2]) >= 0.9) { a[0] = 1.0; a[2] = 0.0; }
+  double e1[3] = {a[1] * d[2] - a[2] * d[1], a[2] * d[0] - a[0] * d[2], a[0] * d[1] - a[1] * d[0]};
+  double l = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+  for (int k = 0; k < 3; ++k) e1[k] /= l;
+  double e2[3] = {d[1] * e1[2] - d[2] * e1[1], d[2] * e1[0] - d[0] * e1[2], d[0] * e1[1] - d[1] * e1[0]};
+  double st = sqrt(fmax(0.0, 1.0 - ct * ct)), ph = 2.0 * M_PI * u;
+  double cp = cos(ph), sp = sin(ph);
+  for (int k = 0; k < 3; ++k) out[k] = ct * d[k] + st * (cp * e1[k] + sp * e2[k]);
+}
+
+/* Children of one particle and step: pairs (electron, cation) in slots
+ * [(i*mi + c)*2 + {0, 1}]. */
+typedef struct {
+  int64_t i;
+  int mi;
+  int32_t *n_child;
+  double *child_x, *child_v;
+} oc_kids;
+
+static int add_pair(oc_kids *K, const double *xe, const double *ve, const double *xc, const double *vc) {
+  int nc = K->n_child[K->i];
+  if (nc >= K->mi) return 0;
+  double *ce = K->child_x + ((K->i * K->mi + nc) * 2 + 0) * 3, *cv = K->child_v + ((K->i * K->mi + nc) * 2 + 0) * 3;
+  double *ix = K->child_x + ((K->i * K->mi + nc) * 2 + 1) * 3, *iv = K->child_v + ((K->i * K->mi + nc) * 2 + 1) * 3;
+  for (int d = 0; d < 3; ++d) { ce[d] = xe[d]; cv[d] = ve[d]; ix[d] = xc[d]; iv[d] = vc[d]; }
+  K->n_child[K->i] = nc + 1;
+  return 1;
+}
+
+/* Counter slots (shared by both collision models). */
+enum { CN_EL = 0, CN_NULL = 5, CN_ION = 6, CN_OVF = 7, CN_CAP = 8, CN_DROP = 9, CN_PEN = 10, CN_COUNT = 11 };
+
+/* Real interaction `proc` (elastic, exc1, exc2, ionisation, attachment) of an
+ * electron of energy eps (eV) at X with velocity V (section 3.4.3).  u2, u3:
+ * the collision's own uniforms; c4 (counter word 3 free) and key give the
+ * extra draws: word 3 = 2k + 1 for the ionisation / Penning words, 0x80000000
+ * | k for the Penning cation.  Returns 1 when the electron became an anion. */
+static int electron_interaction(const oc_gas *g, int proc, double eps, double *X, double *Vv, double u2, double u3,
+                                uint32_t *c4, const uint32_t *key, uint32_t k, oc_kids *K, int64_t *cnt) {
+  const double qe = (double)QE, me = (double)ME, ke = (double)k_e();
+  const double e_therm = 1.5 * (double)KB * g->temperature; /* J */
+  double v2 = Vv[0] * Vv[0] + Vv[1] * Vv[1] + Vv[2] * Vv[2];
+  double vm = sqrt(v2);
+  double dir[3];
+  if (proc == 0) { /* elastic, recoil loss 2 m_e/M (1 - cos theta) */
+    double ct;
+    if (g->xi && vm > 0) { /* eq. (anisotrop) about the incident direction */
+      double xi = table_at(g, g->xi, eps);
+      ct = oc_aniso_cos(xi, u2);
+      double d0[3] = {Vv[0] / vm, Vv[1] / vm, Vv[2] / vm};
+      rotate_about(d0, ct, u3, dir);
+    } else {
+      isotropic(u2, u3, dir);
+      ct = (vm > 0) ? (dir[0] * Vv[0] + dir[1] * Vv[1] + dir[2] * Vv[2]) / vm : 1.0;
+    }
+    double e2 = eps * (1.0 - 2.0 * me / g->m_gas * (1.0 - ct));
+    double s = sqrt(2.0 * e2 * qe / me);
+    for (int d = 0; d < 3; ++d) Vv[d] = s * dir[d];
+    return 0;
+  }
+  if (proc == 1 || proc == 2 || proc == 3) {
+    double e_res = (proc == 3) ? eps - g->thr[3] - e_therm / qe : -1.0;
+    if (proc != 3 || e_res <= 0.0) { /* excitation (or sub-threshold ionisation) */
+      double e2 = eps - g->thr[proc];
+      if (e2 < 0) e2 = 0;
+      isotropic(u2, u3, dir);
+      double s = sqrt(2.0 * e2 * qe / me);
+      for (int d = 0; d < 3; ++d) Vv[d] = s * dir[d];
+      if (proc != 3 && g->penning_prob > 0.0 && g->thr[proc] >= g->penning_level) {
+        /* Penning transfer (section 3.4.4): the excited state ionises the
+         * quencher with probability penning_prob; the released electron
+         * takes the excess energy thr - penning_level, the cation a thermal
+         * speed, both isotropic, at the collision point */
+        uint32_t w2[4], w3[4];
+        c4[3] = 2u * k + 1u;
+        oc_philox4x32_10(c4, key, w2);
+        if (u01(w2[0]) < g->penning_prob) {
+          c4[3] = 0x80000000u | k;
+          oc_philox4x32_10(c4, key, w3);
+          double de[3], dc[3], ve[3], vc[3];
+          isotropic(u01(w2[1]), u01(w2[2]), de);
+          isotropic(u01(w3[0]), u01(w3[1]), dc);
+          double se = sqrt(2.0 * (g->thr[proc] - g->penning_level) * qe / me);
+          double si = sqrt(2.0 * e_therm / g->m_cation);
+          for (int d = 0; d < 3; ++d) { ve[d] = se * de[d]; vc[d] = si * dc[d]; }
+          cnt[CN_PEN] += 1;
+          if (!add_pair(K, X, ve, X, vc)) cnt[CN_DROP] += 2;
+        }
+      }
+      return 0;
+    }
+    /* ionisation, eq. (distIoni) */
+    uint32_t w2[4];
+    c4[3] = 2u * k + 1u;
+    oc_philox4x32_10(c4, key, w2);
+    double uh[3], ud[3];
+    isotropic(u01(w2[0]), u01(w2[1]), uh);
+    isotropic(u01(w2[2]), u01(w2[3]), ud);
+    double eres_j = e_res * qe;
+    /* eq. (distIoni) with the energy in eV (volts): r = k_e e / (2 E_res[eV]),
+     * i.e. the separation at which the pair's Coulomb energy k_e e^2 / r is
+     * 2 E_res (the same convention gives 4.59e-11 m for eq. (distRecomb)
+     * at 15.7 eV). */
+    double r = ke * qe * qe / (2.0 * eres_j);
+    double s = sqrt(2.0 * (0.5 * eres_j) / me);
+    double si = sqrt(2.0 * e_therm / g->m_cation);
+    double xe[3], ve[3], vc[3];
+    for (int d = 0; d < 3; ++d) { xe[d] = X[d] - r * uh[d]; ve[d] = -s * uh[d]; vc[d] = si * ud[d]; }
+    if (!add_pair(K, xe, ve, X, vc)) cnt[CN_DROP] += 2;
+    for (int d = 0; d < 3; ++d) { X[d] += r * uh[d]; Vv[d] = s * uh[d]; }
+    return 0;
+  }
+  /* attachment: anion, momentum conserved with the gas at rest */
+  for (int d = 0; d < 3; ++d) Vv[d] *= me / g->m_anion;
+  return 1;
+}
+
+/* Ion collision: 0 = isotropic in the centre of mass (gas at rest), 1 =
+ * backscatter (charge exchange: the ion takes a thermal gas velocity). */
+static void ion_interaction(const oc_gas *g, int sp, int proc, double *Vv, double u2, double u3, uint32_t *c4,
+                            const uint32_t *key, uint32_t k) {
+  double vm = sqrt(Vv[0] * Vv[0] + Vv[1] * Vv[1] + Vv[2] * Vv[2]);
+  if (proc == 0) {
+    double mion = (sp == 1) ? g->m_cation : g->m_anion;
+    double fm = mion / (mion + g->m_gas), fM = g->m_gas / (mion + g->m_gas);
+    double dir[3];
+    isotropic(u2, u3, dir);
+    for (int d = 0; d < 3; ++d) Vv[d] = fm * Vv[d] + fM * vm * dir[d];
+  } else {
+    uint32_t w2[4];
+    c4[3] = 2u * k + 1u;
+    oc_philox4x32_10(c4, key, w2);
+    double sd = sqrt((double)KB * g->temperature / g->m_gas);
+    double r1 = sqrt(-2.0 * log(u01(w2[0]))), r2 = sqrt(-2.0 * log(u01(w2[2])));
+    Vv[0] = sd * r1 * cos(2.0 * M_PI * u01(w2[1]));
+    Vv[1] = sd * r1 * sin(2.0 * M_PI * u01(w2[1]));
+    Vv[2] = sd * r2 * cos(2.0 * M_PI * u01(w2[3]));
+  }
+}
+
+static int outside_box(const oc_step *p, const double *X) {
+  return X[0] < p->box_lo[0] || X[0] > p->box_hi[0] || X[1] < p->box_lo[1] || X[1] > p->box_hi[1] ||
+         X[2] < p->box_lo[2] || X[2] > p->box_hi[2];
+}
+
 /* Outputs per particle i (arrays of n): new state in place (x, v), species in
  * place, status (OC_*), hit cell (or -1), event counters, and up to
  * max_ion_per_step child pairs: child_x/child_v [(i*max_ion + c)*2 + {0 e-, 1
- * cation}][3], n_child[i].  counters: [0] real collisions by process 0..4 for
- * electrons (5 slots), [5] null, [6] ion collisions, [7] rate overflows,
- * [8] flight cap reached, [9] children dropped.  */
+ * cation}][3], n_child[i].  counters (CN_*): real collisions by electron
+ * process (5 slots), null, ion collisions, rate overflows, flight cap
+ * reached, children dropped, Penning transfers.  */
 void oc_mc_step(int64_t n, double *x, double *v, int8_t *species, const int64_t *id, const double *E,
                 const uint8_t *skip, const oc_gas *g, const oc_step *p, int64_t N, const double *a,
                 const double *b, const double *c, int8_t *status, int64_t *hit, int32_t *n_child,
                 double *child_x, double *child_v, int64_t *counters) {
   tri_t *T = (tri_t *)malloc(sizeof(tri_t) * (size_t)(N > 0 ? N : 1));
   for (int64_t k = 0; k < N; ++k) tri_setup(a + 3 * k, b + 3 * k, c + 3 * k, &T[k]);
-  const double qe = (double)QE, me = (double)ME, ke = (double)k_e();
+  const double qe = (double)QE, me = (double)ME;
   double nu_e = oc_nu_max_electron(g);
   double nu_i = g->density * (g->ion_xs_iso + g->ion_xs_back) * p->ion_v_cap;
-  double e_therm = 1.5 * (double)KB * g->temperature; /* J */
-  int64_t cnt[10] = {0};
-  int mi = p->max_ion_per_step;
+  int64_t cnt[CN_COUNT] = {0};
   uint32_t key[2] = {(uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32)};
 
-#pragma omp parallel for schedule(dynamic, 64) reduction(+ : cnt[:10])
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : cnt[:CN_COUNT])
   for (int64_t i = 0; i < n; ++i) {
     status[i] = OC_ALIVE;
     hit[i] = -1;
     n_child[i] = 0;
     if (skip && skip[i]) continue;
+    oc_kids K = {i, p->max_ion_per_step, n_child, child_x, child_v};
     double X[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
     double Vv[3] = {v[3 * i], v[3 * i + 1], v[3 * i + 2]};
     int sp = species[i];
@@ -600,7 +769,7 @@ void oc_mc_step(int64_t n, double *x, double *v, int8_t *species, const int64_t 
       uint32_t w[4];
       int last = 0;
       if (ballistic || k >= p->max_coll || numax <= 0) {
-        if (!ballistic && numax > 0 && k >= p->max_coll) cnt[8] += 1;
+        if (!ballistic && numax > 0 && k >= p->max_coll) cnt[CN_CAP] += 1;
         tau = p->dt - t;
         last = 1;
       } else {
@@ -619,11 +788,7 @@ void oc_mc_step(int64_t n, double *x, double *v, int8_t *species, const int64_t 
       int64_t h = (N > 0) ? first_hit(N, T, X, X1, &th) : -1;
       if (h >= 0) { status[i] = OC_ABSORBED; hit[i] = h; break; }
       for (int d = 0; d < 3; ++d) { X[d] = X1[d]; Vv[d] = V1[d]; }
-      if (X[0] < p->box_lo[0] || X[0] > p->box_hi[0] || X[1] < p->box_lo[1] || X[1] > p->box_hi[1] ||
-          X[2] < p->box_lo[2] || X[2] > p->box_hi[2]) {
-        status[i] = OC_LEFT;
-        break;
-      }
+      if (outside_box(p, X)) { status[i] = OC_LEFT; break; }
       if (last) break;
       t += tau;
       double v2 = Vv[0] * Vv[0] + Vv[1] * Vv[1] + Vv[2] * Vv[2];
@@ -634,87 +799,26 @@ void oc_mc_step(int64_t n, double *x, double *v, int8_t *species, const int64_t 
         double nuk[5], tot = 0;
         for (int kk = 0; kk < 5; ++kk) { nuk[kk] = g->density * xs_at(g, kk, eps) * vm; tot += nuk[kk]; }
         double lim = numax;
-        if (tot > numax) { cnt[7] += 1; lim = tot; }
+        if (tot > numax) { cnt[CN_OVF] += 1; lim = tot; }
         double sel = u1 * lim, cum = 0;
         int proc = -1;
         for (int kk = 0; kk < 5; ++kk) { cum += nuk[kk]; if (sel < cum) { proc = kk; break; } }
-        if (proc < 0) { cnt[5] += 1; continue; }
-        cnt[proc] += 1;
-        double dir[3];
-        if (proc == 0) { /* elastic: isotropic, recoil loss 2 m_e/M (1 - cos theta) */
-          isotropic(u2, u3, dir);
-          double ct = (vm > 0) ? (dir[0] * Vv[0] + dir[1] * Vv[1] + dir[2] * Vv[2]) / vm : 1.0;
-          double e2 = eps * (1.0 - 2.0 * me / g->m_gas * (1.0 - ct));
-          double s = sqrt(2.0 * e2 * qe / me);
-          for (int d = 0; d < 3; ++d) Vv[d] = s * dir[d];
-        } else if (proc == 1 || proc == 2 || proc == 3) {
-          double e_res = (proc == 3) ? eps - g->thr[3] - e_therm / qe : -1.0;
-          if (proc != 3 || e_res <= 0.0) { /* excitation (or sub-threshold ionisation) */
-            double e2 = eps - g->thr[proc];
-            if (e2 < 0) e2 = 0;
-            isotropic(u2, u3, dir);
-            double s = sqrt(2.0 * e2 * qe / me);
-            for (int d = 0; d < 3; ++d) Vv[d] = s * dir[d];
-          } else { /* ionisation, eq. (distIoni) */
-            uint32_t w2[4];
-            c4[3] = 2u * (uint32_t)k + 1u;
-            oc_philox4x32_10(c4, key, w2);
-            double uh[3], ud[3];
-            isotropic(u01(w2[0]), u01(w2[1]), uh);
-            isotropic(u01(w2[2]), u01(w2[3]), ud);
-            double eres_j = e_res * qe;
-            /* eq. (distIoni) with the energy in eV (volts): r = k_e e / (2 E_res[eV]),
-             * i.e. the separation at which the pair's Coulomb energy k_e e^2 / r is
-             * 2 E_res (the same convention gives 4.59e-11 m for eq. (distRecomb)
-             * at 15.7 eV). */
-            double r = ke * qe * qe / (2.0 * eres_j);
-            double s = sqrt(2.0 * (0.5 * eres_j) / me);
-            double si = sqrt(2.0 * e_therm / g->m_cation);
-            int nc = n_child[i];
-            if (nc < mi) {
-              double *ce = child_x + ((i * mi + nc) * 2 + 0) * 3, *cv = child_v + ((i * mi + nc) * 2 + 0) * 3;
-              double *ix = child_x + ((i * mi + nc) * 2 + 1) * 3, *iv = child_v + ((i * mi + nc) * 2 + 1) * 3;
-              for (int d = 0; d < 3; ++d) {
-                ce[d] = X[d] - r * uh[d];
-                cv[d] = -s * uh[d];
-                ix[d] = X[d];
-                iv[d] = si * ud[d];
-              }
-              n_child[i] = nc + 1;
-            } else {
-              cnt[9] += 2;
-            }
-            for (int d = 0; d < 3; ++d) { X[d] += r * uh[d]; Vv[d] = s * uh[d]; }
-          }
-        } else { /* attachment: anion, momentum conserved with the gas at rest */
+        if (proc < 0) { cnt[CN_NULL] += 1; continue; }
+        cnt[CN_EL + proc] += 1;
+        if (electron_interaction(g, proc, eps, X, Vv, u2, u3, c4, key, (uint32_t)k, &K, cnt)) {
           sp = 2;
-          for (int d = 0; d < 3; ++d) Vv[d] *= me / g->m_anion;
           ballistic = 1;
         }
       } else {
         double nui = g->density * g->ion_xs_iso * vm, nub = g->density * g->ion_xs_back * vm;
         double lim = numax;
-        if (nui + nub > numax) { cnt[7] += 1; lim = nui + nub; }
+        if (nui + nub > numax) { cnt[CN_OVF] += 1; lim = nui + nub; }
         double sel = u1 * lim;
-        if (sel < nui) { /* isotropic in the centre of mass, gas at rest */
-          double mion = (sp == 1) ? g->m_cation : g->m_anion;
-          double fm = mion / (mion + g->m_gas), fM = g->m_gas / (mion + g->m_gas);
-          double dir[3];
-          isotropic(u2, u3, dir);
-          for (int d = 0; d < 3; ++d) Vv[d] = fm * Vv[d] + fM * vm * dir[d];
-          cnt[6] += 1;
-        } else if (sel < nui + nub) { /* backscatter: the ion takes a thermal gas velocity */
-          uint32_t w2[4];
-          c4[3] = 2u * (uint32_t)k + 1u;
-          oc_philox4x32_10(c4, key, w2);
-          double sd = sqrt((double)KB * g->temperature / g->m_gas);
-          double r1 = sqrt(-2.0 * log(u01(w2[0]))), r2 = sqrt(-2.0 * log(u01(w2[2])));
-          Vv[0] = sd * r1 * cos(2.0 * M_PI * u01(w2[1]));
-          Vv[1] = sd * r1 * sin(2.0 * M_PI * u01(w2[1]));
-          Vv[2] = sd * r2 * cos(2.0 * M_PI * u01(w2[3]));
-          cnt[6] += 1;
+        if (sel < nui + nub) {
+          ion_interaction(g, sp, sel < nui ? 0 : 1, Vv, u2, u3, c4, key, (uint32_t)k);
+          cnt[CN_ION] += 1;
         } else {
-          cnt[5] += 1;
+          cnt[CN_NULL] += 1;
         }
       }
     }
@@ -722,8 +826,83 @@ void oc_mc_step(int64_t n, double *x, double *v, int8_t *species, const int64_t 
     v[3 * i] = Vv[0]; v[3 * i + 1] = Vv[1]; v[3 * i + 2] = Vv[2];
     species[i] = (int8_t)sp;
   }
-  for (int k = 0; k < 10; ++k) counters[k] += cnt[k];
+  for (int k = 0; k < CN_COUNT; ++k) counters[k] += cnt[k];
   free(T);
+}
+
+/* Flight of duration tau for the particles with skip[i] == 0 and status[i]
+ * == OC_ALIVE: constant acceleration q E / m (E may be NULL: straight drift),
+ * chord tested for absorption, then the world box.  Used by the Euler and
+ * PEFRL steppers of section 3.3.5 (a drift is one PEFRL position update). */
+void oc_flight(int64_t n, double *x, double *v, const int8_t *species, const double *E, const uint8_t *skip,
+               const oc_gas *g, const oc_step *p, double tau, int64_t N, const double *a, const double *b,
+               const double *c, int8_t *status, int64_t *hit) {
+  tri_t *T = (tri_t *)malloc(sizeof(tri_t) * (size_t)(N > 0 ? N : 1));
+  for (int64_t k = 0; k < N; ++k) tri_setup(a + 3 * k, b + 3 * k, c + 3 * k, &T[k]);
+  const double qe = (double)QE, me = (double)ME;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
+    if ((skip && skip[i]) || status[i] != OC_ALIVE) continue;
+    int sp = species[i];
+    double m = (sp == 0) ? me : (sp == 1 ? g->m_cation : g->m_anion);
+    double q = (sp == 1) ? qe : -qe;
+    double X1[3], V1[3];
+    for (int d = 0; d < 3; ++d) {
+      double acc = E ? q * E[3 * i + d] / m : 0.0;
+      X1[d] = x[3 * i + d] + v[3 * i + d] * tau + 0.5 * acc * tau * tau;
+      V1[d] = v[3 * i + d] + acc * tau;
+    }
+    double th;
+    int64_t h = (N > 0) ? first_hit(N, T, x + 3 * i, X1, &th) : -1;
+    if (h >= 0) { status[i] = OC_ABSORBED; hit[i] = h; continue; }
+    for (int d = 0; d < 3; ++d) { x[3 * i + d] = X1[d]; v[3 * i + d] = V1[d]; }
+    if (outside_box(p, x + 3 * i)) status[i] = OC_LEFT;
+  }
+  free(T);
+}
+
+/* Per-step collision model of section 3.4.2: after the drift over dt, each
+ * live particle collides with probability 1 - exp(-nu_tot dt) (nu_tot = N
+ * sigma_tot(E) v, gas at rest), the process chosen with probabilities
+ * nu_k / nu_tot (one draw: counter (id, step, 0)), then the same
+ * interactions as above at the end point.  At most one collision per step. */
+void oc_collide_step(int64_t n, double *x, double *v, int8_t *species, const int64_t *id, const uint8_t *skip,
+                     const oc_gas *g, const oc_step *p, const int8_t *status, int32_t *n_child, double *child_x,
+                     double *child_v, int64_t *counters) {
+  const double qe = (double)QE, me = (double)ME;
+  int64_t cnt[CN_COUNT] = {0};
+  uint32_t key[2] = {(uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32)};
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : cnt[:CN_COUNT])
+  for (int64_t i = 0; i < n; ++i) {
+    n_child[i] = 0;
+    if ((skip && skip[i]) || status[i] != OC_ALIVE) continue;
+    oc_kids K = {i, p->max_ion_per_step, n_child, child_x, child_v};
+    double *X = x + 3 * i, *Vv = v + 3 * i;
+    int sp = species[i];
+    uint32_t c4[4] = {(uint32_t)((uint64_t)id[i] & 0xffffffffu), (uint32_t)((uint64_t)id[i] >> 32), p->step, 0};
+    uint32_t w[4];
+    oc_philox4x32_10(c4, key, w);
+    double v2 = Vv[0] * Vv[0] + Vv[1] * Vv[1] + Vv[2] * Vv[2];
+    double vm = sqrt(v2);
+    double u0 = u01(w[0]), u1 = u01(w[1]), u2 = u01(w[2]), u3 = u01(w[3]);
+    if (sp == 0) {
+      double eps = 0.5 * me * v2 / qe;
+      double nuk[5], tot = 0;
+      for (int kk = 0; kk < 5; ++kk) { nuk[kk] = g->density * xs_at(g, kk, eps) * vm; tot += nuk[kk]; }
+      if (!(u0 < -expm1(-tot * p->dt))) { cnt[CN_NULL] += 1; continue; }
+      double sel = u1 * tot, cum = 0;
+      int proc = 4;
+      for (int kk = 0; kk < 5; ++kk) { cum += nuk[kk]; if (sel < cum) { proc = kk; break; } }
+      cnt[CN_EL + proc] += 1;
+      if (electron_interaction(g, proc, eps, X, Vv, u2, u3, c4, key, 0u, &K, cnt)) species[i] = 2;
+    } else {
+      double nui = g->density * g->ion_xs_iso * vm, nub = g->density * g->ion_xs_back * vm;
+      if (!(u0 < -expm1(-(nui + nub) * p->dt))) { cnt[CN_NULL] += 1; continue; }
+      ion_interaction(g, sp, (u1 * (nui + nub) < nui) ? 0 : 1, Vv, u2, u3, c4, key, 0u);
+      cnt[CN_ION] += 1;
+    }
+  }
+  for (int k = 0; k < CN_COUNT; ++k) counters[k] += cnt[k];
 }
 
 /* Central difference of L = sum_i w_i . E(x_i) (targets = sources = the n

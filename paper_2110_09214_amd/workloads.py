@@ -490,12 +490,19 @@ class GasTables:
     m_anion: float
     ion_xs_iso: float             # m^2
     ion_xs_back: float            # m^2
+    xi: np.ndarray | None = None  # (n,) anisotropy parameter of the elastic angle, None = isotropic
+    penning_prob: float = 0.0     # Penning transfer probability (0 = off)
+    penning_level: float = 0.0    # eV, ionisation potential of the quenching species
 
 
-def synthetic_ar_co2(n_nodes=2000, e_min=0.01, e_max=1000.0, pressure=1e5, temperature=300.0):
+def synthetic_ar_co2(n_nodes=2000, e_min=0.01, e_max=1000.0, pressure=1e5, temperature=300.0, anisotropic=False,
+                     penning_prob=0.0, penning_level=12.5):
     """Smooth Ar/CO2-like (70/30) electron cross sections: elastic with a
     resonance-like bump, two excitations (11.55, 13.0 eV), a Lotz-like
-    ionisation (15.7 eV) and a Gaussian attachment band at 8.2 eV."""
+    ionisation (15.7 eV) and a Gaussian attachment band at 8.2 eV.  With
+    anisotropic=True the elastic angle's anisotropy parameter rises smoothly
+    with energy, xi(E) = 0.9 E / (E + 5 eV); penning_prob > 0 turns on Penning
+    transfer from excited states at or above penning_level (eV)."""
     E = e_min * (e_max / e_min) ** (np.arange(n_nodes) / (n_nodes - 1))
     x = E / 12.0
     el = 1e-20 * (0.3 + 35.0 * x ** 2 / (1.0 + x ** 2) ** 1.35)
@@ -514,6 +521,7 @@ def synthetic_ar_co2(n_nodes=2000, e_min=0.01, e_max=1000.0, pressure=1e5, tempe
         e_min=e_min, e_max=e_max, density=pressure / (K_BOLTZMANN * temperature),
         temperature=temperature, m_gas=m_gas, m_cation=m_gas, m_anion=15.999 * ATOMIC_MASS,
         ion_xs_iso=2.5e-19, ion_xs_back=2.5e-19,
+        xi=(0.9 * E / (E + 5.0)) if anisotropic else None, penning_prob=penning_prob, penning_level=penning_level,
     )
 
 
