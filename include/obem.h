@@ -202,6 +202,52 @@ obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh, const dou
                                 double *g_sz);
 
 /* ---------------------------------------------------------------------------
+ * Static field option (section 3.3.1) and signal induction (section 3.5)
+ * ------------------------------------------------------------------------- */
+
+/* Field of the cells on a uniform 3D grid: nodes lo + (i h0, j h1, k h2),
+ * 0 <= i < nx etc. (each >= 2, nx*ny*nz < 2^31), values in caller-owned
+ * device arrays ex, ey, ez of nx*ny*nz doubles, index (k*ny + j)*nx + i. */
+typedef struct {
+  int32_t nx, ny, nz;
+  double lo[3];
+  double h[3];    /* node spacing, > 0 */
+  double *ex, *ey, *ez;
+} obem_field_map;
+
+/* Fill map->ex/ey/ez with the cell field of sigma (eq. (BEM3)) at the grid
+ * nodes, computed once before tracking (the static option: it leaves out
+ * the influence of the particles and the charging-up).  A node exactly in a
+ * cell's plane inside the cell gets the principal value of that cell's
+ * normal field. */
+obem_status field_map_build(obem_ctx *ctx, const obem_meshh *mesh, const double *sigma,
+                            const obem_field_map *map, obem_precision precision);
+
+/* Trilinear interpolation of the map at n points (device SoA x, y, z);
+ * points outside the grid box take the value at the nearest point of the
+ * box.  Outputs Ex, Ey, Ez (n device doubles) are overwritten. */
+obem_status field_map_eval(obem_ctx *ctx, const obem_field_map *map, int64_t n, const double *x,
+                           const double *y, const double *z, double *Ex, double *Ey, double *Ez);
+
+/* Shockley-Ramo current induced on one read-out electrode, eq. (ramo):
+ *   i_s = sum over particles p of species s of q_p v_p . E_w(x_p),
+ * with E_w the electrode's weighting field: either the cell field of sigma_w
+ * (mesh and sigma_w given, map NULL; sigma_w = bem_solve_charges with that
+ * electrode's cells at 1 V, every other ed cell at 0 V and no free charge on
+ * dd cells -- the dynamic option) or a map of it (map given, mesh and sigma_w
+ * NULL -- the static option).  Particles: n entries of device SoA positions,
+ * velocities and species (charge -e for electrons (0) and anions (2), +e
+ * for cations (1)).  current (host, 3 doubles, A): the sums for electrons,
+ * cations and anions; requesting it synchronises the stream.  terms (device,
+ * n doubles, may be NULL): the per-particle q v . E_w.  The sums are taken
+ * in a fixed order (deterministic). */
+obem_status induced_current(obem_ctx *ctx, const obem_meshh *mesh, const double *sigma_w,
+                            const obem_field_map *map, int64_t n, const double *x, const double *y,
+                            const double *z, const double *vx, const double *vy, const double *vz,
+                            const int8_t *species, obem_precision precision, double *current,
+                            double *terms);
+
+/* ---------------------------------------------------------------------------
  * Transport step (sections 3.3-3.4)
  * ------------------------------------------------------------------------- */
 #define OBEM_ELECTRON 0
@@ -236,7 +282,24 @@ typedef struct {
   double temperature;   /* K */
   double m_gas, m_cation, m_anion;  /* kg */
   double ion_xs_iso, ion_xs_back;   /* m^2 */
+  const double *xi;     /* device [n_nodes] or NULL: anisotropy xi(E) of the elastic
+                           angle, eq. (anisotrop), cos theta = 1 - 2R(1 - xi)/(1 +
+                           xi(1 - 2R)) about the incident direction; NULL =
+                           isotropic */
+  double penning_prob;  /* Penning transfer (section 3.4.4): an excitation whose
+                           threshold is >= penning_level ionises the quencher with
+                           this probability (0 = off); the electron takes the
+                           excess energy, the cation a thermal speed */
+  double penning_level; /* eV, ionisation potential of the quenching species */
 } obem_gas;
+
+/* Transport schemes (sections 3.3.5, 3.4.2). */
+#define OBEM_NULL_COLLISION 0 /* constant-field flights with null collisions      */
+#define OBEM_EULER 1          /* one flight in the start field, then the per-step
+                                 collision test                                   */
+#define OBEM_PEFRL 2          /* PEFRL (4 field evaluations at the intermediate
+                                 positions, from the set-up and the charges still
+                                 in the step), then the per-step collision test  */
 
 typedef struct {
   double dt;            /* step length, s                                          */
@@ -254,6 +317,16 @@ typedef struct {
   int32_t influence;    /* with resolve: also move the live particles' influence
                            onto the RHS before the solve (as bem_influence)       */
   const double *rhs0;   /* device, n_panels: [V_i ; sigma_F0,i]                    */
+  int32_t stepper;      /* OBEM_NULL_COLLISION, OBEM_EULER or OBEM_PEFRL. Per-step
+                           collision test: probability 1 - exp(-nu_tot dt) with
+                           nu_tot = N sigma_tot(E) v at the end of the drift, the
+                           process chosen in proportion to nu_k; at most one
+                           collision per particle and step                      */
+  const obem_field_map *map;  /* static option (section 3.3.1): if not NULL the field
+                           of the set-up is interpolated in this map instead of
+                           summed over the cells (resolve must then be 0); the
+                           mesh, if given, still absorbs particles and collects
+                           charging counts                                       */
 } obem_step_params;
 
 typedef struct {
@@ -262,6 +335,7 @@ typedef struct {
   int64_t real_collisions[5];   /* electron processes, in table order           */
   int64_t null_collisions, ion_collisions, rate_overflow, flight_cap;
   int64_t dd_charge_deposited;  /* elementary charges landed on dd cells         */
+  int64_t penning;              /* Penning transfers (pairs created)            */
 } obem_step_stats;
 
 /* One tracking step (ordered as in the paper's dynamic option):

@@ -50,7 +50,8 @@ class Gas_t(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("e_min", C.c_double), ("e_max", C.c_double), ("xs", C.c_void_p),
                 ("thr", C.c_double * 5), ("density", C.c_double), ("temperature", C.c_double),
                 ("m_gas", C.c_double), ("m_cation", C.c_double), ("m_anion", C.c_double),
-                ("ion_xs_iso", C.c_double), ("ion_xs_back", C.c_double)]
+                ("ion_xs_iso", C.c_double), ("ion_xs_back", C.c_double), ("xi", C.c_void_p),
+                ("penning_prob", C.c_double), ("penning_level", C.c_double)]
 
 
 class StepParams_t(C.Structure):
@@ -58,7 +59,12 @@ class StepParams_t(C.Structure):
                 ("max_ion_per_step", C.c_int32), ("ion_v_cap", C.c_double), ("box_lo", C.c_double * 3),
                 ("box_hi", C.c_double * 3), ("soft", C.c_double), ("r_rec", C.c_double),
                 ("precision", C.c_int), ("resolve", C.c_int32), ("influence", C.c_int32),
-                ("rhs0", C.c_void_p)]
+                ("rhs0", C.c_void_p), ("stepper", C.c_int32), ("map", C.c_void_p)]
+
+
+class FieldMap_t(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("lo", C.c_double * 3),
+                ("h", C.c_double * 3), ("ex", C.c_void_p), ("ey", C.c_void_p), ("ez", C.c_void_p)]
 
 
 class StepStats_t(C.Structure):
@@ -66,13 +72,13 @@ class StepStats_t(C.Structure):
                 ("left_world", C.c_int64), ("children", C.c_int64), ("children_dropped", C.c_int64),
                 ("real_collisions", C.c_int64 * 5), ("null_collisions", C.c_int64),
                 ("ion_collisions", C.c_int64), ("rate_overflow", C.c_int64), ("flight_cap", C.c_int64),
-                ("dd_charge_deposited", C.c_int64)]
+                ("dd_charge_deposited", C.c_int64), ("penning", C.c_int64)]
 
 
 SYMBOLS = ["obem_create", "obem_destroy", "obem_last_error", "obem_constants", "obem_profile_enable",
            "obem_profile_read", "obem_mesh_bind",
            "obem_mesh_release", "obem_mesh_geometry", "bem_solve_charges", "bem_solve_charges_adjoint", "bem_influence",
-           "field_eval", "field_eval_backward", "track_step"]
+           "field_eval", "field_eval_backward", "field_map_build", "field_map_eval", "induced_current", "track_step"]
 
 _lib = None
 
@@ -100,6 +106,9 @@ def load(path: str = LIB_PATH):
     lib.bem_solve_charges.argtypes = [vp, vp, vp, vp, i32, C.POINTER(SolveInfo_t)]
     lib.bem_solve_charges_adjoint.argtypes = [vp, vp, vp, vp, i32, C.POINTER(SolveInfo_t)]
     lib.bem_influence.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp]
+    lib.field_map_build.argtypes = [vp, vp, vp, C.POINTER(FieldMap_t), i32]
+    lib.field_map_eval.argtypes = [vp, C.POINTER(FieldMap_t), i64, vp, vp, vp, vp, vp, vp]
+    lib.induced_current.argtypes = [vp, vp, vp, C.POINTER(FieldMap_t), i64, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp]
     lib.field_eval.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, d, i32, C.c_uint, vp, vp, vp, vp]
     lib.field_eval_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, d, i32, C.c_uint,
                                         vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -342,19 +351,75 @@ class Particles:
 
 
 def gas_struct(gas, device):
-    """obem_gas from a workloads.GasTables; returns (struct, keep-alive tensor)."""
+    """obem_gas from a workloads.GasTables; returns (struct, keep-alive tensors)."""
     xs = torch.as_tensor(gas.xs, dtype=torch.float64, device=device).contiguous()
+    xi = None
+    if getattr(gas, "xi", None) is not None:
+        xi = torch.as_tensor(gas.xi, dtype=torch.float64, device=device).contiguous()
     g = Gas_t(xs.shape[1], gas.e_min, gas.e_max, _ptr(xs), (C.c_double * 5)(*[float(t) for t in gas.thresholds]),
-              gas.density, gas.temperature, gas.m_gas, gas.m_cation, gas.m_anion, gas.ion_xs_iso, gas.ion_xs_back)
-    return g, xs
+              gas.density, gas.temperature, gas.m_gas, gas.m_cation, gas.m_anion, gas.ion_xs_iso, gas.ion_xs_back,
+              _ptr(xi), float(getattr(gas, "penning_prob", 0.0)), float(getattr(gas, "penning_level", 0.0)))
+    return g, (xs, xi)
 
 
-def track_step(ctx: Context, mesh: BoundMesh, parts: Particles, gas_s, params: dict, dd_counts, sigma, rhs0=None):
+class FieldMap:
+    """Uniform-grid field map (obem_field_map) with its device arrays:
+    nodes lo + (i, j, k) h, n = (nx, ny, nz)."""
+
+    def __init__(self, lo, h, n, device="cuda"):
+        self.lo, self.h, self.n = tuple(float(v) for v in lo), tuple(float(v) for v in h), tuple(int(v) for v in n)
+        m = self.n[0] * self.n[1] * self.n[2]
+        self.e = [torch.zeros(m, dtype=torch.float64, device=device) for _ in range(3)]
+        self.s = FieldMap_t(self.n[0], self.n[1], self.n[2], (C.c_double * 3)(*self.lo), (C.c_double * 3)(*self.h),
+                            *[C.c_void_p(t.data_ptr()) for t in self.e])
+
+    def values(self):
+        """(nz, ny, nx, 3) tensor of the node values."""
+        nx, ny, nz = self.n
+        return torch.stack(self.e, 1).reshape(nz, ny, nx, 3)
+
+
+def field_map_build(ctx: Context, mesh: BoundMesh, sigma, fmap: FieldMap, precision=OBEM_MIXED):
+    ctx.check(ctx.lib.field_map_build(ctx.h, mesh.h, _ptr(sigma, n=mesh.n, name="sigma"), C.byref(fmap.s),
+                                      int(precision)))
+    return fmap
+
+
+def field_map_eval(ctx: Context, fmap: FieldMap, x, out=None):
+    n = int(x.shape[0])
+    xs = _soa(x)
+    out = out if out is not None else [torch.empty(n, dtype=torch.float64, device=x.device) for _ in range(3)]
+    ctx.check(ctx.lib.field_map_eval(ctx.h, C.byref(fmap.s), n, *[_ptr(a, n=n) for a in xs],
+                                     *[_ptr(a, n=n) for a in out]))
+    return torch.stack(out, 1)
+
+
+def induced_current(ctx: Context, x, v, species, mesh: BoundMesh = None, sigma_w=None, fmap: FieldMap = None,
+                    precision=OBEM_MIXED, want_terms=False):
+    """Shockley-Ramo currents [electrons, cations, anions] (A) induced on the
+    electrode whose weighting field is the cell field of sigma_w, or fmap."""
+    n = int(x.shape[0])
+    xs, vs = _soa(x), _soa(v)
+    cur = (C.c_double * 3)()
+    terms = torch.empty(n, dtype=torch.float64, device=x.device) if want_terms else None
+    ctx.check(ctx.lib.induced_current(ctx.h, mesh.h if mesh is not None else None,
+                                      _ptr(sigma_w, n=mesh.n, name="sigma_w") if mesh is not None else None,
+                                      C.byref(fmap.s) if fmap is not None else None, n,
+                                      *[_ptr(a, n=n) for a in xs], *[_ptr(a, n=n) for a in vs],
+                                      _ptr(species, torch.int8, n=n, name="species"), int(precision), cur,
+                                      _ptr(terms, n=n)))
+    c = [cur[0], cur[1], cur[2]]
+    return (c, terms) if want_terms else c
+
+
+def track_step(ctx: Context, mesh: BoundMesh, parts: Particles, gas_s, params: dict, dd_counts, sigma, rhs0=None,
+               fmap: FieldMap = None):
     p = StepParams_t(params["dt"], params["step"], params["seed"], params["max_coll"], params["max_ion_per_step"],
                      params["ion_v_cap"], (C.c_double * 3)(*params["box_lo"]), (C.c_double * 3)(*params["box_hi"]),
                      params["soft"], params["r_rec"], int(params.get("precision", OBEM_MIXED)),
                      int(params.get("resolve", 0)), int(params.get("influence", 0)),
-                     _ptr(rhs0) if rhs0 is not None else None)
+                     _ptr(rhs0) if rhs0 is not None else None, int(params.get("stepper", 0)),
+                     C.cast(C.pointer(fmap.s), C.c_void_p) if fmap is not None else None)
     ps = parts.struct()
     stats = StepStats_t()
     st = ctx.lib.track_step(ctx.h, mesh.h if mesh is not None else None, C.byref(ps), C.byref(gas_s), C.byref(p),

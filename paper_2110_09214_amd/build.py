@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libobem.so")
-SOURCES = ["api.hip", "field.hip", "bem.hip", "adjoint.hip", "influence.hip", "track.hip"]
+SOURCES = ["api.hip", "field.hip", "bem.hip", "adjoint.hip", "influence.hip", "fieldmap.hip", "track.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

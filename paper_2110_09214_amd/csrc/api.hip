@@ -181,27 +181,6 @@ __global__ __launch_bounds__(64) void k_tile_spheres(int n, const double *f, dou
 
 using namespace obem;
 
-#define CHECK_CTX(ctx)                                                       \
-  do {                                                                       \
-    if (!(ctx)) return OBEM_EINVAL;                                          \
-    if ((ctx)->sticky) return OBEM_ESTATE;                                   \
-    if (hipSetDevice((ctx)->device) != hipSuccess) {                         \
-      hipGetLastError();                                                     \
-      return fail(ctx, OBEM_EDEVICE, "hipSetDevice(%d) failed", (ctx)->device); \
-    }                                                                        \
-  } while (0)
-
-#define REQ_DEV(ctx, p, name)                                                             \
-  do {                                                                                    \
-    if (!is_device_ptr(p)) return fail(ctx, OBEM_EINVAL, "%s is NULL or not device memory", name); \
-  } while (0)
-
-#define OPT_DEV(ctx, p, name)                                                             \
-  do {                                                                                    \
-    if ((p) && !is_device_ptr(p)) return fail(ctx, OBEM_EINVAL, "%s is not device memory", name); \
-  } while (0)
-
-static const int64_t kMaxCount = (int64_t)1 << 31;
 
 extern "C" {
 

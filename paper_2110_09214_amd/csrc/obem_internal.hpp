@@ -42,7 +42,7 @@ struct DevBuf {
 enum WsSlot {
   WS_BBOX = 0, WS_KEYS0, WS_KEYS1, WS_IDX0, WS_IDX1, WS_SORT_TMP, WS_TSORT, WS_ACC, WS_PART,
   WS_NN, WS_MISC0, WS_MISC1, WS_MISC2, WS_MISC3, WS_MISC4, WS_MISC5, WS_MISC6, WS_MISC7,
-  WS_SOLVE0, WS_SOLVE1, WS_SOLVE2, WS_SRC, WS_SRCPERM, WS_SRCKEY, WS_SORT_TMP2, WS_TBOX,
+  WS_SOLVE0, WS_SOLVE1, WS_SOLVE2, WS_SRC, WS_SRCPERM, WS_SRCKEY, WS_SORT_TMP2, WS_TBOX, WS_MAP, WS_STATUS,
   WS_COUNT
 };
 
@@ -165,5 +165,71 @@ obem_status influence_rhs(obem_ctx *ctx, const obem_meshh *m, int64_t n_src, con
                           const double *sz, const double *sq, const double *rhs, double *rhs_out, obem_precision prec,
                           double *vbar, double *ebx, double *eby, double *ebz);
 void solver_release(obem_ctx *ctx);
+
+// Uniform-grid field map of the static option (fieldmap.hip).
+struct MapDev {
+  int nx, ny, nz;
+  double lo[3], h[3];
+  const double *ex, *ey, *ez;
+};
+
+// Trilinear interpolation; points outside the grid box take the value at the
+// nearest point of the box.
+__device__ __forceinline__ void map_interp(const MapDev &g, double x, double y, double z, double E[3]) {
+  const double p[3] = {x, y, z};
+  const int nn[3] = {g.nx, g.ny, g.nz};
+  int i0[3];
+  double f[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double u = (p[c] - g.lo[c]) / g.h[c];
+    u = fmin(fmax(u, 0.0), (double)(nn[c] - 1));
+    int i = (int)floor(u);
+    if (i > nn[c] - 2) i = nn[c] - 2;
+    i0[c] = i;
+    f[c] = u - (double)i;
+  }
+  E[0] = E[1] = E[2] = 0.0;
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        const double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
+        const size_t k = ((size_t)(i0[2] + dz) * g.ny + (i0[1] + dy)) * g.nx + (i0[0] + dx);
+        E[0] += w * g.ex[k];
+        E[1] += w * g.ey[k];
+        E[2] += w * g.ez[k];
+      }
+}
+// Checks a caller's map (sizes >= 2, spacing > 0, device arrays) and copies it.
+bool map_dev(const obem_field_map *m, MapDev *g);
+// Map field at the Morton-sorted targets into the accumulator (units 1/k_e,
+// V component 0), in place of the cell field.
+obem_status launch_map_acc(obem_ctx *ctx, const MapDev &g, const TargetOrder &to, double *acc);
+
+// Argument checks shared by the entry points (host side).
+#define CHECK_CTX(ctx)                                                       \
+  do {                                                                       \
+    if (!(ctx)) return OBEM_EINVAL;                                          \
+    if ((ctx)->sticky) return OBEM_ESTATE;                                   \
+    if (hipSetDevice((ctx)->device) != hipSuccess) {                         \
+      hipGetLastError();                                                     \
+      return fail(ctx, OBEM_EDEVICE, "hipSetDevice(%d) failed", (ctx)->device); \
+    }                                                                        \
+  } while (0)
+
+#define REQ_DEV(ctx, p, name)                                                             \
+  do {                                                                                    \
+    if (!is_device_ptr(p)) return fail(ctx, OBEM_EINVAL, "%s is NULL or not device memory", name); \
+  } while (0)
+
+#define OPT_DEV(ctx, p, name)                                                             \
+  do {                                                                                    \
+    if ((p) && !is_device_ptr(p)) return fail(ctx, OBEM_EINVAL, "%s is not device memory", name); \
+  } while (0)
+
+constexpr int64_t kMaxCount = (int64_t)1 << 31;
 
 }  // namespace obem

@@ -43,6 +43,8 @@ struct GasDev {
   double thr[5];
   double density, temperature, m_gas, m_cation, m_anion, ion_iso, ion_back;
   double nu_e, nu_i;
+  const double *xi;  // anisotropy of the elastic angle (eq. (anisotrop)) or NULL
+  double pen_prob, pen_level;
 };
 
 struct StepDev {
@@ -161,7 +163,204 @@ __device__ __forceinline__ void iso_dir(double u2, double u3, double *d) {
   d[2] = ct;
 }
 
-enum { C_EL = 0, C_NULL = 5, C_ION = 6, C_OVF = 7, C_CAP = 8, C_DROP = 9, C_ABS = 10, C_LEFT = 11, C_DD = 12, NCNT = 13 };
+// Table value at eps (eV), linear in the normalised lethargy of eq. (leth)
+// between log-spaced nodes, clamped to the end nodes (as xs_at).
+__device__ __forceinline__ double table_at(const GasDev &g, const double *tab, double eps) {
+  const int n = g.n;
+  if (!(eps > g.e_min)) return tab[0];
+  if (eps >= g.e_max) return tab[n - 1];
+  const double p = (double)(n - 1) * (log(eps / g.e_min) / log(g.e_max / g.e_min));
+  int i = (int)floor(p);
+  if (i >= n - 1) i = n - 2;
+  const double fr = p - (double)i;
+  return tab[i] * (1.0 - fr) + tab[i + 1] * fr;
+}
+
+// Unit vector at polar angle theta (cosine ct) and azimuth 2 pi u about the
+// unit vector d: e1 = (a x d)/|a x d| with a the z axis (the x axis when d is
+// within 25.8 degrees of z), e2 = d x e1.
+__device__ __forceinline__ void rotate_about(const double *d, double ct, double u, double *out) {
+  double a[3] = {0.0, 0.0, 1.0};
+  if (fabs(d[2]) >= 0.9) {
+    a[0] = 1.0;
+    a[2] = 0.0;
+  }
+  double e1[3] = {a[1] * d[2] - a[2] * d[1], a[2] * d[0] - a[0] * d[2], a[0] * d[1] - a[1] * d[0]};
+  const double l = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) e1[k] /= l;
+  const double e2[3] = {d[1] * e1[2] - d[2] * e1[1], d[2] * e1[0] - d[0] * e1[2], d[0] * e1[1] - d[1] * e1[0]};
+  const double st = sqrt(fmax(0.0, 1.0 - ct * ct)), ph = 2.0 * kPi * u;
+  const double cp = cos(ph), sp = sin(ph);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) out[k] = ct * d[k] + st * (cp * e1[k] + sp * e2[k]);
+}
+
+enum {
+  C_EL = 0, C_NULL = 5, C_ION = 6, C_OVF = 7, C_CAP = 8, C_DROP = 9, C_ABS = 10, C_LEFT = 11, C_DD = 12, C_PEN = 13,
+  NCNT = 14
+};
+
+// Child pairs (electron, cation) of one particle in this step: slots
+// child[((i*max_ion + c)*2 + {0, 1})*6 + (x, v)].
+struct Kids {
+  double *child;
+  int max_ion;
+  int i;
+  int nc;
+};
+
+__device__ __forceinline__ bool add_pair(Kids &K, const double *xe, const double *ve, const double *xc,
+                                         const double *vc) {
+  if (K.nc >= K.max_ion) return false;
+  double *ce = K.child + (((size_t)K.i * K.max_ion + K.nc) * 2 + 0) * 6;
+  double *ci = K.child + (((size_t)K.i * K.max_ion + K.nc) * 2 + 1) * 6;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    ce[d] = xe[d];
+    ce[3 + d] = ve[d];
+    ci[d] = xc[d];
+    ci[3 + d] = vc[d];
+  }
+  ++K.nc;
+  return true;
+}
+
+// Real interaction `proc` (elastic, exc1, exc2, ionisation, attachment) of an
+// electron of energy eps (eV) at X with velocity V (section 3.4.3).  u2, u3:
+// the collision's own uniforms; extra draws use counter word 3 = 2k + 1
+// (ionisation, Penning) and 0x80000000 | k (Penning cation).  Returns true
+// when the electron became an anion.
+__device__ bool electron_interaction(const GasDev &g, int proc, double eps, double *X, double *Vv, double u2,
+                                     double u3, uint64_t pid, uint32_t step, uint2 key, uint32_t k, Kids &K,
+                                     int *cnt) {
+  const double e_therm = 1.5 * kKb * g.temperature;
+  const double v2 = Vv[0] * Vv[0] + Vv[1] * Vv[1] + Vv[2] * Vv[2];
+  const double vm = sqrt(v2);
+  double dir[3];
+  if (proc == 0) {  // elastic, recoil loss 2 m_e/M (1 - cos theta)
+    double ct;
+    if (g.xi && vm > 0.0) {  // eq. (anisotrop) about the incident direction
+      const double xi = table_at(g, g.xi, eps);
+      ct = 1.0 - 2.0 * u2 * (1.0 - xi) / (1.0 + xi * (1.0 - 2.0 * u2));
+      const double d0[3] = {Vv[0] / vm, Vv[1] / vm, Vv[2] / vm};
+      rotate_about(d0, ct, u3, dir);
+    } else {
+      iso_dir(u2, u3, dir);
+      ct = (vm > 0.0) ? (dir[0] * Vv[0] + dir[1] * Vv[1] + dir[2] * Vv[2]) / vm : 1.0;
+    }
+    const double e2 = eps * (1.0 - 2.0 * kMe / g.m_gas * (1.0 - ct));
+    const double s = sqrt(2.0 * e2 * kQe / kMe);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) Vv[d] = s * dir[d];
+    return false;
+  }
+  if (proc <= 3) {
+    const double e_res = (proc == 3) ? eps - g.thr[3] - e_therm / kQe : -1.0;
+    if (proc != 3 || e_res <= 0.0) {  // excitation (or sub-threshold ionisation)
+      double e2 = eps - g.thr[proc];
+      if (e2 < 0.0) e2 = 0.0;
+      iso_dir(u2, u3, dir);
+      const double s = sqrt(2.0 * e2 * kQe / kMe);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) Vv[d] = s * dir[d];
+      if (proc != 3 && g.pen_prob > 0.0 && g.thr[proc] >= g.pen_level) {
+        // Penning transfer (section 3.4.4): the released electron takes the
+        // excess energy thr - pen_level, the cation a thermal speed, both
+        // isotropic, at the collision point
+        const uint4 w2 = philox10(make_uint4((uint32_t)pid, (uint32_t)(pid >> 32), step, 2u * k + 1u), key);
+        if (u01(w2.x) < g.pen_prob) {
+          const uint4 w3 = philox10(make_uint4((uint32_t)pid, (uint32_t)(pid >> 32), step, 0x80000000u | k), key);
+          double de[3], dc[3], ve[3], vc[3];
+          iso_dir(u01(w2.y), u01(w2.z), de);
+          iso_dir(u01(w3.x), u01(w3.y), dc);
+          const double se = sqrt(2.0 * (g.thr[proc] - g.pen_level) * kQe / kMe);
+          const double si = sqrt(2.0 * e_therm / g.m_cation);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            ve[d] = se * de[d];
+            vc[d] = si * dc[d];
+          }
+          cnt[C_PEN] += 1;
+          if (!add_pair(K, X, ve, X, vc)) cnt[C_DROP] += 2;
+        }
+      }
+      return false;
+    }
+    // ionisation, eq. (distIoni)
+    const uint4 w2 = philox10(make_uint4((uint32_t)pid, (uint32_t)(pid >> 32), step, 2u * k + 1u), key);
+    double uh[3], ud[3];
+    iso_dir(u01(w2.x), u01(w2.y), uh);
+    iso_dir(u01(w2.z), u01(w2.w), ud);
+    const double eres_j = e_res * kQe;
+    // energy in eV (volts): r = k_e e / (2 E_res[eV]) = k_e e^2 / (2 E_res[J])
+    const double r = kKe * kQe * kQe / (2.0 * eres_j);
+    const double s = sqrt(2.0 * (0.5 * eres_j) / kMe);
+    const double si = sqrt(2.0 * e_therm / g.m_cation);
+    double xe[3], ve[3], vc[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      xe[d] = X[d] - r * uh[d];
+      ve[d] = -s * uh[d];
+      vc[d] = si * ud[d];
+    }
+    if (!add_pair(K, xe, ve, X, vc)) cnt[C_DROP] += 2;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      X[d] += r * uh[d];
+      Vv[d] = s * uh[d];
+    }
+    return false;
+  }
+  // attachment: anion, momentum conserved with the gas at rest
+#pragma unroll
+  for (int d = 0; d < 3; ++d) Vv[d] *= kMe / g.m_anion;
+  return true;
+}
+
+// Ion collision: 0 = isotropic in the centre of mass (gas at rest), 1 =
+// backscatter (charge exchange: the ion takes a thermal gas velocity).
+__device__ void ion_interaction(const GasDev &g, int sp, int proc, double *Vv, double u2, double u3, uint64_t pid,
+                                uint32_t step, uint2 key, uint32_t k) {
+  const double vm = sqrt(Vv[0] * Vv[0] + Vv[1] * Vv[1] + Vv[2] * Vv[2]);
+  if (proc == 0) {
+    const double mion = (sp == 1) ? g.m_cation : g.m_anion;
+    const double fm = mion / (mion + g.m_gas), fM = g.m_gas / (mion + g.m_gas);
+    double dir[3];
+    iso_dir(u2, u3, dir);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) Vv[d] = fm * Vv[d] + fM * vm * dir[d];
+  } else {
+    const uint4 w2 = philox10(make_uint4((uint32_t)pid, (uint32_t)(pid >> 32), step, 2u * k + 1u), key);
+    const double sd = sqrt(kKb * g.temperature / g.m_gas);
+    const double r1 = sqrt(-2.0 * log(u01(w2.x))), r2 = sqrt(-2.0 * log(u01(w2.z)));
+    Vv[0] = sd * r1 * cos(2.0 * kPi * u01(w2.y));
+    Vv[1] = sd * r1 * sin(2.0 * kPi * u01(w2.y));
+    Vv[2] = sd * r2 * cos(2.0 * kPi * u01(w2.w));
+  }
+}
+
+__device__ __forceinline__ bool outside(const StepDev &p, const double *X) {
+  return X[0] < p.lo[0] || X[0] > p.hi[0] || X[1] < p.lo[1] || X[1] > p.hi[1] || X[2] < p.lo[2] || X[2] > p.hi[2];
+}
+
+// Absorption bookkeeping: a dd hit adds the particle's charge to the cell's
+// elementary-charge count (eq. (charge-up)).
+__device__ __forceinline__ void absorb(const GridDev &G, int hcell, int sp, int64_t *dd_counts, int *cnt) {
+  cnt[C_ABS] += 1;
+  if (G.kind[hcell] == 1) {
+    atomicAdd((unsigned long long *)&dd_counts[hcell], (unsigned long long)(long long)(sp == 1 ? 1 : -1));
+    cnt[C_DD] += 1;
+  }
+}
+
+__device__ __forceinline__ void flush_counts(const int *cnt, unsigned long long *sc, unsigned long long *counters) {
+#pragma unroll
+  for (int k = 0; k < NCNT; ++k)
+    if (cnt[k]) atomicAdd(&sc[k], (unsigned long long)cnt[k]);
+  __syncthreads();
+  if (threadIdx.x < NCNT && sc[threadIdx.x]) atomicAdd(&counters[threadIdx.x], sc[threadIdx.x]);
+}
 
 // Constant-field flights with null-collision Monte Carlo for one particle per
 // thread.  Outputs status (0 alive, 1 absorbed, 2 left the world box), the
@@ -194,8 +393,7 @@ __global__ __launch_bounds__(256) void k_push_mc(int n, double *X0, double *X1, 
     bool ballistic = false;
     const uint64_t pid = (uint64_t)id[i];
     const uint2 key = make_uint2(p.key0, p.key1);
-    const double e_therm = 1.5 * kKb * g.temperature;
-    int nc = 0;
+    Kids K = {child, p.max_ion, i, 0};
     int st = 0, hcell = -1;
     for (int k = 0;; ++k) {
       const double m = (sp == 0) ? kMe : (sp == 1 ? g.m_cation : g.m_anion);
@@ -234,7 +432,7 @@ __global__ __launch_bounds__(256) void k_push_mc(int n, double *X0, double *X1, 
         X[d] = Xn[d];
         Vv[d] = Vn[d];
       }
-      if (X[0] < p.lo[0] || X[0] > p.hi[0] || X[1] < p.lo[1] || X[1] > p.hi[1] || X[2] < p.lo[2] || X[2] > p.hi[2]) {
+      if (outside(p, X)) {
         st = 2;
         break;
       }
@@ -269,58 +467,8 @@ __global__ __launch_bounds__(256) void k_push_mc(int n, double *X0, double *X1, 
           continue;
         }
         cnt[C_EL + proc] += 1;
-        double dir[3];
-        if (proc == 0) {
-          iso_dir(u2, u3, dir);
-          const double ct = (vm > 0.0) ? (dir[0] * Vv[0] + dir[1] * Vv[1] + dir[2] * Vv[2]) / vm : 1.0;
-          const double e2 = eps * (1.0 - 2.0 * kMe / g.m_gas * (1.0 - ct));
-          const double s = sqrt(2.0 * e2 * kQe / kMe);
-#pragma unroll
-          for (int d = 0; d < 3; ++d) Vv[d] = s * dir[d];
-        } else if (proc <= 3) {
-          const double e_res = (proc == 3) ? eps - g.thr[3] - e_therm / kQe : -1.0;
-          if (proc != 3 || e_res <= 0.0) {
-            double e2 = eps - g.thr[proc];
-            if (e2 < 0.0) e2 = 0.0;
-            iso_dir(u2, u3, dir);
-            const double s = sqrt(2.0 * e2 * kQe / kMe);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) Vv[d] = s * dir[d];
-          } else {  // ionisation, eq. (distIoni)
-            const uint4 w2 =
-                philox10(make_uint4((uint32_t)pid, (uint32_t)(pid >> 32), p.step, 2u * (uint32_t)k + 1u), key);
-            double uh[3], ud[3];
-            iso_dir(u01(w2.x), u01(w2.y), uh);
-            iso_dir(u01(w2.z), u01(w2.w), ud);
-            const double eres_j = e_res * kQe;
-            // energy in eV (volts): r = k_e e / (2 E_res[eV]) = k_e e^2 / (2 E_res[J])
-            const double r = kKe * kQe * kQe / (2.0 * eres_j);
-            const double s = sqrt(2.0 * (0.5 * eres_j) / kMe);
-            const double si = sqrt(2.0 * e_therm / g.m_cation);
-            if (nc < p.max_ion) {
-              double *ce = child + (((size_t)i * p.max_ion + nc) * 2 + 0) * 6;
-              double *ci = child + (((size_t)i * p.max_ion + nc) * 2 + 1) * 6;
-#pragma unroll
-              for (int d = 0; d < 3; ++d) {
-                ce[d] = X[d] - r * uh[d];
-                ce[3 + d] = -s * uh[d];
-                ci[d] = X[d];
-                ci[3 + d] = si * ud[d];
-              }
-              ++nc;
-            } else {
-              cnt[C_DROP] += 2;
-            }
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-              X[d] += r * uh[d];
-              Vv[d] = s * uh[d];
-            }
-          }
-        } else {  // attachment: anion, momentum conserved with the gas at rest
+        if (electron_interaction(g, proc, eps, X, Vv, u2, u3, pid, p.step, key, (uint32_t)k, K, cnt)) {
           sp = 2;
-#pragma unroll
-          for (int d = 0; d < 3; ++d) Vv[d] *= kMe / g.m_anion;
           ballistic = true;
         }
       } else {
@@ -331,22 +479,8 @@ __global__ __launch_bounds__(256) void k_push_mc(int n, double *X0, double *X1, 
           lim = nui + nub;
         }
         const double sel = u1 * lim;
-        if (sel < nui) {  // isotropic in the centre of mass, gas at rest
-          const double mion = (sp == 1) ? g.m_cation : g.m_anion;
-          const double fm = mion / (mion + g.m_gas), fM = g.m_gas / (mion + g.m_gas);
-          double dir[3];
-          iso_dir(u2, u3, dir);
-#pragma unroll
-          for (int d = 0; d < 3; ++d) Vv[d] = fm * Vv[d] + fM * vm * dir[d];
-          cnt[C_ION] += 1;
-        } else if (sel < nui + nub) {  // backscatter: thermal velocity of the gas
-          const uint4 w2 =
-              philox10(make_uint4((uint32_t)pid, (uint32_t)(pid >> 32), p.step, 2u * (uint32_t)k + 1u), key);
-          const double sd = sqrt(kKb * g.temperature / g.m_gas);
-          const double r1 = sqrt(-2.0 * log(u01(w2.x))), r2 = sqrt(-2.0 * log(u01(w2.z)));
-          Vv[0] = sd * r1 * cos(2.0 * kPi * u01(w2.y));
-          Vv[1] = sd * r1 * sin(2.0 * kPi * u01(w2.y));
-          Vv[2] = sd * r2 * cos(2.0 * kPi * u01(w2.w));
+        if (sel < nui + nub) {
+          ion_interaction(g, sp, sel < nui ? 0 : 1, Vv, u2, u3, pid, p.step, key, (uint32_t)k);
           cnt[C_ION] += 1;
         } else {
           cnt[C_NULL] += 1;
@@ -362,22 +496,157 @@ __global__ __launch_bounds__(256) void k_push_mc(int n, double *X0, double *X1, 
     species[i] = (int8_t)sp;
     status[i] = (int8_t)st;
     hit[i] = hcell;
-    n_child[i] = nc;
-    if (st == 1) {
-      cnt[C_ABS] += 1;
-      if (G.kind[hcell] == 1) {
-        atomicAdd((unsigned long long *)&dd_counts[hcell], (unsigned long long)(long long)(sp == 1 ? 1 : -1));
-        cnt[C_DD] += 1;
-      }
-    } else if (st == 2) {
+    n_child[i] = K.nc;
+    if (st == 1)
+      absorb(G, hcell, sp, dd_counts, cnt);
+    else if (st == 2)
       cnt[C_LEFT] += 1;
+  }
+  flush_counts(cnt, sc, counters);
+}
+
+// Flight of duration tau for the live particles (dead == 0, status == 0):
+// constant acceleration q E / m (E0 == NULL: straight drift), chord tested
+// for absorption, then the world box.  The Euler stepper is one such flight
+// in the start field; a PEFRL drift is one straight flight.
+__global__ __launch_bounds__(256) void k_flight(int n, double *X0, double *X1, double *X2, double *V0, double *V1,
+                                                double *V2, const int8_t *__restrict__ species,
+                                                const double *__restrict__ E0, const double *__restrict__ E1,
+                                                const double *__restrict__ E2, const uint8_t *__restrict__ dead,
+                                                GasDev g, StepDev p, GridDev G, double tau, int8_t *status,
+                                                int32_t *hit, int64_t *dd_counts, unsigned long long *counters) {
+  __shared__ unsigned long long sc[NCNT];
+  if (threadIdx.x < NCNT) sc[threadIdx.x] = 0;
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  int cnt[NCNT];
+#pragma unroll
+  for (int k = 0; k < NCNT; ++k) cnt[k] = 0;
+  if (i < n && !dead[i] && status[i] == 0) {
+    const int sp = species[i];
+    const double m = (sp == 0) ? kMe : (sp == 1 ? g.m_cation : g.m_anion);
+    const double q = (sp == 1) ? kQe : -kQe;
+    const double X[3] = {X0[i], X1[i], X2[i]};
+    const double Vv[3] = {V0[i], V1[i], V2[i]};
+    const double Ef[3] = {E0 ? E0[i] : 0.0, E0 ? E1[i] : 0.0, E0 ? E2[i] : 0.0};
+    double Xn[3], Vn[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double acc = E0 ? q * Ef[d] / m : 0.0;
+      Xn[d] = X[d] + Vv[d] * tau + 0.5 * acc * tau * tau;
+      Vn[d] = Vv[d] + acc * tau;
+    }
+    const int h = first_hit(G, X, Xn);
+    if (h >= 0) {
+      status[i] = 1;
+      hit[i] = h;
+      absorb(G, h, sp, dd_counts, cnt);
+    } else {
+      X0[i] = Xn[0];
+      X1[i] = Xn[1];
+      X2[i] = Xn[2];
+      V0[i] = Vn[0];
+      V1[i] = Vn[1];
+      V2[i] = Vn[2];
+      if (outside(p, Xn)) {
+        status[i] = 2;
+        cnt[C_LEFT] += 1;
+      }
     }
   }
-#pragma unroll
-  for (int k = 0; k < NCNT; ++k)
-    if (cnt[k]) atomicAdd(&sc[k], (unsigned long long)cnt[k]);
+  flush_counts(cnt, sc, counters);
+}
+
+// PEFRL kick: v += c dt q E / m for the live particles.
+__global__ __launch_bounds__(256) void k_kick(int n, double *V0, double *V1, double *V2,
+                                              const int8_t *__restrict__ species, const double *__restrict__ E0,
+                                              const double *__restrict__ E1, const double *__restrict__ E2,
+                                              const uint8_t *__restrict__ dead, const int8_t *__restrict__ status,
+                                              GasDev g, double cdt) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n || dead[i] || status[i] != 0) return;
+  const int sp = species[i];
+  const double m = (sp == 0) ? kMe : (sp == 1 ? g.m_cation : g.m_anion);
+  const double q = (sp == 1) ? kQe : -kQe;
+  V0[i] += cdt * (q / m * E0[i]);
+  V1[i] += cdt * (q / m * E1[i]);
+  V2[i] += cdt * (q / m * E2[i]);
+}
+
+// Per-step collision model of section 3.4.2: each live particle collides with
+// probability 1 - exp(-nu_tot dt) (gas at rest), the process chosen with
+// probabilities nu_k / nu_tot from one draw (counter (id, step, 0)); the
+// interactions are those of the null-collision step, at the end point.
+__global__ __launch_bounds__(256) void k_collide_step(int n, double *X0, double *X1, double *X2, double *V0,
+                                                      double *V1, double *V2, int8_t *species,
+                                                      const int64_t *__restrict__ id, const uint8_t *__restrict__ dead,
+                                                      GasDev g, StepDev p, const int8_t *__restrict__ status,
+                                                      int32_t *n_child, double *child, unsigned long long *counters) {
+  __shared__ unsigned long long sc[NCNT];
+  if (threadIdx.x < NCNT) sc[threadIdx.x] = 0;
   __syncthreads();
-  if (threadIdx.x < NCNT && sc[threadIdx.x]) atomicAdd(&counters[threadIdx.x], sc[threadIdx.x]);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  int cnt[NCNT];
+#pragma unroll
+  for (int k = 0; k < NCNT; ++k) cnt[k] = 0;
+  if (i < n) n_child[i] = 0;
+  if (i < n && !dead[i] && status[i] == 0) {
+    double X[3] = {X0[i], X1[i], X2[i]};
+    double Vv[3] = {V0[i], V1[i], V2[i]};
+    const int sp = species[i];
+    const uint64_t pid = (uint64_t)id[i];
+    const uint2 key = make_uint2(p.key0, p.key1);
+    Kids K = {child, p.max_ion, i, 0};
+    const uint4 w = philox10(make_uint4((uint32_t)pid, (uint32_t)(pid >> 32), p.step, 0u), key);
+    const double v2 = Vv[0] * Vv[0] + Vv[1] * Vv[1] + Vv[2] * Vv[2];
+    const double vm = sqrt(v2);
+    const double u0 = u01(w.x), u1 = u01(w.y), u2 = u01(w.z), u3 = u01(w.w);
+    bool changed = false;
+    if (sp == 0) {
+      const double eps = 0.5 * kMe * v2 / kQe;
+      double nuk[5], tot = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < 5; ++kk) {
+        nuk[kk] = g.density * xs_at(g, kk, eps) * vm;
+        tot += nuk[kk];
+      }
+      if (!(u0 < -expm1(-tot * p.dt))) {
+        cnt[C_NULL] += 1;
+      } else {
+        const double sel = u1 * tot;
+        double cum = 0.0;
+        int proc = -1;
+#pragma unroll
+        for (int kk = 0; kk < 5; ++kk) {
+          cum += nuk[kk];
+          if (proc < 0 && sel < cum) proc = kk;
+        }
+        if (proc < 0) proc = 4;
+        cnt[C_EL + proc] += 1;
+        if (electron_interaction(g, proc, eps, X, Vv, u2, u3, pid, p.step, key, 0u, K, cnt)) species[i] = 2;
+        changed = true;
+      }
+    } else {
+      const double nui = g.density * g.ion_iso * vm, nub = g.density * g.ion_back * vm;
+      if (!(u0 < -expm1(-(nui + nub) * p.dt))) {
+        cnt[C_NULL] += 1;
+      } else {
+        ion_interaction(g, sp, (u1 * (nui + nub) < nui) ? 0 : 1, Vv, u2, u3, pid, p.step, key, 0u);
+        cnt[C_ION] += 1;
+        changed = true;
+      }
+    }
+    if (changed) {
+      X0[i] = X[0];
+      X1[i] = X[1];
+      X2[i] = X[2];
+      V0[i] = Vv[0];
+      V1[i] = Vv[1];
+      V2[i] = Vv[2];
+    }
+    n_child[i] = K.nc;
+  }
+  flush_counts(cnt, sc, counters);
 }
 
 // ---------------------------------------------------------------------------
@@ -426,17 +695,22 @@ __global__ __launch_bounds__(256) void k_species_key(int n, const int32_t *__res
 // each carry one charge, which the pairwise kernel takes out of the inner
 // loop, and are spatially compact, so the nearest-partner search can skip
 // tiles farther than the recombination radius.
+// Particles removed earlier in the step (dead, or status != 0 when given)
+// keep their slot with charge 0.
 __global__ __launch_bounds__(256) void k_gather_sources(int n, const int32_t *__restrict__ perm,
                                                         const double *__restrict__ x, const double *__restrict__ y,
                                                         const double *__restrict__ z, const int8_t *__restrict__ sp,
-                                                        double *out, int8_t *sp_out) {
+                                                        const uint8_t *__restrict__ dead,
+                                                        const int8_t *__restrict__ status, double *out,
+                                                        int8_t *sp_out) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const int j = perm[i];
+  const bool gone = (dead && dead[j]) || (status && status[j] != 0);
   out[i] = x[j];
   out[(size_t)n + i] = y[j];
   out[2 * (size_t)n + i] = z[j];
-  out[3 * (size_t)n + i] = (sp[j] == 1) ? kQe : -kQe;
+  out[3 * (size_t)n + i] = gone ? 0.0 : ((sp[j] == 1) ? kQe : -kQe);
   sp_out[i] = sp[j];
 }
 
@@ -466,6 +740,16 @@ __global__ __launch_bounds__(256) void k_tile_boxes(int n, const double *__restr
 }
 
 __global__ __launch_bounds__(256) void k_fill_u64(int n, unsigned long long *p, unsigned long long v) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_fill_i8(int n, int8_t *p) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_fill_i32(int n, int32_t *p, int32_t v) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < n) p[i] = v;
 }
@@ -634,9 +918,70 @@ static obem_status build_grid(obem_ctx *ctx, obem_meshh *m) {
 
 static inline int nbt(int64_t n) { return (int)((n + 255) / 256); }
 
+// Field at every particle from the set-up (cells with sigma, or the map) and
+// from all charges still in the step (dead / status mask, may be NULL),
+// into E (3 x n, caller order).  With nn (int32 x n) also the nearest
+// opposite-species partner (within r_rec in mixed precision), caller index
+// or -1.  The sources are a copy ordered by species, then Morton.
+static obem_status step_field(obem_ctx *ctx, obem_meshh *mesh, const double *sigma, const MapDev *map,
+                              const obem_particles *S, int n, const obem_step_params *p, const uint8_t *dead,
+                              const int8_t *status, double *E, int32_t *nn) {
+  const size_t nz = (size_t)n;
+  uint8_t *skey = (uint8_t *)ws_get(ctx, WS_SRCKEY, 2 * nz + 64);
+  int32_t *sperm = (int32_t *)ws_get(ctx, WS_SRCPERM, sizeof(int32_t) * 2 * nz);
+  double *srcb = (double *)ws_get(ctx, WS_SRC, sizeof(double) * 4 * nz + nz + 64);
+  double *acc = (double *)ws_get(ctx, WS_ACC, sizeof(double) * 4 * nz);
+  const int ntile = nbt(n);
+  double *tbox = (double *)ws_get(ctx, WS_TBOX, sizeof(double) * 6 * (size_t)ntile);
+  int32_t *nn_s = nn ? (int32_t *)ws_get(ctx, WS_MISC0, sizeof(int32_t) * nz) : nullptr;
+  double *nnd = nn ? (double *)ws_get(ctx, WS_MISC3, sizeof(double) * nz) : nullptr;
+  if (!skey || !sperm || !srcb || !acc || !tbox || (nn && (!nn_s || !nnd)))
+    return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  int8_t *ssp = (int8_t *)(srcb + 4 * nz);
+  TargetOrder to;
+  obem_status st = order_targets(ctx, n, S->x, S->y, S->z, &to);
+  if (st) return st;
+  hipLaunchKernelGGL(k_species_key, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, to.perm, S->species, skey, sperm);
+  size_t tb = 0;
+  OBEM_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, tb, skey, skey + nz, sperm, sperm + nz, n, 0, 2,
+                                                   ctx->stream));
+  void *tmp = ws_get(ctx, WS_SORT_TMP2, tb + 256);
+  if (!tmp) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  OBEM_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(tmp, tb, skey, skey + nz, sperm, sperm + nz, n, 0, 2,
+                                                   ctx->stream));
+  hipLaunchKernelGGL(k_gather_sources, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, sperm + nz, S->x, S->y, S->z,
+                     S->species, dead, status, srcb, ssp);
+  if (nn) hipLaunchKernelGGL(k_tile_boxes, dim3(ntile), dim3(256), 0, ctx->stream, n, srcb, tbox);
+  OBEM_HIP(ctx, hipGetLastError());
+  if (map)
+    st = launch_map_acc(ctx, *map, to, acc);
+  else
+    st = mesh ? launch_panel_field(ctx, mesh, sigma, to, p->precision, false, acc) : launch_fill(ctx, acc, 4 * nz, 0.0);
+  if (st) return st;
+  st = launch_pair_field(ctx, n, srcb, srcb + nz, srcb + 2 * nz, srcb + 3 * nz, to, p->soft, p->precision, true,
+                         false, S->species, ssp, acc, nn_s, nnd, nn ? tbox : nullptr, p->r_rec);
+  if (st) return st;
+  st = launch_scatter(ctx, to, acc, kKe, E, E + nz, E + 2 * nz, nullptr);
+  if (st) return st;
+  if (nn) hipLaunchKernelGGL(k_scatter_nn, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, to.perm, nn_s, sperm + nz, nn);
+  OBEM_HIP(ctx, hipGetLastError());
+  return OBEM_OK;
+}
+
 }  // namespace obem
 
 using namespace obem;
+
+// PEFRL coefficients (Omelyan, Mryglod, Folk, Comput. Phys. Commun. 146
+// (2002) 188).
+static constexpr double kPefrlXi = 0.1786178958448091;
+static constexpr double kPefrlLambda = -0.2123418310626054;
+static constexpr double kPefrlChi = -0.06626458266981849;
+
+static obem_status compact_step(obem_ctx *ctx, obem_particles *S, int n, int mi, const uint8_t *dead,
+                                const int8_t *status, const int32_t *nchild, const double *child, int32_t *keep,
+                                int32_t *kids, const unsigned long long *cnt_dev, obem_step_stats out,
+                                obem_step_stats *stats);
 
 extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particles *S, const obem_gas *gas,
                                   const obem_step_params *p, int64_t *dd_counts, double *sigma,
@@ -654,15 +999,24 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
       !(p->soft >= 0.0) || !(p->r_rec >= 0.0) || !(p->ion_v_cap >= 0.0))
     return fail(ctx, OBEM_EINVAL, "bad step parameters");
   if (p->precision != OBEM_FP64 && p->precision != OBEM_MIXED) return fail(ctx, OBEM_EINVAL, "bad precision");
+  if (p->stepper != OBEM_NULL_COLLISION && p->stepper != OBEM_EULER && p->stepper != OBEM_PEFRL)
+    return fail(ctx, OBEM_EINVAL, "bad stepper");
+  if (gas->xi && !is_device_ptr(gas->xi)) return fail(ctx, OBEM_EINVAL, "gas->xi must be device memory");
+  if (!(gas->penning_prob >= 0.0 && gas->penning_prob <= 1.0)) return fail(ctx, OBEM_EINVAL, "bad penning_prob");
   if (gas->n_nodes < 2 || !(gas->e_max > gas->e_min) || !(gas->e_min > 0.0) || !is_device_ptr(gas->xs))
     return fail(ctx, OBEM_EINVAL, "bad gas tables");
   void *arrs[] = {S->x, S->y, S->z, S->vx, S->vy, S->vz, S->species, S->id};
   for (void *a : arrs)
     if (!is_device_ptr(a)) return fail(ctx, OBEM_EINVAL, "particle arrays must be device memory");
   if (mesh) {
-    if (!is_device_ptr(sigma)) return fail(ctx, OBEM_EINVAL, "sigma must be device memory");
+    if (!p->map && !is_device_ptr(sigma)) return fail(ctx, OBEM_EINVAL, "sigma must be device memory");
     if (mesh->n_dd && !is_device_ptr(dd_counts)) return fail(ctx, OBEM_EINVAL, "dd_counts must be device memory");
     if (p->resolve && !is_device_ptr(p->rhs0)) return fail(ctx, OBEM_EINVAL, "rhs0 must be device memory");
+  }
+  MapDev gmap;
+  if (p->map) {
+    if (!map_dev(p->map, &gmap)) return fail(ctx, OBEM_EINVAL, "bad field map");
+    if (p->resolve) return fail(ctx, OBEM_EINVAL, "the static field map excludes the re-solve");
   }
   obem_status st;
   const int n = (int)S->n_live;
@@ -699,51 +1053,14 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
   // scratch
   const int mi = p->max_ion_per_step;
   const size_t nz = (size_t)n;
-  double *q = (double *)ws_get(ctx, WS_MISC4, sizeof(double) * nz);
   double *E = (double *)ws_get(ctx, WS_MISC5, sizeof(double) * 3 * nz);
-  int32_t *nn_s = (int32_t *)ws_get(ctx, WS_MISC0, sizeof(int32_t) * nz);
-  double *nnd = (double *)ws_get(ctx, WS_MISC3, sizeof(double) * nz);
   int32_t *nn = (int32_t *)ws_get(ctx, WS_MISC1, sizeof(int32_t) * nz * 4 + 64);
-  if (!q || !E || !nn_s || !nnd || !nn) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  int8_t *status = (int8_t *)ws_get(ctx, WS_STATUS, nz + 64);
+  if (!E || !nn || !status) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
   int32_t *keep = nn + nz, *kids = nn + 2 * nz, *hitv = nn + 3 * nz;
-  // 2. field at every particle (cells + all other particles) and nearest partner
-  (void)q;
-  uint8_t *skey = (uint8_t *)ws_get(ctx, WS_SRCKEY, 2 * nz + 64);
-  int32_t *sperm = (int32_t *)ws_get(ctx, WS_SRCPERM, sizeof(int32_t) * 2 * nz);
-  double *srcb = (double *)ws_get(ctx, WS_SRC, sizeof(double) * 4 * nz + nz + 64);
-  if (!skey || !sperm || !srcb) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
-  int8_t *ssp = (int8_t *)(srcb + 4 * nz);
-  TargetOrder to;
-  st = order_targets(ctx, n, S->x, S->y, S->z, &to);
+  // 2. field at every particle (cells or map + all other particles) and nearest partner
+  st = step_field(ctx, mesh, sigma, p->map ? &gmap : nullptr, S, n, p, nullptr, nullptr, E, nn);
   if (st) return st;
-  const int ntile = nbt(n);
-  double *tbox = (double *)ws_get(ctx, WS_TBOX, sizeof(double) * 6 * (size_t)ntile);
-  if (!tbox) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
-  {
-    hipLaunchKernelGGL(k_species_key, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, to.perm, S->species, skey, sperm);
-    size_t tb = 0;
-    OBEM_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, tb, skey, skey + nz, sperm, sperm + nz, n, 0, 2,
-                                                     ctx->stream));
-    void *tmp = ws_get(ctx, WS_SORT_TMP2, tb + 256);
-    if (!tmp) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
-    OBEM_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(tmp, tb, skey, skey + nz, sperm, sperm + nz, n, 0, 2,
-                                                     ctx->stream));
-    hipLaunchKernelGGL(k_gather_sources, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, sperm + nz, S->x, S->y, S->z,
-                       S->species, srcb, ssp);
-    hipLaunchKernelGGL(k_tile_boxes, dim3(ntile), dim3(256), 0, ctx->stream, n, srcb, tbox);
-    OBEM_HIP(ctx, hipGetLastError());
-  }
-  const int32_t *src_perm = sperm + nz;
-  double *acc = (double *)ws_get(ctx, WS_ACC, sizeof(double) * 4 * nz);
-  if (!acc) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
-  st = mesh ? launch_panel_field(ctx, mesh, sigma, to, p->precision, false, acc) : launch_fill(ctx, acc, 4 * nz, 0.0);
-  if (st) return st;
-  st = launch_pair_field(ctx, n, srcb, srcb + nz, srcb + 2 * nz, srcb + 3 * nz, to, p->soft, p->precision, true,
-                         false, S->species, ssp, acc, nn_s, nnd, tbox, p->r_rec);
-  if (st) return st;
-  st = launch_scatter(ctx, to, acc, kKe, E, E + nz, E + 2 * nz, nullptr);
-  if (st) return st;
-  hipLaunchKernelGGL(k_scatter_nn, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, to.perm, nn_s, src_perm, nn);
   // 3. recombination
   unsigned long long *key = (unsigned long long *)ws_get(ctx, WS_MISC2, sizeof(unsigned long long) * 2 * nz);
   uint8_t *dead = (uint8_t *)ws_get(ctx, WS_MISC6, nz + 64);
@@ -774,6 +1091,9 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
   g.m_anion = gas->m_anion;
   g.ion_iso = gas->ion_xs_iso;
   g.ion_back = gas->ion_xs_back;
+  g.xi = gas->xi;
+  g.pen_prob = gas->penning_prob;
+  g.pen_level = gas->penning_level;
   double *nu_dev = (double *)ws_get(ctx, WS_SOLVE2 + 0, 64);
   unsigned long long *cnt_dev = (unsigned long long *)ws_get(ctx, WS_SOLVE1 + 0, 256);
   if (!nu_dev || !cnt_dev) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
@@ -809,18 +1129,67 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
     G.f = mesh->f;
     G.kind = mesh->kind;
   }
-  int8_t *status = (int8_t *)ws_get(ctx, WS_MISC7, nz + 64);
-  double *child = (double *)ws_get(ctx, WS_PART, sizeof(double) * 12 * (size_t)std::max(mi, 1) * nz);
-  int32_t *nchild = (int32_t *)ws_get(ctx, WS_NN, sizeof(int32_t) * nz + 64);
-  if (!status || !child || !nchild) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
-  {
-  OBEM_PROF(ctx, "push_mc");
-  hipLaunchKernelGGL(k_push_mc, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->x, S->y, S->z, S->vx, S->vy, S->vz,
-                     S->species, S->id, E, E + nz, E + 2 * nz, dead, g, sd, G, status, hitv, nchild, child,
-                     dd_counts, cnt_dev);
+  if (p->stepper == OBEM_NULL_COLLISION) {
+    double *child = (double *)ws_get(ctx, WS_PART, sizeof(double) * 12 * (size_t)std::max(mi, 1) * nz);
+    int32_t *nchild = (int32_t *)ws_get(ctx, WS_NN, sizeof(int32_t) * nz + 64);
+    if (!child || !nchild) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+    {
+      OBEM_PROF(ctx, "push_mc");
+      hipLaunchKernelGGL(k_push_mc, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->x, S->y, S->z, S->vx, S->vy,
+                         S->vz, S->species, S->id, E, E + nz, E + 2 * nz, dead, g, sd, G, status, hitv, nchild, child,
+                         dd_counts, cnt_dev);
+    }
+    OBEM_HIP(ctx, hipGetLastError());
+    return compact_step(ctx, S, n, mi, dead, status, nchild, child, keep, kids, cnt_dev, out, stats);
+  }
+  hipLaunchKernelGGL(k_fill_i8, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, status);
+  hipLaunchKernelGGL(k_fill_i32, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, hitv, -1);
+  if (p->stepper == OBEM_EULER) {
+    OBEM_PROF(ctx, "push");
+    hipLaunchKernelGGL(k_flight, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->x, S->y, S->z, S->vx, S->vy, S->vz,
+                       S->species, E, E + nz, E + 2 * nz, dead, g, sd, G, p->dt, status, hitv, dd_counts, cnt_dev);
+  } else {
+    // PEFRL (Omelyan, Mryglod, Folk 2002): drifts and kicks, the field
+    // re-evaluated after each of the first four drifts at the new positions
+    // from the set-up and the charges still in the step
+    const double dr[5] = {kPefrlXi, kPefrlChi, 1.0 - 2.0 * (kPefrlChi + kPefrlXi), kPefrlChi, kPefrlXi};
+    const double kc[4] = {0.5 * (1.0 - 2.0 * kPefrlLambda), kPefrlLambda, kPefrlLambda,
+                          0.5 * (1.0 - 2.0 * kPefrlLambda)};
+    for (int s_ = 0; s_ < 5; ++s_) {
+      {
+        OBEM_PROF(ctx, "push");
+        hipLaunchKernelGGL(k_flight, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->x, S->y, S->z, S->vx, S->vy,
+                           S->vz, S->species, (const double *)nullptr, (const double *)nullptr,
+                           (const double *)nullptr, dead, g, sd, G, dr[s_] * p->dt, status, hitv, dd_counts, cnt_dev);
+        OBEM_HIP(ctx, hipGetLastError());
+      }
+      if (s_ == 4) break;
+      st = step_field(ctx, mesh, sigma, p->map ? &gmap : nullptr, S, n, p, dead, status, E, nullptr);
+      if (st) return st;
+      hipLaunchKernelGGL(k_kick, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->vx, S->vy, S->vz, S->species, E,
+                         E + nz, E + 2 * nz, dead, status, g, kc[s_] * p->dt);
+    }
   }
   OBEM_HIP(ctx, hipGetLastError());
-  // 5. compaction: survivors in id order, then children in parent order
+  double *child = (double *)ws_get(ctx, WS_PART, sizeof(double) * 12 * (size_t)std::max(mi, 1) * nz);
+  int32_t *nchild = (int32_t *)ws_get(ctx, WS_NN, sizeof(int32_t) * nz + 64);
+  if (!child || !nchild) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  {
+    OBEM_PROF(ctx, "collide");
+    hipLaunchKernelGGL(k_collide_step, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, S->x, S->y, S->z, S->vx, S->vy,
+                       S->vz, S->species, S->id, dead, g, sd, status, nchild, child, cnt_dev);
+  }
+  OBEM_HIP(ctx, hipGetLastError());
+  return compact_step(ctx, S, n, mi, dead, status, nchild, child, keep, kids, cnt_dev, out, stats);
+}
+
+// 5. compaction: survivors in id order, then children in parent order; the
+// step's statistics.
+static obem_status compact_step(obem_ctx *ctx, obem_particles *S, int n, int mi, const uint8_t *dead,
+                                const int8_t *status, const int32_t *nchild, const double *child, int32_t *keep,
+                                int32_t *kids, const unsigned long long *cnt_dev, obem_step_stats out,
+                                obem_step_stats *stats) {
+  const size_t nz = (size_t)n;
   hipLaunchKernelGGL(k_keep, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, dead, status, nchild, keep, kids);
   int32_t *kpos = (int32_t *)ws_get(ctx, WS_KEYS0, sizeof(int32_t) * nz);
   int32_t *cpos = (int32_t *)ws_get(ctx, WS_KEYS1, sizeof(int32_t) * nz);
@@ -880,6 +1249,7 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
   out.rate_overflow = (int64_t)hc[C_OVF];
   out.flight_cap = (int64_t)hc[C_CAP];
   out.dd_charge_deposited = (int64_t)hc[C_DD];
+  out.penning = (int64_t)hc[C_PEN];
   S->n_live = n_surv + take;
   S->next_id += take;
   out.n_live = S->n_live;

@@ -38,18 +38,30 @@ def _scenario(seed=0):
     return m, dict(x=x, v=v, species=sp.astype(np.int8), id=ids, next_id=n)
 
 
-def _params(step, prec, cap=20000):
-    return dict(dt=1e-12, step=step, seed=5, max_coll=64, max_ion_per_step=4, ion_v_cap=2e4,
+def _params(step, prec, cap=20000, dt=1e-12, stepper=0):
+    return dict(dt=dt, step=step, seed=5, max_coll=64, max_ion_per_step=4, ion_v_cap=2e4,
                 box_lo=(-1e-3, -1e-3, 0.0), box_hi=(1e-3, 1e-3, 1e-3), soft=1e-7, r_rec=1e-6, capacity=cap,
-                precision=prec, resolve=1 if step > 0 else 0)
+                precision=prec, resolve=1 if step > 0 else 0, stepper=stepper)
 
 
-@pytest.mark.parametrize("influence", [False, True])
-def test_track_step_fp64_exact_stream(ctx, orc, influence):
-    """With influence, each re-solve also carries the particles' influence on
-    the cell equations (section 3.3.2)."""
+# (influence, stepper, dt, gas): the null-collision step with and without the
+# particles' influence on the re-solve (section 3.3.2); with the anisotropic
+# elastic angle and Penning transfer; Euler and PEFRL with the per-step
+# collision test at 25 fs (sections 3.3.5, 3.4.2)
+STREAMS = {
+    "null": (False, 0, 1e-12, dict()),
+    "null_influence": (True, 0, 1e-12, dict()),
+    "null_aniso_penning": (False, 0, 1e-12, dict(anisotropic=True, penning_prob=0.574, penning_level=12.5)),
+    "euler_25fs": (False, 1, 25e-15, dict(anisotropic=True, penning_prob=0.574, penning_level=12.5)),
+    "pefrl_25fs": (False, 2, 25e-15, dict(anisotropic=True, penning_prob=0.574, penning_level=12.5)),
+}
+
+
+@pytest.mark.parametrize("case", list(STREAMS))
+def test_track_step_fp64_exact_stream(ctx, orc, case):
+    influence, stepper, dt, gas_kw = STREAMS[case]
     m, st0 = _scenario()
-    gas = W.synthetic_ar_co2()
+    gas = W.synthetic_ar_co2(**gas_kw)
     _, area, _, _ = orc.tri_geometry(m.a, m.b, m.c)
     sig_o, A = orc.bem_solve(m)
     counts_o = np.zeros(m.n, np.int64)
@@ -62,7 +74,7 @@ def test_track_step_fp64_exact_stream(ctx, orc, influence):
     gas_s, keep = B.gas_struct(gas, "cuda")
     state = st0
     for s in range(3):
-        p = _params(s, B.OBEM_FP64)
+        p = _params(s, B.OBEM_FP64, dt=dt, stepper=stepper)
         p["influence"] = int(influence)
         state, sig_o, counts_o, so, _ = orc.track_step(state, m, sig_o, gas, p, counts_o, rhs0=m.rhs, area=area,
                                                        A=A, resolve=bool(p["resolve"]), with_influence=influence)
@@ -83,12 +95,16 @@ def test_track_step_fp64_exact_stream(ctx, orc, influence):
         assert sg["recombined"] == so["recombined"]
         assert sg["absorbed"] == so["absorbed"]
         assert sg["children"] == so["children"]
-    assert so["recombined"] >= 0 and counts_o.any()
+        assert sg["penning"] == so["penning"]
+    assert so["recombined"] >= 0
+    if stepper == 0:
+        assert counts_o.any()
     # sigma after the last re-solve agrees
     assert np.abs(host(sig_g) - sig_o).max() <= 1e-10 * np.abs(sig_o).max()
 
 
-def test_track_step_mixed_consistent_with_fp64(ctx):
+@pytest.mark.parametrize("stepper,dt", [(0, 1e-12), (2, 25e-15)])
+def test_track_step_mixed_consistent_with_fp64(ctx, stepper, dt):
     m, st0 = _scenario(1)
     gas = W.synthetic_ar_co2()
     gas_s, keep = B.gas_struct(gas, "cuda")
@@ -102,7 +118,7 @@ def test_track_step_mixed_consistent_with_fp64(ctx):
         counts = torch.zeros(m.n, dtype=torch.int64, device="cuda")
         tot = np.zeros(5)
         for s in range(4):
-            sg = B.track_step(ctx, bm, parts, gas_s, _params(s, prec), counts, sig, rhs0)
+            sg = B.track_step(ctx, bm, parts, gas_s, _params(s, prec, dt=dt, stepper=stepper), counts, sig, rhs0)
             tot += np.array(sg["real_collisions"])
         res[prec] = (parts.n_live, tot)
     (n64, t64), (n32, t32) = res[B.OBEM_FP64], res[B.OBEM_MIXED]
