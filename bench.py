@@ -51,8 +51,10 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the translation unit that holds the pairwise kernel (and the
+    cell integrals it includes)."""
     h = hashlib.sha256()
-    for f in ("field.hip", "cellmath.hpp", "obem_internal.hpp"):
+    for f in ("field.hip", "cellmath.hpp"):
         with open(os.path.join(ROOT, "paper_2110_09214_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
