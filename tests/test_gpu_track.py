@@ -181,3 +181,51 @@ def test_recombination_of_planted_pairs(ctx, orc, prec):
     assert sg["recombined"] == 2 * n_pair
     ids = host(parts.state()["id"])
     assert np.array_equal(np.sort(ids), np.sort(np.arange(n)[~dead]))
+
+
+def test_full_size_cloud_step_invariants(ctx):
+    """The benchmarked step at full size (4M charges, 40,776 cells, mixed):
+    particle accounting, id order, and the recombination rule checked on
+    sampled electrons against an FP64 brute-force nearest-cation search:
+    every removed electron had a cation within r_rec, and every survivor with
+    a cation well inside r_rec saw one of its nearby cations removed."""
+    m = W.gem_cell_mesh()
+    x, q, sp = W.space_charge_cloud()
+    n = len(q)
+    bm = bind(ctx, m)
+    rhs = dev(m.rhs)
+    sig, _ = B.bem_solve_charges(ctx, bm, rhs)
+    gas_s, keep = B.gas_struct(W.synthetic_ar_co2(), "cuda")
+    geo = W.GemGeometry()
+    top = geo.t_kapton / 2 + geo.t_cu
+    r_rec = 1e-6
+    p = dict(dt=1e-12, step=1, seed=5, max_coll=64, max_ion_per_step=4, ion_v_cap=2e4,
+             box_lo=(-geo.half_x, -geo.half_y, -(top + 2e-3)), box_hi=(geo.half_x, geo.half_y, top + 3e-3),
+             soft=1e-7, r_rec=r_rec, precision=B.OBEM_MIXED, resolve=1)
+    parts = B.Particles(n + n // 4, "cuda", dev(x), torch.zeros(n, 3, dtype=torch.float64, device="cuda"),
+                        dev(sp, torch.int8), torch.arange(n, dtype=torch.int64, device="cuda"), n)
+    counts = torch.zeros(m.n, dtype=torch.int64, device="cuda")
+    st = B.track_step(ctx, bm, parts, gas_s, p, counts, sig, rhs)
+    print("full-size step", st)
+    assert st["status"] == 0
+    assert parts.n_live == n - st["recombined"] - st["absorbed"] - st["left_world"] + st["children"]
+    ids = host(parts.state()["id"])
+    assert np.all(np.diff(ids) > 0)
+    alive = np.zeros(n, bool)
+    alive[ids[ids < n]] = True
+    assert st["recombined"] > 0 and st["recombined"] % 2 == 0
+    cations = x[sp == 1]
+    cat_idx = np.nonzero(sp == 1)[0]
+    inside = np.all((x > np.array(p["box_lo"]) + 1e-5) & (x < np.array(p["box_hi"]) - 1e-5), axis=1)
+    rng = np.random.default_rng(3)
+    elec = np.nonzero((sp == 0) & inside)[0]
+    removed = rng.choice(elec[~alive[elec]], 48, replace=False)
+    survived = rng.choice(elec[alive[elec]], 48, replace=False)
+    for e in removed:
+        d = np.sqrt(((cations - x[e]) ** 2).sum(1))
+        assert d.min() <= r_rec * (1 + 1e-5)
+    for e in survived:
+        d = np.sqrt(((cations - x[e]) ** 2).sum(1))
+        if d.min() < r_rec * (1 - 1e-5):
+            near = cat_idx[d <= r_rec * (1 + 1e-5)]
+            assert not alive[near].all()
