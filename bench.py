@@ -323,6 +323,59 @@ def main():
         log(f"[bench] gem cell: mixed {extra['gem_cell_mixed_interactions_per_s']:.3e}/s, "
             f"fp64 {extra['gem_cell_fp64_interactions_per_s']:.3e}/s, rel L2 {float(d):.2e}")
         del outs, pts
+        # double-GEM run: 200k electron-cation pairs at the central hole of the
+        # upper foil, 60,752 cells, charging-up re-solve every step; then the
+        # final-step backward dL/dsigma of L = sum w . E(x)
+        geo5 = W.GemGeometry(m=10, n_r=5, n_cone=6)
+        top5 = geo5.t_kapton / 2 + geo5.t_cu
+        m5 = W.double_gem_mesh(geo5)
+        x5, sp5 = W.double_gem_initial(geo=geo5)
+        n5 = len(sp5)
+        bm5 = bind(ctx, m5)
+        rhs5 = dev(m5.rhs)
+        t0 = time.time()
+        sig5, _ = B.bem_solve_charges(ctx, bm5, rhs5)
+        torch.cuda.synchronize()
+        t_setup5 = time.time() - t0
+        parts5 = B.Particles(2_000_000, "cuda", dev(x5), dev(np.zeros_like(x5)), dev(sp5, torch.int8),
+                             torch.arange(n5, dtype=torch.int64, device="cuda"), n5)
+        counts5 = torch.zeros(m5.n, dtype=torch.int64, device="cuda")
+        p5 = dict(dt=1e-12, step=0, seed=5, max_coll=64, max_ion_per_step=4, ion_v_cap=2e4,
+                  box_lo=(-geo5.half_x, -geo5.half_y, -2e-3 - top5 - 2e-3),
+                  box_hi=(geo5.half_x, geo5.half_y, top5 + 3e-3), soft=1e-7, r_rec=1e-6,
+                  precision=B.OBEM_MIXED, resolve=1)
+        inter5 = []
+
+        def step5():
+            nl = parts5.n_live
+            B.track_step(ctx, bm5, parts5, gas_s, p5, counts5, sig5, rhs5)
+            p5["step"] += 1
+            inter5.append(nl * (nl - 1) + nl * m5.n)
+
+        ms5, _ = timed(step5, 10, 1)
+        rate5 = sum(inter5[-10:]) / (10 * ms5 / 1e3)
+        X5 = torch.stack([c[:parts5.n_live] for c in parts5.cols[:3]], 1).contiguous()
+        Q5 = torch.full((parts5.n_live,), -W.E_CHARGE, dtype=torch.float64, device="cuda")
+        Q5[parts5.species[:parts5.n_live] == 1] = W.E_CHARGE
+        W5 = dev(np.random.default_rng(6).normal(size=(parts5.n_live, 3)))
+
+        def bwd5():
+            B.field_eval_backward(ctx, bm5, sig5, X5, Q5, X5, 1e-7, W5, B.OBEM_MIXED, tgt_is_src=True,
+                                  want_t=False, want_s=False)
+
+        ms5b, _ = timed(bwd5, 1, 1)
+        extra["double_gem_step_ms"] = ms5
+        extra["double_gem_interactions_per_s"] = rate5
+        extra["double_gem_n_live_after"] = parts5.n_live
+        extra["double_gem_dd_charges"] = int(counts5.abs().sum())
+        extra["double_gem_final_backward_ms"] = ms5b
+        extra["double_gem_workload"] = (f"{n5} charges (electron-cation pairs at the central hole of the upper "
+                                        f"foil) + {m5.n} cells, charging-up re-solve each step, mixed; 10 steps "
+                                        f"after 1, setup (assembly + LU + inverse) {t_setup5:.1f} s; then "
+                                        f"dL/dsigma of L = sum w.E")
+        log(f"[bench] double GEM: {ms5:.1f} ms per step, {rate5:.3e} interactions/s, n_live {parts5.n_live}, "
+            f"backward {ms5b:.1f} ms")
+        del bm5, parts5, X5, Q5, W5
         # adjoint bwd/fwd on 1M charges + refined mesh (synthetic cell charges)
         m4 = W.gem_cell_mesh(W.gem_cell_refined_geometry())
         x4, q4, sp4, w4 = W.adjoint_workload()

@@ -116,3 +116,20 @@ def test_gem_cell_full_size_sampled(ctx, orc, prec):
     err = rel_l2(E[idx], E_ref)
     print("gem", prec, err)
     assert err <= TOL[prec]
+
+
+def test_space_charge_cloud_full_size_sampled(ctx, orc):
+    """The benchmarked workload at full size: 4M charges (targets = sources,
+    soft 0.1 um) + 40,776 cells, mixed precision; 64 sampled charges against
+    the oracle's brute force over all charges and cells."""
+    m = W.gem_cell_mesh()
+    x, q, _ = W.space_charge_cloud()
+    bm = bind(ctx, m)
+    sig, _ = B.bem_solve_charges(ctx, bm, dev(m.rhs))
+    E = host(B.field_eval(ctx, bm, sig, dev(x), dev(q), dev(x), 1e-7, B.OBEM_MIXED, tgt_is_src=True))
+    s = host(sig)
+    rows = np.random.default_rng(9).choice(len(q), 64, replace=False)
+    ref = orc.pair_field(x[rows], x, q, 1e-7) + orc.panel_field(x[rows], m.a, m.b, m.c, s)
+    err = rel_l2(E[rows], ref)
+    print("4M cloud sampled rel L2", err)
+    assert err <= 1e-5
