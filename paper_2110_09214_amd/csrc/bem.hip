@@ -263,9 +263,24 @@ void bem_release(obem_meshh *m) {
   hipFree(m->LU);
   hipFree(m->ipiv);
   hipFree(m->info);
+  hipFree(m->ipiv64);
+  hipFree(m->info64);
   m->A = m->LU = nullptr;
   m->ipiv = m->info = nullptr;
+  m->ipiv64 = m->info64 = nullptr;
   m->factored = false;
+}
+
+// Matrices of 2^31 elements or more go through the 64-bit library entry
+// points (the 32-bit ones index the matrix with 32-bit offsets).
+static inline bool large_matrix(int N) { return (int64_t)N * N >= ((int64_t)1 << 31); }
+
+// B = identity (column-major N x N); a workgroup writes 256 rows of strided
+// columns.
+__global__ __launch_bounds__(256) void k_identity(int N, double *B) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  for (int j = blockIdx.y; j < N; j += gridDim.y) B[(size_t)j * N + i] = (i == j) ? 1.0 : 0.0;
 }
 
 // Compensated residual r = b - A x (device), chunked over columns.
@@ -286,9 +301,14 @@ obem_status bem_factor(obem_ctx *ctx, obem_meshh *m) {
   if (m->factored) return OBEM_OK;
   const int N = (int)m->n;
   const size_t bytes = sizeof(double) * (size_t)N * N;
+  const bool large = large_matrix(N);
   if (!m->A) {
-    if (hipMalloc(&m->A, bytes) != hipSuccess || hipMalloc(&m->LU, bytes) != hipSuccess ||
-        hipMalloc(&m->ipiv, sizeof(int32_t) * N) != hipSuccess || hipMalloc(&m->info, sizeof(int32_t)) != hipSuccess) {
+    bool ok = hipMalloc(&m->A, bytes) == hipSuccess && hipMalloc(&m->LU, bytes) == hipSuccess;
+    if (ok && large)
+      ok = hipMalloc(&m->ipiv64, sizeof(int64_t) * N) == hipSuccess && hipMalloc(&m->info64, sizeof(int64_t)) == hipSuccess;
+    else if (ok)
+      ok = hipMalloc(&m->ipiv, sizeof(int32_t) * N) == hipSuccess && hipMalloc(&m->info, sizeof(int32_t)) == hipSuccess;
+    if (!ok) {
       hipGetLastError();
       bem_release(m);
       return fail(ctx, OBEM_ENOMEM, "cannot allocate the %d x %d collocation matrix and its factors", N, N);
@@ -320,19 +340,29 @@ obem_status bem_factor(obem_ctx *ctx, obem_meshh *m) {
   if (st) return st;
   {
     OBEM_PROF(ctx, "lu");
-    if (rocsolver_dgetrf(h, N, N, m->LU, N, m->ipiv, m->info) != rocblas_status_success)
-      return fail(ctx, OBEM_EDEVICE, "rocsolver_dgetrf failed");
+    const rocblas_status rs = large ? rocsolver_dgetrf_64(h, N, N, m->LU, N, m->ipiv64, m->info64)
+                                    : rocsolver_dgetrf(h, N, N, m->LU, N, m->ipiv, m->info);
+    if (rs != rocblas_status_success) return fail(ctx, OBEM_EDEVICE, "rocsolver_dgetrf failed");
   }
-  int32_t info = 0;
+  int64_t info = 0;
   double *dm = (double *)ws_get(ctx, WS_MISC5, 2 * sizeof(double));
   if (!dm) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
   hipLaunchKernelGGL(k_diag_minmax, dim3(1), dim3(256), 0, ctx->stream, N, m->LU, dm);
   OBEM_HIP(ctx, hipGetLastError());
   double hd[2] = {0, 0};
-  OBEM_HIP(ctx, hipMemcpyAsync(&info, m->info, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  if (large) {
+    OBEM_HIP(ctx, hipMemcpyAsync(&info, m->info64, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+  } else {
+    int32_t i32 = 0;
+    OBEM_HIP(ctx, hipMemcpyAsync(&i32, m->info, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    info = i32;
+  }
   OBEM_HIP(ctx, hipMemcpyAsync(hd, dm, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  if (info != 0) return fail(ctx, OBEM_ESINGULAR, "zero pivot U(%d,%d): collocation matrix is singular", info, info);
+  if (info != 0)
+    return fail(ctx, OBEM_ESINGULAR, "zero pivot U(%lld,%lld): collocation matrix is singular", (long long)info,
+                (long long)info);
   // a pivot at rounding level relative to the largest one: numerically singular
   // (duplicate or coincident cells)
   if (!(hd[0] > (double)N * 2.220446049250313e-16 * hd[1]))
@@ -342,14 +372,37 @@ obem_status bem_factor(obem_ctx *ctx, obem_meshh *m) {
   // inverse to re-solve cheaply whenever voltages or free charges change):
   // every later solve is one bandwidth-bound matrix-vector product, refined
   // against the stored A.
-  {
-    OBEM_PROF(ctx, "lu");
-    if (rocsolver_dgetri(h, N, m->LU, N, m->ipiv, m->info) != rocblas_status_success)
-      return fail(ctx, OBEM_EDEVICE, "rocsolver_dgetri failed");
+  if (large) {
+    // no 64-bit in-place inverse: solve L U X = P I into a third buffer,
+    // then keep X and release the factors
+    double *X = nullptr;
+    if (hipMalloc(&X, bytes) != hipSuccess) {
+      hipGetLastError();
+      return fail(ctx, OBEM_ENOMEM, "cannot allocate the %d x %d inverse", N, N);
+    }
+    hipLaunchKernelGGL(k_identity, dim3(nb(N), std::min(N, 65535)), dim3(256), 0, ctx->stream, N, X);
+    OBEM_HIP(ctx, hipGetLastError());
+    {
+      OBEM_PROF(ctx, "lu");
+      if (rocsolver_dgetrs_64(h, rocblas_operation_none, N, N, m->LU, N, m->ipiv64, X, N) != rocblas_status_success) {
+        hipFree(X);
+        return fail(ctx, OBEM_EDEVICE, "rocsolver_dgetrs failed");
+      }
+    }
+    OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    hipFree(m->LU);
+    m->LU = X;
+  } else {
+    {
+      OBEM_PROF(ctx, "lu");
+      if (rocsolver_dgetri(h, N, m->LU, N, m->ipiv, m->info) != rocblas_status_success)
+        return fail(ctx, OBEM_EDEVICE, "rocsolver_dgetri failed");
+    }
+    int32_t i32 = 0;
+    OBEM_HIP(ctx, hipMemcpyAsync(&i32, m->info, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (i32 != 0) return fail(ctx, OBEM_ESINGULAR, "inversion failed at U(%d,%d)", i32, i32);
   }
-  OBEM_HIP(ctx, hipMemcpyAsync(&info, m->info, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-  OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  if (info != 0) return fail(ctx, OBEM_ESINGULAR, "inversion failed at U(%d,%d)", info, info);
   m->factored = true;
   return OBEM_OK;
 }
@@ -361,10 +414,12 @@ static obem_status inv_apply(obem_ctx *ctx, obem_meshh *m, const double *in, dou
   if (st) return st;
   const int N = (int)m->n;
   const double one = 1.0, zero = 0.0;
-  if (rocblas_set_pointer_mode(h, rocblas_pointer_mode_host) != rocblas_status_success ||
-      rocblas_dgemv(h, trans ? rocblas_operation_transpose : rocblas_operation_none, N, N, &one, m->LU, N, in, 1,
-                    &zero, out, 1) != rocblas_status_success)
-    return fail(ctx, OBEM_EDEVICE, "rocblas_dgemv failed");
+  const rocblas_operation op = trans ? rocblas_operation_transpose : rocblas_operation_none;
+  if (rocblas_set_pointer_mode(h, rocblas_pointer_mode_host) != rocblas_status_success)
+    return fail(ctx, OBEM_EDEVICE, "rocblas_set_pointer_mode failed");
+  const rocblas_status rs = large_matrix(N) ? rocblas_dgemv_64(h, op, N, N, &one, m->LU, N, in, 1, &zero, out, 1)
+                                            : rocblas_dgemv(h, op, N, N, &one, m->LU, N, in, 1, &zero, out, 1);
+  if (rs != rocblas_status_success) return fail(ctx, OBEM_EDEVICE, "rocblas_dgemv failed");
   return OBEM_OK;
 }
 

@@ -72,6 +72,8 @@ struct obem_meshh {
   double *A = nullptr;        // n x n column-major
   double *LU = nullptr;       // n x n column-major
   int32_t *ipiv = nullptr;
+  int64_t *ipiv64 = nullptr;  // pivots and info of the 64-bit path (n^2 >= 2^31)
+  int64_t *info64 = nullptr;
   int32_t *info = nullptr;
   bool factored = false;
   double anorm_inf = 0;       // max_i sum_j |A_ij|

@@ -139,3 +139,28 @@ def test_voltage_gradient_through_solve_and_field(ctx):
             return float((B.field_eval(ctx, bm, s, None, None, x, 0.0, B.OBEM_FP64) * w).sum())
         d = (Lv(-400.0) - Lv(-600.0)) / 200.0
     assert float(v.grad) == pytest.approx(d, rel=1e-9)
+
+
+def test_double_gem_solve_beyond_2_31_elements(ctx, orc):
+    """60,752 cells (n^2 = 3.7e9 matrix elements, the 64-bit factor / inverse /
+    product path): backward error, sampled residual rows of the oracle's
+    matrix, and the transposed (adjoint) solve on the same factors."""
+    m = W.double_gem_mesh()
+    assert m.n * m.n >= 2 ** 31
+    bm = bind(ctx, m)
+    sig, info = B.bem_solve_charges(ctx, bm, dev(m.rhs), max_refine=3)
+    s = host(sig)
+    print("double GEM solve", m.n, info)
+    assert info["backward_error"] <= 1e-15
+    rng = np.random.default_rng(4)
+    rows = np.concatenate([rng.choice(np.nonzero(m.kind == 0)[0], 8, replace=False),
+                           rng.choice(np.nonzero(m.kind == 1)[0], 8, replace=False)])
+    res, absr = orc.bem_residual_rows(m, s, m.rhs, rows)
+    rel = np.abs(res) / (absr * np.abs(s).max() + np.abs(m.rhs[rows]))
+    print("double GEM residual rows", rel.max())
+    assert rel.max() <= 1e-13
+    g = np.random.default_rng(5).normal(size=m.n)
+    lam, info_t = B.bem_solve_charges_adjoint(ctx, bm, dev(g))
+    print("double GEM adjoint", info_t)
+    assert info_t["backward_error"] <= 1e-15
+    bm.release()
