@@ -327,6 +327,9 @@ typedef struct {
                            summed over the cells (resolve must then be 0); the
                            mesh, if given, still absorbs particles and collects
                            charging counts                                       */
+  double *field_out;    /* device, 3 x n_live or NULL: the field at the start
+                           positions (all Ex, then Ey, then Ez; particles in the
+                           order of the state at the call)                      */
 } obem_step_params;
 
 typedef struct {

@@ -59,7 +59,7 @@ class StepParams_t(C.Structure):
                 ("max_ion_per_step", C.c_int32), ("ion_v_cap", C.c_double), ("box_lo", C.c_double * 3),
                 ("box_hi", C.c_double * 3), ("soft", C.c_double), ("r_rec", C.c_double),
                 ("precision", C.c_int), ("resolve", C.c_int32), ("influence", C.c_int32),
-                ("rhs0", C.c_void_p), ("stepper", C.c_int32), ("map", C.c_void_p)]
+                ("rhs0", C.c_void_p), ("stepper", C.c_int32), ("map", C.c_void_p), ("field_out", C.c_void_p)]
 
 
 class FieldMap_t(C.Structure):
@@ -413,13 +413,16 @@ def induced_current(ctx: Context, x, v, species, mesh: BoundMesh = None, sigma_w
 
 
 def track_step(ctx: Context, mesh: BoundMesh, parts: Particles, gas_s, params: dict, dd_counts, sigma, rhs0=None,
-               fmap: FieldMap = None):
+               fmap: FieldMap = None, field_out=None):
+    """One tracking step (obem track_step); field_out (3 x n_live device
+    doubles) receives the field at the start positions."""
     p = StepParams_t(params["dt"], params["step"], params["seed"], params["max_coll"], params["max_ion_per_step"],
                      params["ion_v_cap"], (C.c_double * 3)(*params["box_lo"]), (C.c_double * 3)(*params["box_hi"]),
                      params["soft"], params["r_rec"], int(params.get("precision", OBEM_MIXED)),
                      int(params.get("resolve", 0)), int(params.get("influence", 0)),
                      _ptr(rhs0) if rhs0 is not None else None, int(params.get("stepper", 0)),
-                     C.cast(C.pointer(fmap.s), C.c_void_p) if fmap is not None else None)
+                     C.cast(C.pointer(fmap.s), C.c_void_p) if fmap is not None else None,
+                     _ptr(field_out, n=3 * parts.n_live, name="field_out") if field_out is not None else None)
     ps = parts.struct()
     stats = StepStats_t()
     st = ctx.lib.track_step(ctx.h, mesh.h if mesh is not None else None, C.byref(ps), C.byref(gas_s), C.byref(p),

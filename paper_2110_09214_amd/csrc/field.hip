@@ -468,6 +468,26 @@ __device__ __forceinline__ void pair_tile(const float4 *S, const int *K, int cnt
   }
 }
 
+// Far tiles of one charge (the tile's box at least 2 R_b from the box of the
+// workgroup's targets, R_b = their largest distance from the recentring
+// origin): |r - s|^2 = (|r|^2 + soft^2) + |s|^2 - 2 r.s and E = r sum(w) -
+// sum(w s), 11 VALU per pair instead of 12.  Since |s| <= |r| + |r - s|, the
+// expansion's terms are at most (1 + 2 R_b / |r - s|)^2 <= 4 times |r - s|^2,
+// which bounds its rounding error to a few ulps of |r - s|^2.
+__device__ __forceinline__ void pair_tile_far(const float4 *S2, int cnt, float m0, float m1, float m2, float a,
+                                              float &sw, float &sx, float &sy, float &sz) {
+  for (int jj = 0; jj < cnt; ++jj) {
+    const float4 s = S2[jj];
+    const float rr = fmaf(m0, s.x, fmaf(m1, s.y, fmaf(m2, s.z, a + s.w)));
+    const float ri = __builtin_amdgcn_rsqf(rr);
+    const float w = ri * (ri * ri);
+    sw += w;
+    sx = fmaf(w, s.x, sx);
+    sy = fmaf(w, s.y, sy);
+    sz = fmaf(w, s.z, sz);
+  }
+}
+
 template <bool WANT_V, bool NN, int EXCL>
 __global__ __launch_bounds__(kThreads) void k_pair_mixed(int n_t, const double *__restrict__ xs,
                                                          const int32_t *__restrict__ perm, int n_s,
@@ -480,7 +500,9 @@ __global__ __launch_bounds__(kThreads) void k_pair_mixed(int n_t, const double *
                                                          int chunk, double *part, float *nn_d2p,
                                                          int32_t *nn_ip, const double *__restrict__ tbox,
                                                          float nn_cut2) {
+  constexpr bool kFar = (EXCL == 0) && !WANT_V;  // expanded far tiles allowed
   __shared__ float4 S[kThreads];
+  __shared__ float4 S2[kFar ? kThreads : 1];
   __shared__ int K[kThreads];
   __shared__ float WB[kThreads / 64][6];
   const int tid = threadIdx.x;
@@ -492,6 +514,8 @@ __global__ __launch_bounds__(kThreads) void k_pair_mixed(int n_t, const double *
   const double x1 = active ? xs[(size_t)n_t + i] : c1;
   const double x2 = active ? xs[2 * (size_t)n_t + i] : c2;
   const float r0 = (float)(x0 - c0), r1 = (float)(x1 - c1), r2 = (float)(x2 - c2);
+  const float m0 = -2.f * r0, m1 = -2.f * r1, m2 = -2.f * r2;
+  const float a_t = fmaf(r0, r0, fmaf(r1, r1, fmaf(r2, r2, soft2)));
   int want = -2;
   if (NN && active) want = want_key(species[perm[i]]);
   const int self = active ? perm[i] : -1;
@@ -502,7 +526,7 @@ __global__ __launch_bounds__(kThreads) void k_pair_mixed(int n_t, const double *
   // box (tbox, FP64, 256-source tiles); tiles farther than the cut skip the
   // search.  Inactive lanes hold the first target, which is inside the box.
   float bl0 = r0, bl1 = r1, bl2 = r2, bh0 = r0, bh1 = r1, bh2 = r2;
-  if (NN && tbox) {
+  if ((NN || kFar) && tbox) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       bl0 = fminf(bl0, __shfl_xor(bl0, o));
@@ -527,6 +551,10 @@ __global__ __launch_bounds__(kThreads) void k_pair_mixed(int n_t, const double *
       bh2 = fmaxf(bh2, WB[k][5]);
     }
   }
+  // 4 R_b^2 (with a margin for the FP32 boxes): tiles at least this far
+  // (squared gap) take the expanded form
+  const float far2 = 4.f * (fmaxf(bl0 * bl0, bh0 * bh0) + fmaxf(bl1 * bl1, bh1 * bh1) + fmaxf(bl2 * bl2, bh2 * bh2)) *
+                         1.001f + 1e-30f;
   float hx = 0.f, hy = 0.f, hz = 0.f, hv = 0.f, lx = 0.f, ly = 0.f, lz = 0.f, lv = 0.f;
   float best = INFINITY;
   int bidx = -1;
@@ -534,19 +562,24 @@ __global__ __launch_bounds__(kThreads) void k_pair_mixed(int n_t, const double *
     const int cnt = min(kThreads, je - jt);
     const float q0 = (float)sq[jt];
     bool nn_tile = NN;
-    if (NN && tbox) {
+    bool far_tile = false;
+    if ((NN || kFar) && tbox) {
       const double *b = tbox + 6 * (size_t)(jt / kThreads);
       const float g0 = fmaxf(0.f, fmaxf((float)(b[0] - c0) - bh0, bl0 - (float)(b[3] - c0)));
       const float g1 = fmaxf(0.f, fmaxf((float)(b[1] - c1) - bh1, bl1 - (float)(b[4] - c1)));
       const float g2 = fmaxf(0.f, fmaxf((float)(b[2] - c2) - bh2, bl2 - (float)(b[5] - c2)));
-      nn_tile = fmaf(g0, g0, fmaf(g1, g1, g2 * g2)) <= nn_cut2;
+      const float gap2 = fmaf(g0, g0, fmaf(g1, g1, g2 * g2));
+      if (NN) nn_tile = gap2 <= nn_cut2;
+      far_tile = kFar && !nn_tile && gap2 >= far2;
     }
     __syncthreads();
     float qj = q0;
     if (tid < cnt) {
       const int j = jt + tid;
       qj = (float)sq[j];
-      S[tid] = make_float4((float)(sx[j] - c0), (float)(sy[j] - c1), (float)(sz[j] - c2), qj);
+      const float s0 = (float)(sx[j] - c0), s1 = (float)(sy[j] - c1), s2 = (float)(sz[j] - c2);
+      S[tid] = make_float4(s0, s1, s2, qj);
+      if (kFar) S2[tid] = make_float4(s0, s1, s2, fmaf(s0, s0, fmaf(s1, s1, s2 * s2)));
       if (NN) K[tid] = species_s[j];
     }
     // tiles of equal charges (sources grouped by species) take the charge
@@ -554,11 +587,18 @@ __global__ __launch_bounds__(kThreads) void k_pair_mixed(int n_t, const double *
     const bool uniform = __syncthreads_and(qj == q0);
     float px = 0.f, py = 0.f, pz = 0.f, pv = 0.f;
     if (uniform) {
-      if (nn_tile)
+      if (nn_tile) {
         pair_tile<WANT_V, NN, EXCL, true>(S, K, cnt, jt, r0, r1, r2, soft2, self, want, px, py, pz, pv, best, bidx);
-      else
+      } else if (kFar && far_tile) {
+        float sw = 0.f, sxx = 0.f, syy = 0.f, szz = 0.f;
+        pair_tile_far(S2, cnt, m0, m1, m2, a_t, sw, sxx, syy, szz);
+        px = fmaf(r0, sw, -sxx);
+        py = fmaf(r1, sw, -syy);
+        pz = fmaf(r2, sw, -szz);
+      } else {
         pair_tile<WANT_V, false, EXCL, true>(S, K, cnt, jt, r0, r1, r2, soft2, self, want, px, py, pz, pv, best,
                                              bidx);
+      }
       px *= q0;
       py *= q0;
       pz *= q0;

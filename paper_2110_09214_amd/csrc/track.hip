@@ -951,7 +951,7 @@ static obem_status step_field(obem_ctx *ctx, obem_meshh *mesh, const double *sig
                                                    ctx->stream));
   hipLaunchKernelGGL(k_gather_sources, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, sperm + nz, S->x, S->y, S->z,
                      S->species, dead, status, srcb, ssp);
-  if (nn) hipLaunchKernelGGL(k_tile_boxes, dim3(ntile), dim3(256), 0, ctx->stream, n, srcb, tbox);
+  hipLaunchKernelGGL(k_tile_boxes, dim3(ntile), dim3(256), 0, ctx->stream, n, srcb, tbox);
   OBEM_HIP(ctx, hipGetLastError());
   if (map)
     st = launch_map_acc(ctx, *map, to, acc);
@@ -959,7 +959,7 @@ static obem_status step_field(obem_ctx *ctx, obem_meshh *mesh, const double *sig
     st = mesh ? launch_panel_field(ctx, mesh, sigma, to, p->precision, false, acc) : launch_fill(ctx, acc, 4 * nz, 0.0);
   if (st) return st;
   st = launch_pair_field(ctx, n, srcb, srcb + nz, srcb + 2 * nz, srcb + 3 * nz, to, p->soft, p->precision, true,
-                         false, S->species, ssp, acc, nn_s, nnd, nn ? tbox : nullptr, p->r_rec);
+                         false, S->species, ssp, acc, nn_s, nnd, tbox, p->r_rec);
   if (st) return st;
   st = launch_scatter(ctx, to, acc, kKe, E, E + nz, E + 2 * nz, nullptr);
   if (st) return st;
@@ -1008,6 +1008,7 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
   void *arrs[] = {S->x, S->y, S->z, S->vx, S->vy, S->vz, S->species, S->id};
   for (void *a : arrs)
     if (!is_device_ptr(a)) return fail(ctx, OBEM_EINVAL, "particle arrays must be device memory");
+  if (p->field_out && !is_device_ptr(p->field_out)) return fail(ctx, OBEM_EINVAL, "field_out must be device memory");
   if (mesh) {
     if (!p->map && !is_device_ptr(sigma)) return fail(ctx, OBEM_EINVAL, "sigma must be device memory");
     if (mesh->n_dd && !is_device_ptr(dd_counts)) return fail(ctx, OBEM_EINVAL, "dd_counts must be device memory");
@@ -1061,6 +1062,8 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
   // 2. field at every particle (cells or map + all other particles) and nearest partner
   st = step_field(ctx, mesh, sigma, p->map ? &gmap : nullptr, S, n, p, nullptr, nullptr, E, nn);
   if (st) return st;
+  if (p->field_out)
+    OBEM_HIP(ctx, hipMemcpyAsync(p->field_out, E, sizeof(double) * 3 * nz, hipMemcpyDeviceToDevice, ctx->stream));
   // 3. recombination
   unsigned long long *key = (unsigned long long *)ws_get(ctx, WS_MISC2, sizeof(unsigned long long) * 2 * nz);
   uint8_t *dead = (uint8_t *)ws_get(ctx, WS_MISC6, nz + 64);

@@ -8,7 +8,7 @@ import torch
 
 from paper_2110_09214_amd import binding as B
 from paper_2110_09214_amd import workloads as W
-from gpu_helpers import bind, dev, host
+from gpu_helpers import bind, dev, host, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -183,7 +183,7 @@ def test_recombination_of_planted_pairs(ctx, orc, prec):
     assert np.array_equal(np.sort(ids), np.sort(np.arange(n)[~dead]))
 
 
-def test_full_size_cloud_step_invariants(ctx):
+def test_full_size_cloud_step_invariants(ctx, orc):
     """The benchmarked step at full size (4M charges, 40,776 cells, mixed):
     particle accounting, id order, and the recombination rule checked on
     sampled electrons against an FP64 brute-force nearest-cation search:
@@ -205,8 +205,17 @@ def test_full_size_cloud_step_invariants(ctx):
     parts = B.Particles(n + n // 4, "cuda", dev(x), torch.zeros(n, 3, dtype=torch.float64, device="cuda"),
                         dev(sp, torch.int8), torch.arange(n, dtype=torch.int64, device="cuda"), n)
     counts = torch.zeros(m.n, dtype=torch.int64, device="cuda")
-    st = B.track_step(ctx, bm, parts, gas_s, p, counts, sig, rhs)
+    fo = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+    st = B.track_step(ctx, bm, parts, gas_s, p, counts, sig, rhs, field_out=fo)
     print("full-size step", st)
+    # the step's field (species/Morton source copy, partner search, far tiles
+    # in the expanded form) against the oracle on sampled charges
+    E_step = host(fo).reshape(3, n).T
+    rows = np.random.default_rng(8).choice(n, 48, replace=False)
+    ref = orc.pair_field(x[rows], x, q, 1e-7) + orc.panel_field(x[rows], m.a, m.b, m.c, host(sig))
+    err = rel_l2(E_step[rows], ref)
+    print("step field vs oracle", err)
+    assert err <= 1e-5
     assert st["status"] == 0
     assert parts.n_live == n - st["recombined"] - st["absorbed"] - st["left_world"] + st["children"]
     ids = host(parts.state()["id"])
