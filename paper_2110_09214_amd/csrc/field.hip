@@ -489,7 +489,7 @@ __device__ __forceinline__ void pair_tile_far(const float4 *S2, int cnt, float m
 }
 
 template <bool WANT_V, bool NN, int EXCL>
-__global__ __launch_bounds__(kThreads) void k_pair_mixed(int n_t, const double *__restrict__ xs,
+__global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const double *__restrict__ xs,
                                                          const int32_t *__restrict__ perm, int n_s,
                                                          const double *__restrict__ sx,
                                                          const double *__restrict__ sy,
