@@ -283,6 +283,72 @@ const char *obem_last_error(const obem_ctx *ctx) {
   return ctx->err.c_str();
 }
 
+// Device state of a bound mesh, filled step by step; on an error the caller
+// releases whatever was allocated.
+static obem_status bind_fill(obem_ctx *ctx, const obem_mesh *mesh, obem_meshh *m) {
+  const int64_t n = m->n;
+  const double *v[9] = {mesh->ax, mesh->ay, mesh->az, mesh->bx, mesh->by, mesh->bz, mesh->cx, mesh->cy, mesh->cz};
+  const int ntile = (int)((n + 63) / 64);
+  if (hipMalloc(&m->f, sizeof(double) * MF_COUNT * (size_t)n) != hipSuccess ||
+      hipMalloc(&m->kind, (size_t)n) != hipSuccess || hipMalloc(&m->tiles, sizeof(double) * 4 * ntile) != hipSuccess ||
+      hipMalloc(&m->order, sizeof(int32_t) * n) != hipSuccess) {
+    hipGetLastError();
+    return fail(ctx, OBEM_ENOMEM, "mesh allocation failed");
+  }
+  for (int k = 0; k < 9; ++k)
+    OBEM_HIP(ctx, hipMemcpyAsync(m->f + (size_t)k * n, v[k], sizeof(double) * n, hipMemcpyDeviceToDevice, ctx->stream));
+  OBEM_HIP(ctx, hipMemcpyAsync(m->kind, mesh->kind, (size_t)n, hipMemcpyDeviceToDevice, ctx->stream));
+  int *bad = (int *)ws_get(ctx, WS_MISC0, sizeof(int));
+  if (!bad) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  OBEM_HIP(ctx, hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
+  hipLaunchKernelGGL(k_mesh_derive, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, (int)n, m->f,
+                     m->kind, mesh->eps_r1, mesh->eps_r2, bad);
+  OBEM_HIP(ctx, hipGetLastError());
+  hipLaunchKernelGGL(k_tile_spheres, dim3(ntile), dim3(64), 0, ctx->stream, (int)n, m->f, m->tiles);
+  OBEM_HIP(ctx, hipGetLastError());
+  {
+    TargetOrder co;
+    obem_status st = order_targets(ctx, n, m->f + (size_t)MF_GX * n, m->f + (size_t)MF_GY * n,
+                                   m->f + (size_t)MF_GZ * n, &co);
+    if (st) return st;
+    OBEM_HIP(ctx, hipMemcpyAsync(m->order, co.perm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  int hbad = 0;
+  OBEM_HIP(ctx, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  // host copies for the bounding box and diameters
+  std::vector<double> hv((size_t)n * 9), hd((size_t)n);
+  OBEM_HIP(ctx, hipMemcpyAsync(hv.data(), m->f, sizeof(double) * 9 * n, hipMemcpyDeviceToHost, ctx->stream));
+  OBEM_HIP(ctx, hipMemcpyAsync(hd.data(), m->f + (size_t)MF_DIAM * n, sizeof(double) * n, hipMemcpyDeviceToHost,
+                               ctx->stream));
+  OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (hbad) return fail(ctx, OBEM_EINVAL, "mesh has %d degenerate or non-finite cells", hbad);
+  for (int c = 0; c < 3; ++c) {
+    m->bbox_lo[c] = INFINITY;
+    m->bbox_hi[c] = -INFINITY;
+  }
+  for (int64_t k = 0; k < n; ++k)
+    for (int vtx = 0; vtx < 3; ++vtx)
+      for (int c = 0; c < 3; ++c) {
+        double x = hv[(size_t)(3 * vtx + c) * n + k];
+        m->bbox_lo[c] = std::min(m->bbox_lo[c], x);
+        m->bbox_hi[c] = std::max(m->bbox_hi[c], x);
+      }
+  m->max_diam = *std::max_element(hd.begin(), hd.end());
+  return OBEM_OK;
+}
+
+static void free_mesh(obem_meshh *m) {
+  hipFree(m->f);
+  hipFree(m->kind);
+  hipFree(m->tiles);
+  hipFree(m->order);
+  bem_release(m);
+  hipFree(m->grid_start);
+  hipFree(m->grid_items);
+  hipGetLastError();
+  delete m;
+}
+
 obem_status obem_mesh_bind(obem_ctx *ctx, const obem_mesh *mesh, obem_meshh **out) {
   CHECK_CTX(ctx);
   if (!mesh || !out) return fail(ctx, OBEM_EINVAL, "mesh/out is NULL");
@@ -306,68 +372,11 @@ obem_status obem_mesh_bind(obem_ctx *ctx, const obem_mesh *mesh, obem_meshh **ou
   obem_meshh *m = new obem_meshh();
   m->n = n;
   m->n_dd = n_dd;
-  if (hipMalloc(&m->f, sizeof(double) * MF_COUNT * (size_t)n) != hipSuccess ||
-      hipMalloc(&m->kind, (size_t)n) != hipSuccess) {
-    hipGetLastError();
-    hipFree(m->f);
-    delete m;
-    return fail(ctx, OBEM_ENOMEM, "mesh allocation failed");
+  const obem_status st = bind_fill(ctx, mesh, m);
+  if (st) {
+    free_mesh(m);
+    return st;
   }
-  for (int k = 0; k < 9; ++k)
-    OBEM_HIP(ctx, hipMemcpyAsync(m->f + (size_t)k * n, v[k], sizeof(double) * n, hipMemcpyDeviceToDevice, ctx->stream));
-  OBEM_HIP(ctx, hipMemcpyAsync(m->kind, mesh->kind, (size_t)n, hipMemcpyDeviceToDevice, ctx->stream));
-  int *bad = (int *)ws_get(ctx, WS_MISC0, sizeof(int));
-  if (!bad) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
-  OBEM_HIP(ctx, hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
-  hipLaunchKernelGGL(k_mesh_derive, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, (int)n, m->f,
-                     m->kind, mesh->eps_r1, mesh->eps_r2, bad);
-  OBEM_HIP(ctx, hipGetLastError());
-  const int ntile = (int)((n + 63) / 64);
-  if (hipMalloc(&m->tiles, sizeof(double) * 4 * ntile) != hipSuccess) {
-    hipGetLastError();
-    return fail(ctx, OBEM_ENOMEM, "mesh allocation failed");
-  }
-  hipLaunchKernelGGL(k_tile_spheres, dim3(ntile), dim3(64), 0, ctx->stream, (int)n, m->f, m->tiles);
-  OBEM_HIP(ctx, hipGetLastError());
-  if (hipMalloc(&m->order, sizeof(int32_t) * n) != hipSuccess) {
-    hipGetLastError();
-    return fail(ctx, OBEM_ENOMEM, "mesh allocation failed");
-  }
-  {
-    TargetOrder co;
-    obem_status st = order_targets(ctx, n, m->f + (size_t)MF_GX * n, m->f + (size_t)MF_GY * n,
-                                   m->f + (size_t)MF_GZ * n, &co);
-    if (st) return st;
-    OBEM_HIP(ctx, hipMemcpyAsync(m->order, co.perm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, ctx->stream));
-  }
-  int hbad = 0;
-  OBEM_HIP(ctx, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-  // host copies for the bounding box and diameters
-  std::vector<double> hv((size_t)n * 9), hd((size_t)n);
-  OBEM_HIP(ctx, hipMemcpyAsync(hv.data(), m->f, sizeof(double) * 9 * n, hipMemcpyDeviceToHost, ctx->stream));
-  OBEM_HIP(ctx, hipMemcpyAsync(hd.data(), m->f + (size_t)MF_DIAM * n, sizeof(double) * n, hipMemcpyDeviceToHost,
-                               ctx->stream));
-  OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  if (hbad) {
-    hipFree(m->f);
-    hipFree(m->kind);
-    hipFree(m->tiles);
-    hipFree(m->order);
-    delete m;
-    return fail(ctx, OBEM_EINVAL, "mesh has %d degenerate or non-finite cells", hbad);
-  }
-  for (int c = 0; c < 3; ++c) {
-    m->bbox_lo[c] = INFINITY;
-    m->bbox_hi[c] = -INFINITY;
-  }
-  for (int64_t k = 0; k < n; ++k)
-    for (int vtx = 0; vtx < 3; ++vtx)
-      for (int c = 0; c < 3; ++c) {
-        double x = hv[(size_t)(3 * vtx + c) * n + k];
-        m->bbox_lo[c] = std::min(m->bbox_lo[c], x);
-        m->bbox_hi[c] = std::max(m->bbox_hi[c], x);
-      }
-  m->max_diam = *std::max_element(hd.begin(), hd.end());
   *out = m;
   return OBEM_OK;
 }
@@ -376,15 +385,7 @@ obem_status obem_mesh_release(obem_ctx *ctx, obem_meshh *m) {
   if (!ctx || !m) return OBEM_EINVAL;
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
-  hipFree(m->f);
-  hipFree(m->kind);
-  hipFree(m->tiles);
-  hipFree(m->order);
-  bem_release(m);
-  hipFree(m->grid_start);
-  hipFree(m->grid_items);
-  hipGetLastError();
-  delete m;
+  free_mesh(m);
   return OBEM_OK;
 }
 

@@ -164,3 +164,22 @@ def test_double_gem_solve_beyond_2_31_elements(ctx, orc):
     print("double GEM adjoint", info_t)
     assert info_t["backward_error"] <= 1e-15
     bm.release()
+
+
+def test_degenerate_cells_rejected_at_bind(ctx):
+    """A zero-area cell or a non-finite vertex is rejected (OBEM_EINVAL) and
+    the partially bound mesh is released; the context stays usable."""
+    m = W.parallel_plate_mesh(n=4)
+    for mutate in ("flat", "nan"):
+        a, b, c = m.a.copy(), m.b.copy(), m.c.copy()
+        if mutate == "flat":
+            c[3] = a[3] + 0.5 * (b[3] - a[3])   # collinear vertices
+        else:
+            b[5, 1] = np.nan
+        bad = W.Mesh(a=a, b=b, c=c, kind=m.kind, eps1=m.eps1, eps2=m.eps2, rhs=m.rhs)
+        with pytest.raises(B.ObemError) as e:
+            bind(ctx, bad)
+        assert e.value.status == -1
+    bm = bind(ctx, m)
+    sig, info = B.bem_solve_charges(ctx, bm, dev(m.rhs))
+    assert info["backward_error"] <= 1e-15
