@@ -155,12 +155,14 @@ obem_status order_targets(obem_ctx *ctx, int64_t n64, const double *tx, const do
 // Cell (panel) field
 // ---------------------------------------------------------------------------
 constexpr int kPT = 64;               // cells per LDS tile
-constexpr int kNG = 3 + 21 + 9;       // staged FP32 geometry: centroid, 7-pt and 3-pt points
 
-struct PanelTile {
-  float g[kNG][kPT];
-  float w[4][kPT];     // area*sigma*{w0, wa, wb, 1/3}
-  float lim[2][kPT];   // (3 D)^2, (64 D)^2
+// One cell of an LDS tile, recentred FP32, as 11 float4 records read whole
+// (one address per cell, 128-bit LDS reads):
+//   c[0] = centroid, (3 D)^2          c[1] = (64 D)^2, area sigma {w0, wa, wb}
+//   c[2..7] = the 7 points of the degree-5 rule (21 floats), area sigma / 3
+//   c[8..10] = the 3 points of the degree-2 rule (9 floats), 3 unused
+struct PanelCell {
+  float4 c[11];
 };
 
 __device__ __forceinline__ void neumaier(float &s, float &c, float v) {
@@ -204,7 +206,7 @@ template <bool WANT_V>
 __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double *__restrict__ xs, int N,
                                                           const double *__restrict__ f,
                                                           const double *__restrict__ sigma, double *acc) {
-  __shared__ PanelTile T;
+  __shared__ PanelCell T[kPT];
   const int tid = threadIdx.x;
   const int i0 = blockIdx.x * kThreads;
   const int i = i0 + tid;
@@ -218,64 +220,90 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
   for (int k0 = 0; k0 < N; k0 += kPT) {
     const int cnt = min(kPT, N - k0);
     __syncthreads();
-    for (int idx = tid; idx < kNG * kPT; idx += kThreads) {
-      const int fld = idx / kPT, k = idx % kPT;
+    // staging, coalesced along the cells: the 30 rule coordinates of the
+    // 64 cells, then one thread per cell for centroid, limits and weights
+    for (int idx = tid; idx < 30 * kPT; idx += kThreads) {
+      const int m = idx / kPT, k = idx % kPT;
       float v = 0.f;
       if (k < cnt) {
-        const int src = (fld < 3) ? (MF_GX + fld) : (MF_Q7 + fld - 3);
-        const int c = fld % 3;
-        const double cc = (c == 0) ? c0 : (c == 1 ? c1 : c2);
-        v = (float)(f[(size_t)src * N + k0 + k] - cc);
+        const int src = (m < 21) ? MF_Q7 + m : MF_Q3 + (m - 21);
+        const int c = (m < 21 ? m : m - 21) % 3;
+        v = (float)(f[(size_t)src * N + k0 + k] - (c == 0 ? c0 : (c == 1 ? c1 : c2)));
       }
-      T.g[fld][k] = v;
+      reinterpret_cast<float *>(&T[k])[m < 21 ? 8 + m : 32 + (m - 21)] = v;
     }
     if (tid < kPT) {
       const int k = tid;
+      float4 g = make_float4(0.f, 0.f, 0.f, 0.f), h = g;
+      float w3 = 0.f;
       if (k < cnt) {
-        const double as = f[(size_t)MF_AREA * N + k0 + k] * sigma[k0 + k];
-        const double D = f[(size_t)MF_DIAM * N + k0 + k];
-        T.w[0][k] = (float)(as * Rule7::w0);
-        T.w[1][k] = (float)(as * Rule7::wa);
-        T.w[2][k] = (float)(as * Rule7::wb);
-        T.w[3][k] = (float)(as * (1.0 / 3.0));
-        T.lim[0][k] = (float)(kNearMixed * kNearMixed * D * D);
-        T.lim[1][k] = (float)(kFar3Mixed * kFar3Mixed * D * D);
+        const int kk = k0 + k;
+        const double D = f[(size_t)MF_DIAM * N + kk];
+        const double as = f[(size_t)MF_AREA * N + kk] * sigma[kk];
+        g = make_float4((float)(f[(size_t)MF_GX * N + kk] - c0), (float)(f[(size_t)MF_GY * N + kk] - c1),
+                        (float)(f[(size_t)MF_GZ * N + kk] - c2), (float)(kNearMixed * kNearMixed * D * D));
+        h = make_float4((float)(kFar3Mixed * kFar3Mixed * D * D), (float)(as * Rule7::w0), (float)(as * Rule7::wa),
+                        (float)(as * Rule7::wb));
+        w3 = (float)(as * (1.0 / 3.0));
       }
+      T[k].c[0] = g;
+      T[k].c[1] = h;
+      reinterpret_cast<float *>(&T[k])[29] = w3;
     }
     __syncthreads();
     float px = 0.f, py = 0.f, pz = 0.f, pv = 0.f;
     for (int k = 0; k < cnt; ++k) {
-      const float R2 = dist2f(r0, r1, r2, T.g[0][k], T.g[1][k], T.g[2][k]);
-      const bool nearp = R2 < T.lim[0][k];  // taken by k_panel_near in FP64
-      const bool need7 = (!nearp) && (R2 < T.lim[1][k]);
+      const float4 g = T[k].c[0];
+      const float R2 = dist2f(r0, r1, r2, g.x, g.y, g.z);
+      const bool nearp = R2 < g.w;  // taken by k_panel_near in FP64
+      const float4 h = T[k].c[1];
+      const bool need7 = (!nearp) && (R2 < h.x);
       if (__any(need7)) {
         if (!nearp) {
+          float q[24];
 #pragma unroll
-          for (int q = 0; q < 7; ++q) {
-            const float w = T.w[q == 0 ? 0 : (q < 4 ? 1 : 2)][k];
-            const float ex = r0 - T.g[3 + 3 * q][k], ey = r1 - T.g[4 + 3 * q][k], ez = r2 - T.g[5 + 3 * q][k];
+          for (int u = 0; u < 6; ++u) {
+            const float4 t = T[k].c[2 + u];
+            q[4 * u] = t.x;
+            q[4 * u + 1] = t.y;
+            q[4 * u + 2] = t.z;
+            q[4 * u + 3] = t.w;
+          }
+#pragma unroll
+          for (int m = 0; m < 7; ++m) {
+            const float w = (m == 0) ? h.y : (m < 4 ? h.z : h.w);
+            const float ex = r0 - q[3 * m], ey = r1 - q[3 * m + 1], ez = r2 - q[3 * m + 2];
             const float rr = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
             const float ri = __builtin_amdgcn_rsqf(rr);
             const float wr = w * ri;
-            const float s = wr * (ri * ri);
-            px = fmaf(s, ex, px);
-            py = fmaf(s, ey, py);
-            pz = fmaf(s, ez, pz);
+            const float s_ = wr * (ri * ri);
+            px = fmaf(s_, ex, px);
+            py = fmaf(s_, ey, py);
+            pz = fmaf(s_, ez, pz);
             if (WANT_V) pv += wr;
           }
         }
       } else if (!nearp) {
-        const float w = T.w[3][k];
+        const float w = T[k].c[7].y;  // area sigma / 3
+        float q[12];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const float ex = r0 - T.g[24 + 3 * q][k], ey = r1 - T.g[25 + 3 * q][k], ez = r2 - T.g[26 + 3 * q][k];
+        for (int u = 0; u < 3; ++u) {
+          const float4 t = T[k].c[8 + u];
+          q[4 * u] = t.x;
+          q[4 * u + 1] = t.y;
+          q[4 * u + 2] = t.z;
+          q[4 * u + 3] = t.w;
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const float ex = r0 - q[3 * m], ey = r1 - q[3 * m + 1], ez = r2 - q[3 * m + 2];
           const float rr = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
           const float ri = __builtin_amdgcn_rsqf(rr);
           const float wr = w * ri;
-          const float s = wr * (ri * ri);
-          px = fmaf(s, ex, px);
-          py = fmaf(s, ey, py);
-          pz = fmaf(s, ez, pz);
+          const float s_ = wr * (ri * ri);
+          px = fmaf(s_, ex, px);
+          py = fmaf(s_, ey, py);
+          pz = fmaf(s_, ez, pz);
           if (WANT_V) pv += wr;
         }
       }
