@@ -432,6 +432,12 @@ obem_status field_eval(obem_ctx *ctx, const obem_meshh *mesh, const double *sigm
     REQ_DEV(ctx, sq, "sq");
   }
   if (mesh) REQ_DEV(ctx, sigma, "sigma");
+  // sources first (their ordering reuses the target-ordering workspace)
+  SourceOrder so;
+  if (n_src > 0) {
+    obem_status st = order_sources(ctx, n_src, sx, sy, sz, sq, tis, &so);
+    if (st) return st;
+  }
   TargetOrder to;
   obem_status st = order_targets(ctx, n_tgt, tx, ty, tz, &to);
   if (st) return st;
@@ -444,8 +450,8 @@ obem_status field_eval(obem_ctx *ctx, const obem_meshh *mesh, const double *sigm
   }
   if (st) return st;
   if (n_src > 0) {
-    st = launch_pair_field(ctx, n_src, sx, sy, sz, sq, to, soft, precision, tis, want_v, nullptr, nullptr, acc,
-                           nullptr, nullptr);
+    st = launch_pair_field(ctx, n_src, so.x, so.y, so.z, so.q, to, soft, precision, tis, want_v, nullptr, nullptr,
+                           acc, nullptr, nullptr, so.tbox, 0.0, tis ? so.inv : nullptr);
     if (st) return st;
   }
   return launch_scatter(ctx, to, acc, kKe, Ex, Ey, Ez, want_v ? V : nullptr);

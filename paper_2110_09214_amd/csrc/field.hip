@@ -122,6 +122,93 @@ __global__ __launch_bounds__(256) void k_gather3(int n, const int32_t *__restric
 
 static inline int nblk(int64_t n, int t = 256) { return (int)((n + t - 1) / t); }
 
+// Bounding box of each 256-source tile of the source copy (lo xyz, hi xyz).
+__global__ __launch_bounds__(256) void k_tile_boxes(int n, const double *__restrict__ src, double *box) {
+  __shared__ double red[6][4];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int k = min(i, n - 1);
+  double v[6];
+  for (int c = 0; c < 3; ++c) v[c] = v[3 + c] = src[(size_t)c * n + k];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      v[c] = fmin(v[c], __shfl_xor(v[c], o));
+      v[3 + c] = fmax(v[3 + c], __shfl_xor(v[3 + c], o));
+    }
+  if ((threadIdx.x & 63) == 0)
+    for (int c = 0; c < 6; ++c) red[c][threadIdx.x >> 6] = v[c];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int c = threadIdx.x;
+    double r = red[c][0];
+    for (int w = 1; w < 4; ++w) r = c < 3 ? fmin(r, red[c][w]) : fmax(r, red[c][w]);
+    box[6 * (size_t)blockIdx.x + c] = r;
+  }
+}
+
+void launch_tile_boxes(obem_ctx *ctx, int n, const double *src, double *box) {
+  if (n > 0) hipLaunchKernelGGL(k_tile_boxes, dim3(nblk(n)), dim3(256), 0, ctx->stream, n, src, box);
+}
+
+// Sources in (charge sign, Morton) order: key of the i-th Morton-sorted
+// source, value its caller index.
+__global__ __launch_bounds__(256) void k_charge_key(int n, const int32_t *__restrict__ perm,
+                                                    const double *__restrict__ q, uint8_t *key, int32_t *idx) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    const int j = perm[i];
+    key[i] = q[j] < 0.0 ? 0 : (q[j] > 0.0 ? 1 : 2);
+    idx[i] = j;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gather_src(int n, const int32_t *__restrict__ perm, const double *__restrict__ x,
+                                                    const double *__restrict__ y, const double *__restrict__ z,
+                                                    const double *__restrict__ q, double *out, int32_t *inv) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int j = perm[i];
+  out[i] = x[j];
+  out[(size_t)n + i] = y[j];
+  out[2 * (size_t)n + i] = z[j];
+  out[3 * (size_t)n + i] = q[j];
+  if (inv) inv[j] = i;
+}
+
+obem_status order_sources(obem_ctx *ctx, int64_t n64, const double *sx, const double *sy, const double *sz,
+                          const double *sq, bool want_inv, SourceOrder *out) {
+  const int n = (int)n64;
+  const size_t nz = (size_t)n;
+  out->n = n;
+  if (n == 0) return OBEM_OK;
+  TargetOrder mo;
+  obem_status st = order_targets(ctx, n, sx, sy, sz, &mo);
+  if (st) return st;
+  uint8_t *key = (uint8_t *)ws_get(ctx, WS_SRCKEY, 2 * nz + 64);
+  int32_t *perm = (int32_t *)ws_get(ctx, WS_SRCPERM, sizeof(int32_t) * 2 * nz);
+  double *src = (double *)ws_get(ctx, WS_SRC, sizeof(double) * 4 * nz + nz + 64);
+  double *tbox = (double *)ws_get(ctx, WS_TBOX, sizeof(double) * 6 * (size_t)nblk(n));
+  int32_t *inv = want_inv ? (int32_t *)ws_get(ctx, WS_SRCINV, sizeof(int32_t) * nz) : nullptr;
+  if (!key || !perm || !src || !tbox || (want_inv && !inv)) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  hipLaunchKernelGGL(k_charge_key, dim3(nblk(n)), dim3(256), 0, ctx->stream, n, mo.perm, sq, key, perm);
+  size_t tb = 0;
+  OBEM_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, tb, key, key + nz, perm, perm + nz, n, 0, 2, ctx->stream));
+  void *tmp = ws_get(ctx, WS_SORT_TMP2, tb + 256);
+  if (!tmp) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  OBEM_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(tmp, tb, key, key + nz, perm, perm + nz, n, 0, 2, ctx->stream));
+  hipLaunchKernelGGL(k_gather_src, dim3(nblk(n)), dim3(256), 0, ctx->stream, n, perm + nz, sx, sy, sz, sq, src, inv);
+  launch_tile_boxes(ctx, n, src, tbox);
+  OBEM_HIP(ctx, hipGetLastError());
+  out->x = src;
+  out->y = src + nz;
+  out->z = src + 2 * nz;
+  out->q = src + 3 * nz;
+  out->tbox = tbox;
+  out->inv = inv;
+  return OBEM_OK;
+}
+
 obem_status order_targets(obem_ctx *ctx, int64_t n64, const double *tx, const double *ty, const double *tz,
                           TargetOrder *out) {
   int n = (int)n64;
@@ -527,7 +614,7 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
                                                          const int8_t *__restrict__ species_s, float soft2,
                                                          int chunk, double *part, float *nn_d2p,
                                                          int32_t *nn_ip, const double *__restrict__ tbox,
-                                                         float nn_cut2) {
+                                                         float nn_cut2, const int32_t *__restrict__ self_map) {
   constexpr bool kFar = (EXCL == 0) && !WANT_V;  // expanded far tiles allowed
   __shared__ float4 S[kThreads];
   __shared__ float4 S2[kFar ? kThreads : 1];
@@ -546,7 +633,7 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
   const float a_t = fmaf(r0, r0, fmaf(r1, r1, fmaf(r2, r2, soft2)));
   int want = -2;
   if (NN && active) want = want_key(species[perm[i]]);
-  const int self = active ? perm[i] : -1;
+  const int self = active ? (self_map ? self_map[perm[i]] : perm[i]) : -1;
   const int jb = blockIdx.y * chunk;
   const int je = min(n_s, jb + chunk);
   // Nearest-partner search limited to nn_cut: bounding box of the
@@ -666,7 +753,7 @@ __global__ __launch_bounds__(kThreads) void k_pair_fp64(int n_t, const double *_
                                                         const int8_t *__restrict__ species,
                                                         const int8_t *__restrict__ species_s, double soft2,
                                                         int chunk, double *part, double *nn_d2p,
-                                                        int32_t *nn_ip) {
+                                                        int32_t *nn_ip, const int32_t *__restrict__ self_map) {
   __shared__ double4 S[kThreads];
   __shared__ int K[kThreads];
   const int tid = threadIdx.x;
@@ -676,7 +763,7 @@ __global__ __launch_bounds__(kThreads) void k_pair_fp64(int n_t, const double *_
   const double x0 = xs[ii], x1 = xs[(size_t)n_t + ii], x2 = xs[2 * (size_t)n_t + ii];
   int want = -2;
   if (NN && active) want = want_key(species[perm[i]]);
-  const int self = active ? perm[i] : -1;
+  const int self = active ? (self_map ? self_map[perm[i]] : perm[i]) : -1;
   const int jb = blockIdx.y * chunk;
   const int je = min(n_s, jb + chunk);
   double ex = 0.0, ey = 0.0, ez = 0.0, ev = 0.0;
@@ -760,19 +847,22 @@ template <bool WANT_V, bool NN, int CZ>
 static void launch_pair_t(obem_ctx *ctx, dim3 grid, int n_t, const double *xs, const int32_t *perm, int n_s,
                           const double *sx, const double *sy, const double *sz, const double *sq,
                           const int8_t *sp, const int8_t *sps, double soft, obem_precision prec, int chunk,
-                          double *part, void *nnd, int32_t *nni, const double *tbox, float nn_cut2) {
+                          double *part, void *nnd, int32_t *nni, const double *tbox, float nn_cut2,
+                          const int32_t *self_map) {
   if (prec == OBEM_MIXED)
     hipLaunchKernelGGL((k_pair_mixed<WANT_V, NN, CZ>), grid, dim3(kThreads), 0, ctx->stream, n_t, xs, perm, n_s,
-                       sx, sy, sz, sq, sp, sps, (float)(soft * soft), chunk, part, (float *)nnd, nni, tbox, nn_cut2);
+                       sx, sy, sz, sq, sp, sps, (float)(soft * soft), chunk, part, (float *)nnd, nni, tbox, nn_cut2,
+                       self_map);
   else
     hipLaunchKernelGGL((k_pair_fp64<WANT_V, NN, CZ>), grid, dim3(kThreads), 0, ctx->stream, n_t, xs, perm, n_s,
-                       sx, sy, sz, sq, sp, sps, soft * soft, chunk, part, (double *)nnd, nni);
+                       sx, sy, sz, sq, sp, sps, soft * soft, chunk, part, (double *)nnd, nni, self_map);
 }
 
 obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, const double *sy, const double *sz,
                               const double *sq, const TargetOrder &to, double soft, obem_precision prec,
                               bool tgt_is_src, bool want_v, const int8_t *species, const int8_t *species_s,
-                              double *acc, int32_t *nn_idx, double *nn_d2, const double *tbox, double nn_cut) {
+                              double *acc, int32_t *nn_idx, double *nn_d2, const double *tbox, double nn_cut,
+                              const int32_t *self_map) {
   const int n_t = to.n;
   const int n_s = (int)n_src;
   if (n_t == 0 || n_s == 0) return OBEM_OK;
@@ -810,7 +900,7 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
 #define PAIR_CASE(V, N, Z)                                                                                   \
   if (want_v == V && nn == N && excl == Z)                                                                   \
     launch_pair_t<V, N, Z>(ctx, grid, n_t, to.xs, to.perm, n_s, sx, sy, sz, sq, species, species_s, soft, prec, \
-                           chunk, part, nnd, nni, tbox, nn_cut2);
+                           chunk, part, nnd, nni, tbox, nn_cut2, self_map);
   PAIR_CASE(false, false, 0)
   PAIR_CASE(false, false, 1)
   PAIR_CASE(false, false, 2)

@@ -42,7 +42,7 @@ struct DevBuf {
 enum WsSlot {
   WS_BBOX = 0, WS_KEYS0, WS_KEYS1, WS_IDX0, WS_IDX1, WS_SORT_TMP, WS_TSORT, WS_ACC, WS_PART,
   WS_NN, WS_MISC0, WS_MISC1, WS_MISC2, WS_MISC3, WS_MISC4, WS_MISC5, WS_MISC6, WS_MISC7,
-  WS_SOLVE0, WS_SOLVE1, WS_SOLVE2, WS_SRC, WS_SRCPERM, WS_SRCKEY, WS_SORT_TMP2, WS_TBOX, WS_MAP, WS_STATUS,
+  WS_SOLVE0, WS_SOLVE1, WS_SOLVE2, WS_SRC, WS_SRCPERM, WS_SRCKEY, WS_SORT_TMP2, WS_TBOX, WS_MAP, WS_STATUS, WS_SRCINV,
   WS_COUNT
 };
 
@@ -145,13 +145,28 @@ obem_status launch_panel_field(obem_ctx *ctx, const obem_meshh *m, const double 
 // species_t (caller order of the targets) and species_s (source order) are
 // needed only for the nearest opposite-species search (nn_idx != NULL).
 // With tbox (per 256-source tile: lo xyz, hi xyz; mixed precision only) the
-// search is limited to partners within nn_cut: a target with none gets
-// index -1.
+// search is limited to partners within nn_cut (a target with none gets
+// index -1), and source tiles far from a workgroup's targets take the
+// expanded form.  self_map (targets = sources): caller index -> position in
+// the source arrays, NULL when the sources are in caller order.
 obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, const double *sy,
                               const double *sz, const double *sq, const TargetOrder &to, double soft,
                               obem_precision prec, bool tgt_is_src, bool want_v, const int8_t *species_t,
                               const int8_t *species_s, double *acc, int32_t *nn_idx, double *nn_d2,
-                              const double *tbox = nullptr, double nn_cut = 0.0);
+                              const double *tbox = nullptr, double nn_cut = 0.0, const int32_t *self_map = nullptr);
+
+// Copy of the point sources in (charge sign, Morton) order with per-256-tile
+// boxes (field.hip); inv (caller index -> position) when asked for.  Uses the
+// target-ordering workspace: call before order_targets of the targets.
+struct SourceOrder {
+  int32_t n = 0;
+  const double *x = nullptr, *y = nullptr, *z = nullptr, *q = nullptr;
+  const double *tbox = nullptr;
+  const int32_t *inv = nullptr;
+};
+obem_status order_sources(obem_ctx *ctx, int64_t n, const double *sx, const double *sy, const double *sz,
+                          const double *sq, bool want_inv, SourceOrder *out);
+void launch_tile_boxes(obem_ctx *ctx, int n, const double *src, double *box);
 obem_status launch_scatter(obem_ctx *ctx, const TargetOrder &to, const double *acc, double scale,
                            double *Ex, double *Ey, double *Ez, double *V);
 obem_status launch_fill(obem_ctx *ctx, double *p, size_t n, double v);

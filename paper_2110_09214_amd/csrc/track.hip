@@ -714,31 +714,6 @@ __global__ __launch_bounds__(256) void k_gather_sources(int n, const int32_t *__
   sp_out[i] = sp[j];
 }
 
-// Bounding box of each 256-source tile of the source copy (lo xyz, hi xyz).
-__global__ __launch_bounds__(256) void k_tile_boxes(int n, const double *__restrict__ src, double *box) {
-  __shared__ double red[6][4];
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const int k = min(i, n - 1);
-  double v[6];
-  for (int c = 0; c < 3; ++c) v[c] = v[3 + c] = src[(size_t)c * n + k];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      v[c] = fmin(v[c], __shfl_xor(v[c], o));
-      v[3 + c] = fmax(v[3 + c], __shfl_xor(v[3 + c], o));
-    }
-  if ((threadIdx.x & 63) == 0)
-    for (int c = 0; c < 6; ++c) red[c][threadIdx.x >> 6] = v[c];
-  __syncthreads();
-  if (threadIdx.x < 6) {
-    const int c = threadIdx.x;
-    double r = red[c][0];
-    for (int w = 1; w < 4; ++w) r = c < 3 ? fmin(r, red[c][w]) : fmax(r, red[c][w]);
-    box[6 * (size_t)blockIdx.x + c] = r;
-  }
-}
-
 __global__ __launch_bounds__(256) void k_fill_u64(int n, unsigned long long *p, unsigned long long v) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < n) p[i] = v;
@@ -951,7 +926,7 @@ static obem_status step_field(obem_ctx *ctx, obem_meshh *mesh, const double *sig
                                                    ctx->stream));
   hipLaunchKernelGGL(k_gather_sources, dim3(nbt(n)), dim3(256), 0, ctx->stream, n, sperm + nz, S->x, S->y, S->z,
                      S->species, dead, status, srcb, ssp);
-  hipLaunchKernelGGL(k_tile_boxes, dim3(ntile), dim3(256), 0, ctx->stream, n, srcb, tbox);
+  launch_tile_boxes(ctx, n, srcb, tbox);
   OBEM_HIP(ctx, hipGetLastError());
   if (map)
     st = launch_map_acc(ctx, *map, to, acc);
