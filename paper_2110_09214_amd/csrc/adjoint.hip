@@ -23,7 +23,6 @@ namespace obem {
 
 constexpr int kT = 256;
 constexpr int kPTb = 64;
-constexpr int kNGb = 3 + 21 + 9;
 
 static inline int nbk(int64_t n) { return (int)((n + kT - 1) / kT); }
 
@@ -84,16 +83,23 @@ __device__ __forceinline__ void cell_grad_closed(const d3 P[3], d3 n, double two
 }
 
 // ---------------------------------------------------------------------------
-// Cell adjoint, mixed precision (regimes as in the forward kernel).
+// Cell adjoint, mixed precision (regimes as in the forward kernels).  The far
+// kernel takes the pairs beyond 3 D with the FP32 rules (7 points up to 64 D,
+// 3 beyond); the near kernel then adds the pairs within 3 D (FP64 closed
+// form), both deciding with the same FP32 test on the same recentred values.
 // gx: 3 x n_t (sorted order) position gradient in units of 1/k_e;
 // gsp: partial dL/dsigma per (workgroup, cell), in units of 1/k_e.
 // ---------------------------------------------------------------------------
-struct BTile {
-  float g[kNGb][kPTb];
-  float w[4][kPTb];    // area * {w0, wa, wb, 1/3}
-  float sg[kPTb];      // sigma
-  float lim[2][kPTb];
-  double red[4][kPTb];  // per-wave partial of w . IE
+constexpr int kPB = 32;        // cells per LDS tile of the far kernel
+constexpr int kUPad = kT + 4;  // row pitch of the w . IE buffer (floats)
+constexpr int kParts = kT / kPB;
+
+// One cell of the far kernel's tile, recentred FP32, 11 float4 records:
+//   c[0] = centroid, (3 D)^2          c[1] = (64 D)^2, area {w0, wa, wb}
+//   c[2..7] = the 7 rule points (21 floats), area / 3
+//   c[8..10] = the 3 rule points (9 floats), sigma, 2 unused
+struct BCell {
+  float4 c[11];
 };
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -107,136 +113,242 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// contribution of one quadrature point (weight aw, relative offset e) to
-// G^T w and w . IE (float)
-__device__ __forceinline__ void qpt_grad(float aw, float ex, float ey, float ez, float wx, float wy, float wz,
-                                         float &jx, float &jy, float &jz, float &u) {
+// One quadrature point of weight aw at offset e (target minus point), with
+// a3 = aw / |e|^3:  u += a3 (e . w),  A += a3,  Z += a3 (e . w) e / |e|^2.
+// Summed over the points, w . IE = u and G^T w = A w - 3 Z.
+__device__ __forceinline__ void qpt_adj(float aw, float ex, float ey, float ez, float wx, float wy, float wz,
+                                        float &u, float &A, float &Zx, float &Zy, float &Zz) {
   const float rr = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
   const float ri = __builtin_amdgcn_rsqf(rr);
   const float ri2 = ri * ri;
-  const float a3 = aw * ri * ri2;
-  const float dw = fmaf(ex, wx, fmaf(ey, wy, ez * wz));
-  u = fmaf(a3, dw, u);
-  const float t = 3.0f * a3 * ri2 * dw;
-  jx = fmaf(a3, wx, fmaf(-t, ex, jx));
-  jy = fmaf(a3, wy, fmaf(-t, ey, jy));
-  jz = fmaf(a3, wz, fmaf(-t, ez, jz));
+  const float a3 = (aw * ri) * ri2;
+  const float v = a3 * fmaf(ex, wx, fmaf(ey, wy, ez * wz));
+  u += v;
+  A += a3;
+  const float z = v * ri2;
+  Zx = fmaf(z, ex, Zx);
+  Zy = fmaf(z, ey, Zy);
+  Zz = fmaf(z, ez, Zz);
 }
 
+// The per-cell sums of w . IE over the workgroup's 256 targets go through
+// LDS: every thread stores its value for each cell of the tile, then 8
+// threads per cell add 32 targets each (FP32, fixed order) and the 8
+// partials are added in FP64 in fixed order.
 __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *__restrict__ xs,
                                                         const double *__restrict__ ws, int N,
                                                         const double *__restrict__ f,
                                                         const double *__restrict__ sigma, int want_x, double *gx,
                                                         double *gsp) {
-  __shared__ BTile T;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  __shared__ BCell T[kPB];
+  __shared__ __align__(16) float U[kPB][kUPad];
+  __shared__ double red[kParts][kPB];
+  const int tid = threadIdx.x;
   const int i0 = blockIdx.x * kT;
   const int i = i0 + tid;
   const bool active = i < n_t;
   const double c0 = xs[i0], c1 = xs[(size_t)n_t + i0], c2 = xs[2 * (size_t)n_t + i0];
-  const double x0 = active ? xs[i] : c0, x1 = active ? xs[(size_t)n_t + i] : c1, x2 = active ? xs[2 * (size_t)n_t + i] : c2;
-  const double w0d = active ? ws[i] : 0.0, w1d = active ? ws[(size_t)n_t + i] : 0.0,
-               w2d = active ? ws[2 * (size_t)n_t + i] : 0.0;
+  const double x0 = active ? xs[i] : c0, x1 = active ? xs[(size_t)n_t + i] : c1,
+               x2 = active ? xs[2 * (size_t)n_t + i] : c2;
   const float r0 = (float)(x0 - c0), r1 = (float)(x1 - c1), r2 = (float)(x2 - c2);
-  const float wx = (float)w0d, wy = (float)w1d, wz = (float)w2d;
+  // inactive lanes carry w = 0, so all their contributions vanish
+  const float wx = active ? (float)ws[i] : 0.f, wy = active ? (float)ws[(size_t)n_t + i] : 0.f,
+              wz = active ? (float)ws[2 * (size_t)n_t + i] : 0.f;
   float hx = 0, hy = 0, hz = 0, lx = 0, ly = 0, lz = 0;
-  double nx = 0, ny = 0, nz = 0;
-  for (int k0 = 0; k0 < N; k0 += kPTb) {
-    const int cnt = min(kPTb, N - k0);
+  for (int k0 = 0; k0 < N; k0 += kPB) {
+    const int cnt = min(kPB, N - k0);
     __syncthreads();
-    for (int idx = tid; idx < kNGb * kPTb; idx += kT) {
-      const int fld = idx / kPTb, k = idx % kPTb;
+    for (int idx = tid; idx < 30 * kPB; idx += kT) {
+      const int m = idx / kPB, k = idx % kPB;
       float v = 0.f;
       if (k < cnt) {
-        const int src = (fld < 3) ? (MF_GX + fld) : (MF_Q7 + fld - 3);
-        const int c = fld % 3;
-        const double cc = (c == 0) ? c0 : (c == 1 ? c1 : c2);
-        v = (float)(f[(size_t)src * N + k0 + k] - cc);
+        const int src = (m < 21) ? MF_Q7 + m : MF_Q3 + (m - 21);
+        const int c = (m < 21 ? m : m - 21) % 3;
+        v = (float)(f[(size_t)src * N + k0 + k] - (c == 0 ? c0 : (c == 1 ? c1 : c2)));
       }
-      T.g[fld][k] = v;
+      reinterpret_cast<float *>(&T[k])[m < 21 ? 8 + m : 32 + (m - 21)] = v;
     }
-    if (tid < kPTb) {
+    if (tid < kPB) {
       const int k = tid;
+      float4 g = make_float4(0.f, 0.f, 0.f, 0.f), h = g;
+      float w3 = 0.f, sg = 0.f;
       if (k < cnt) {
-        const double ar = f[(size_t)MF_AREA * N + k0 + k];
-        const double D = f[(size_t)MF_DIAM * N + k0 + k];
-        T.w[0][k] = (float)(ar * Rule7::w0);
-        T.w[1][k] = (float)(ar * Rule7::wa);
-        T.w[2][k] = (float)(ar * Rule7::wb);
-        T.w[3][k] = (float)(ar * (1.0 / 3.0));
-        T.sg[k] = (float)sigma[k0 + k];
-        T.lim[0][k] = (float)(kNearMixed * kNearMixed * D * D);
-        T.lim[1][k] = (float)(kFar3Mixed * kFar3Mixed * D * D);
+        const int kk = k0 + k;
+        const double D = f[(size_t)MF_DIAM * N + kk];
+        const double ar = f[(size_t)MF_AREA * N + kk];
+        g = make_float4((float)(f[(size_t)MF_GX * N + kk] - c0), (float)(f[(size_t)MF_GY * N + kk] - c1),
+                        (float)(f[(size_t)MF_GZ * N + kk] - c2), (float)(kNearMixed * kNearMixed * D * D));
+        h = make_float4((float)(kFar3Mixed * kFar3Mixed * D * D), (float)(ar * Rule7::w0), (float)(ar * Rule7::wa),
+                        (float)(ar * Rule7::wb));
+        w3 = (float)(ar * (1.0 / 3.0));
+        sg = (float)sigma[kk];
       }
+      T[k].c[0] = g;
+      T[k].c[1] = h;
+      reinterpret_cast<float *>(&T[k])[29] = w3;
+      reinterpret_cast<float *>(&T[k])[41] = sg;
     }
     __syncthreads();
-    float px = 0, py = 0, pz = 0;
+    float px = 0.f, py = 0.f, pz = 0.f;
     for (int k = 0; k < cnt; ++k) {
-      const float dx = r0 - T.g[0][k], dy = r1 - T.g[1][k], dz = r2 - T.g[2][k];
-      const float R2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-      const bool nearp = R2 < T.lim[0][k];
-      float u = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-      double un = 0.0;
-      const bool anyn = __any(nearp);
-      if (anyn) {
-        if (nearp && active) {
-          const int kk = k0 + k;
-          d3 P[3];
-          P[0] = mk3(f[(size_t)MF_AX * N + kk] - x0, f[(size_t)MF_AY * N + kk] - x1, f[(size_t)MF_AZ * N + kk] - x2);
-          P[1] = mk3(f[(size_t)MF_BX * N + kk] - x0, f[(size_t)MF_BY * N + kk] - x1, f[(size_t)MF_BZ * N + kk] - x2);
-          P[2] = mk3(f[(size_t)MF_CX * N + kk] - x0, f[(size_t)MF_CY * N + kk] - x1, f[(size_t)MF_CZ * N + kk] - x2);
-          const d3 nn = mk3(f[(size_t)MF_NX * N + kk], f[(size_t)MF_NY * N + kk], f[(size_t)MF_NZ * N + kk]);
-          d3 g;
-          double iw;
-          cell_grad_closed(P, nn, 2.0 * f[(size_t)MF_AREA * N + kk], mk3(w0d, w1d, w2d), g, iw);
-          const double sg = sigma[kk];
-          nx = fma(sg, g.x, nx);
-          ny = fma(sg, g.y, ny);
-          nz = fma(sg, g.z, nz);
-          un = iw;
-        }
-      }
-      const bool need7 = (!nearp) && (R2 < T.lim[1][k]);
+      const float4 g = T[k].c[0];
+      const float R2 = dist2f(r0, r1, r2, g.x, g.y, g.z);
+      const bool nearp = R2 < g.w;  // taken by k_panel_bwd_near in FP64
+      const float4 h = T[k].c[1];
+      const bool need7 = (!nearp) && (R2 < h.x);
+      float u = 0.f, A = 0.f, Zx = 0.f, Zy = 0.f, Zz = 0.f;
       if (__any(need7)) {
         if (!nearp) {
+          float q[24];
 #pragma unroll
-          for (int q = 0; q < 7; ++q) {
-            const float aw = T.w[q == 0 ? 0 : (q < 4 ? 1 : 2)][k];
-            qpt_grad(aw, r0 - T.g[3 + 3 * q][k], r1 - T.g[4 + 3 * q][k], r2 - T.g[5 + 3 * q][k], wx, wy, wz, jx, jy,
-                     jz, u);
+          for (int m = 0; m < 6; ++m) {
+            const float4 t = T[k].c[2 + m];
+            q[4 * m] = t.x;
+            q[4 * m + 1] = t.y;
+            q[4 * m + 2] = t.z;
+            q[4 * m + 3] = t.w;
           }
+#pragma unroll
+          for (int m = 0; m < 7; ++m)
+            qpt_adj((m == 0) ? h.y : (m < 4 ? h.z : h.w), r0 - q[3 * m], r1 - q[3 * m + 1], r2 - q[3 * m + 2], wx,
+                    wy, wz, u, A, Zx, Zy, Zz);
         }
       } else if (!nearp) {
-        const float aw = T.w[3][k];
+        const float aw = T[k].c[7].y;  // area / 3
+        float q[12];
 #pragma unroll
-        for (int q = 0; q < 3; ++q)
-          qpt_grad(aw, r0 - T.g[24 + 3 * q][k], r1 - T.g[25 + 3 * q][k], r2 - T.g[26 + 3 * q][k], wx, wy, wz, jx, jy,
-                   jz, u);
+        for (int m = 0; m < 3; ++m) {
+          const float4 t = T[k].c[8 + m];
+          q[4 * m] = t.x;
+          q[4 * m + 1] = t.y;
+          q[4 * m + 2] = t.z;
+          q[4 * m + 3] = t.w;
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+          qpt_adj(aw, r0 - q[3 * m], r1 - q[3 * m + 1], r2 - q[3 * m + 2], wx, wy, wz, u, A, Zx, Zy, Zz);
       }
-      if (!active) u = 0.f;
-      const float sg = T.sg[k];
-      px = fmaf(sg, jx, px);
-      py = fmaf(sg, jy, py);
-      pz = fmaf(sg, jz, pz);
-      // charge gradient: reduce w . IE over the wave (fixed tree), FP64 for near lanes
-      double tot = (double)wave_sum(u);
-      if (anyn) tot += wave_sum(un);
-      if (lane == 0) T.red[wv][k] = tot;
+      const float sg = T[k].c[10].y;
+      const float sA = sg * A, s3 = -3.0f * sg;
+      px = fmaf(sA, wx, fmaf(s3, Zx, px));
+      py = fmaf(sA, wy, fmaf(s3, Zy, py));
+      pz = fmaf(sA, wz, fmaf(s3, Zz, pz));
+      U[k][tid] = u;
     }
     neum(hx, lx, px);
     neum(hy, ly, py);
     neum(hz, lz, pz);
     __syncthreads();
+    {
+      const int k = tid % kPB, part = tid / kPB;
+      const float4 *row = reinterpret_cast<const float4 *>(&U[k][part * (kT / kParts)]);
+      float4 a = row[0];
+#pragma unroll
+      for (int j = 1; j < kT / kParts / 4; ++j) {
+        const float4 v = row[j];
+        a.x += v.x;
+        a.y += v.y;
+        a.z += v.z;
+        a.w += v.w;
+      }
+      red[part][k] = (double)((a.x + a.y) + (a.z + a.w));
+    }
+    __syncthreads();
     if (tid < cnt) {
-      const int k = tid;
-      const double s = T.red[0][k] + T.red[1][k] + T.red[2][k] + T.red[3][k];
-      gsp[(size_t)blockIdx.x * N + k0 + k] = s;
+      double s = red[0][tid];
+#pragma unroll
+      for (int p = 1; p < kParts; ++p) s += red[p][tid];
+      gsp[(size_t)blockIdx.x * N + k0 + tid] = s;
     }
   }
   if (active && want_x) {
-    gx[i] = ((double)hx + (double)lx) + nx;
-    gx[(size_t)n_t + i] = ((double)hy + (double)ly) + ny;
-    gx[2 * (size_t)n_t + i] = ((double)hz + (double)lz) + nz;
+    gx[i] = (double)hx + (double)lx;
+    gx[(size_t)n_t + i] = (double)hy + (double)ly;
+    gx[2 * (size_t)n_t + i] = (double)hz + (double)lz;
+  }
+}
+
+// FP64 near zone of the mixed cell adjoint, added to gx and to gsp after the
+// far kernel (same workgroups, so gsp[b][k] is read and written by one
+// workgroup only).  The workgroup bounds its 256 targets by a sphere and
+// visits the 64-cell tiles whose near-zone sphere (centre, max_k |c_k -
+// centre| + 3 D_k) it meets, with a relative margin for the FP32 test.
+__global__ __launch_bounds__(kT) void k_panel_bwd_near(int n_t, const double *__restrict__ xs,
+                                                       const double *__restrict__ ws, int N,
+                                                       const double *__restrict__ f,
+                                                       const double *__restrict__ sigma,
+                                                       const double *__restrict__ tiles, int want_x, double *gx,
+                                                       double *gsp) {
+  __shared__ double box[4][6];
+  __shared__ double red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int i0 = blockIdx.x * kT;
+  const int i = i0 + tid;
+  const bool active = i < n_t;
+  const double c0 = xs[i0], c1 = xs[(size_t)n_t + i0], c2 = xs[2 * (size_t)n_t + i0];
+  const double x0 = active ? xs[i] : c0, x1 = active ? xs[(size_t)n_t + i] : c1,
+               x2 = active ? xs[2 * (size_t)n_t + i] : c2;
+  const float r0 = (float)(x0 - c0), r1 = (float)(x1 - c1), r2 = (float)(x2 - c2);
+  const d3 w = active ? mk3(ws[i], ws[(size_t)n_t + i], ws[2 * (size_t)n_t + i]) : mk3(0, 0, 0);
+  double b[6] = {x0, x1, x2, x0, x1, x2};
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      b[d] = fmin(b[d], __shfl_xor(b[d], o));
+      b[3 + d] = fmax(b[3 + d], __shfl_xor(b[3 + d], o));
+    }
+  }
+  if (lane == 0)
+    for (int d = 0; d < 6; ++d) box[wv][d] = b[d];
+  __syncthreads();
+  double lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = fmin(fmin(box[0][d], box[1][d]), fmin(box[2][d], box[3][d]));
+    hi[d] = fmax(fmax(box[0][3 + d], box[1][3 + d]), fmax(box[2][3 + d], box[3][3 + d]));
+  }
+  const double bc0 = 0.5 * (lo[0] + hi[0]), bc1 = 0.5 * (lo[1] + hi[1]), bc2 = 0.5 * (lo[2] + hi[2]);
+  const double br = 0.5 * sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                               (hi[2] - lo[2]) * (hi[2] - lo[2]));
+  double nx = 0.0, ny = 0.0, nz = 0.0;
+  const int ntile = (N + 63) / 64;
+  for (int t = 0; t < ntile; ++t) {
+    const double dx = bc0 - tiles[4 * t], dy = bc1 - tiles[4 * t + 1], dz = bc2 - tiles[4 * t + 2];
+    const double rs = (br + tiles[4 * t + 3]) * (1.0 + 1e-5);
+    if (dx * dx + dy * dy + dz * dz > rs * rs) continue;  // workgroup-uniform
+    const int k0 = t * 64, cnt = min(64, N - k0);
+    for (int k = 0; k < cnt; ++k) {
+      const int kk = k0 + k;
+      const float g0 = (float)(f[(size_t)MF_GX * N + kk] - c0), g1 = (float)(f[(size_t)MF_GY * N + kk] - c1),
+                  g2 = (float)(f[(size_t)MF_GZ * N + kk] - c2);
+      const double D = f[(size_t)MF_DIAM * N + kk];
+      const bool nearp = active && dist2f(r0, r1, r2, g0, g1, g2) < (float)(kNearMixed * kNearMixed * D * D);
+      if (!__syncthreads_or(nearp)) continue;
+      double un = 0.0;
+      if (nearp) {
+        d3 P[3];
+        P[0] = mk3(f[(size_t)MF_AX * N + kk] - x0, f[(size_t)MF_AY * N + kk] - x1, f[(size_t)MF_AZ * N + kk] - x2);
+        P[1] = mk3(f[(size_t)MF_BX * N + kk] - x0, f[(size_t)MF_BY * N + kk] - x1, f[(size_t)MF_BZ * N + kk] - x2);
+        P[2] = mk3(f[(size_t)MF_CX * N + kk] - x0, f[(size_t)MF_CY * N + kk] - x1, f[(size_t)MF_CZ * N + kk] - x2);
+        const d3 nn = mk3(f[(size_t)MF_NX * N + kk], f[(size_t)MF_NY * N + kk], f[(size_t)MF_NZ * N + kk]);
+        d3 g;
+        cell_grad_closed(P, nn, 2.0 * f[(size_t)MF_AREA * N + kk], w, g, un);
+        const double sg = sigma[kk];
+        nx = fma(sg, g.x, nx);
+        ny = fma(sg, g.y, ny);
+        nz = fma(sg, g.z, nz);
+      }
+      const double s = wave_sum(un);
+      if (lane == 0) red[wv] = s;
+      __syncthreads();
+      if (tid == 0) gsp[(size_t)blockIdx.x * N + kk] += ((red[0] + red[1]) + red[2]) + red[3];
+      __syncthreads();
+    }
+  }
+  if (active && want_x) {
+    gx[i] += nx;
+    gx[(size_t)n_t + i] += ny;
+    gx[2 * (size_t)n_t + i] += nz;
   }
 }
 
@@ -327,6 +439,37 @@ __global__ __launch_bounds__(256) void k_sum_partials(int N, int nb, const doubl
 // a_ij = q_j w_i (target role) - q_i w_j (source role, when the targets are
 // the sources).  Partials per source chunk, summed in order by k_sum_chunks.
 // ---------------------------------------------------------------------------
+// One source tile of the target-side pairwise adjoint: with a = q_j w_i
+// (minus q_i w_j when targets are the sources), p += J(d) a with
+// J(d) = I/r^3 - 3 d d^T / r^5.  FOLDQ: q_j w_i = a0 for the whole tile.
+template <bool TIS, int EXCL, bool FOLDQ>
+__device__ __forceinline__ void pair_bwd_tile(const float4 *S, const float4 *Wq, int cnt, int jt, int self, float r0,
+                                              float r1, float r2, float a0x, float a0y, float a0z, float wx, float wy,
+                                              float wz, float qi, float soft2, float &px, float &py, float &pz) {
+  for (int jj = 0; jj < cnt; ++jj) {
+    const float4 s = S[jj];
+    const float dx = r0 - s.x, dy = r1 - s.y, dz = r2 - s.z;
+    const float rr = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, soft2)));
+    float ri = __builtin_amdgcn_rsqf(rr);
+    if (EXCL == 1) ri = rr > 0.f ? ri : 0.f;
+    if (EXCL == 2) ri = (jt + jj == self) ? 0.f : ri;
+    float ax = FOLDQ ? a0x : s.w * wx, ay = FOLDQ ? a0y : s.w * wy, az = FOLDQ ? a0z : s.w * wz;
+    if (TIS) {
+      const float4 wj = Wq[jj];
+      ax = fmaf(-qi, wj.x, ax);
+      ay = fmaf(-qi, wj.y, ay);
+      az = fmaf(-qi, wj.z, az);
+    }
+    // J a = ri^3 (a - 3 ri^2 (d . a) d)
+    const float ri2 = ri * ri;
+    const float ri3 = ri * ri2;
+    const float u = (3.0f * ri2) * fmaf(dx, ax, fmaf(dy, ay, dz * az));
+    px = fmaf(ri3, fmaf(-u, dx, ax), px);
+    py = fmaf(ri3, fmaf(-u, dy, ay), py);
+    pz = fmaf(ri3, fmaf(-u, dz, az), pz);
+  }
+}
+
 template <bool TIS, int EXCL>
 __global__ __launch_bounds__(kT) void k_pair_bwd_t_mixed(int n_t, const double *__restrict__ xs,
                                                          const int32_t *__restrict__ perm,
@@ -356,36 +499,25 @@ __global__ __launch_bounds__(kT) void k_pair_bwd_t_mixed(int n_t, const double *
   float hx = 0, hy = 0, hz = 0, lx = 0, ly = 0, lz = 0;
   for (int jt = jb; jt < je; jt += kT) {
     const int cnt = min(kT, je - jt);
+    const float q0 = (float)sq[jt];
     __syncthreads();
+    float qj = q0;
     if (tid < cnt) {
       const int j = jt + tid;
-      S[tid] = make_float4((float)(sx[j] - c0), (float)(sy[j] - c1), (float)(sz[j] - c2), (float)sq[j]);
+      qj = (float)sq[j];
+      S[tid] = make_float4((float)(sx[j] - c0), (float)(sy[j] - c1), (float)(sz[j] - c2), qj);
       if (TIS) Wq[tid] = make_float4((float)gEx[j], (float)gEy[j], (float)gEz[j], 0.f);
     }
-    __syncthreads();
+    // tiles of one charge (sources grouped by species): q_j w_i is the same
+    // for the whole tile, 3 fewer VALU operations per pair
+    const bool uniform = __syncthreads_and(qj == q0);
     float px = 0, py = 0, pz = 0;
-    for (int jj = 0; jj < cnt; ++jj) {
-      const float4 s = S[jj];
-      const float dx = r0 - s.x, dy = r1 - s.y, dz = r2 - s.z;
-      const float rr = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, soft2)));
-      float ri = __builtin_amdgcn_rsqf(rr);
-      if (EXCL == 1) ri = rr > 0.f ? ri : 0.f;
-      if (EXCL == 2) ri = (jt + jj == self) ? 0.f : ri;
-      float ax = s.w * wx, ay = s.w * wy, az = s.w * wz;
-      if (TIS) {
-        const float4 wj = Wq[jj];
-        ax = fmaf(-qi, wj.x, ax);
-        ay = fmaf(-qi, wj.y, ay);
-        az = fmaf(-qi, wj.z, az);
-      }
-      const float ri2 = ri * ri;
-      const float ri3 = ri * ri2;
-      const float da = fmaf(dx, ax, fmaf(dy, ay, dz * az));
-      const float t = 3.0f * ri3 * ri2 * da;
-      px = fmaf(ri3, ax, fmaf(-t, dx, px));
-      py = fmaf(ri3, ay, fmaf(-t, dy, py));
-      pz = fmaf(ri3, az, fmaf(-t, dz, pz));
-    }
+    if (uniform)
+      pair_bwd_tile<TIS, EXCL, true>(S, Wq, cnt, jt, self, r0, r1, r2, q0 * wx, q0 * wy, q0 * wz, wx, wy, wz, qi,
+                                     soft2, px, py, pz);
+    else
+      pair_bwd_tile<TIS, EXCL, false>(S, Wq, cnt, jt, self, r0, r1, r2, 0.f, 0.f, 0.f, wx, wy, wz, qi, soft2, px, py,
+                                      pz);
     neum(hx, lx, px);
     neum(hy, ly, py);
     neum(hz, lz, pz);
@@ -596,7 +728,7 @@ extern "C" obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh
   if (!ctx) return OBEM_EINVAL;
   if (ctx->sticky) return OBEM_ESTATE;
   if (hipSetDevice(ctx->device) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return fail(ctx, OBEM_EDEVICE, "hipSetDevice failed");
   }
   const int64_t kMax = (int64_t)1 << 31;
@@ -649,10 +781,12 @@ extern "C" obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh
     double *gsp = (double *)ws_get(ctx, WS_MISC2, sizeof(double) * (size_t)bt * N);
     if (!gsp) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed (%d x %d partials)", bt, N);
     OBEM_PROF(ctx, "panel_bwd");
-    if (precision == OBEM_MIXED)
+    if (precision == OBEM_MIXED) {
       hipLaunchKernelGGL(k_panel_bwd_mixed, dim3(bt), dim3(kT), 0, ctx->stream, n_t, to.xs, wsrt, N, mesh->f, sigma,
                          1, gx, gsp);
-    else
+      hipLaunchKernelGGL(k_panel_bwd_near, dim3(bt), dim3(kT), 0, ctx->stream, n_t, to.xs, wsrt, N, mesh->f, sigma,
+                         mesh->tiles, 1, gx, gsp);
+    } else
       hipLaunchKernelGGL(k_panel_bwd_fp64, dim3(bt), dim3(kT), 0, ctx->stream, n_t, to.xs, wsrt, N, mesh->f, sigma, 1,
                          gx, gsp);
     OBEM_HIP(ctx, hipGetLastError());

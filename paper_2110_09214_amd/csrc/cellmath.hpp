@@ -86,6 +86,15 @@ __device__ __forceinline__ void cell_closed_form(const d3 P[3], d3 n, double two
 // Symmetric quadrature rules on the triangle, barycentric weights
 // (Radon's 7-point degree-5 rule; the 3-point degree-2 rule at the edge
 // midpoint-centroid points (2/3, 1/6, 1/6)).
+// Near/far test of the mixed cell field (squared FP32 distance of values
+// recentred on one target of the workgroup).  The far and near kernels of
+// the field and of its adjoint all use this arithmetic on identically
+// recentred operands, so each (target, cell) pair is taken by exactly one.
+__device__ __forceinline__ float dist2f(float a0, float a1, float a2, float b0, float b1, float b2) {
+  const float dx = a0 - b0, dy = a1 - b1, dz = a2 - b2;
+  return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+}
+
 struct Rule7 {
   // a = (6 - sqrt 15)/21, b = (6 + sqrt 15)/21
   static constexpr double a = 0.10128650732345633880;

@@ -281,14 +281,6 @@ __device__ __forceinline__ void near_cell(const double *__restrict__ f, int N, i
   if (WANT_V) ev = fma(sig, IV, ev);
 }
 
-// Near/far test shared by the far and near kernels (identical FP32
-// arithmetic on identically recentred values, so every pair is taken by
-// exactly one of them).
-__device__ __forceinline__ float dist2f(float a0, float a1, float a2, float b0, float b1, float b2) {
-  const float dx = a0 - b0, dy = a1 - b1, dz = a2 - b2;
-  return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-}
-
 template <bool WANT_V>
 __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double *__restrict__ xs, int N,
                                                           const double *__restrict__ f,
