@@ -9,10 +9,11 @@
 // the mesh's Morton order of centroids (a workgroup's cells are spatially
 // close and are recentred on its first centroid), charges staged in LDS
 // tiles, gridDim.y chunks of charges with per-chunk partial sums reduced in
-// chunk order.  Precision
-// regimes as in the field: FP64 closed form within 3 diameters, FP32 7-point
-// rule within 64, 3-point rule beyond (mixed); closed form within 48
-// diameters, FP64 7-point rule beyond (FP64).
+// chunk order.  Precision regimes as in the field: mixed = FP32 7-point rule
+// within 64 diameters, 3-point rule beyond (far kernel, charges ordered by
+// charge sign, then Morton, so the charge comes out of the pair loop), FP64
+// closed form within 3 diameters (near kernel, its own partial slots);
+// FP64 = closed form within 48 diameters, FP64 7-point rule beyond.
 #include <algorithm>
 #include <cmath>
 
@@ -49,6 +50,66 @@ __device__ __forceinline__ void infl_closed(const double *__restrict__ f, int N,
   ez = fma(q, IE.z, ez);
 }
 
+// One LDS tile of charges (recentred FP32 position, charge) against the
+// thread's cell, pairs beyond 3 D only (the near kernel takes the others):
+// 7-point rule within 64 D, 3-point rule beyond.  FOLDQ: all charges of the
+// tile are equal and the charge is applied by the caller.
+template <bool FOLDQ>
+__device__ __forceinline__ void infl_tile(const float4 *P, int cnt, float g0, float g1, float g2, const float *q7,
+                                          const float *q3, float w0, float wa, float wb, float w3, float lim_near,
+                                          float lim_far, float &pv, float &px, float &py, float &pz) {
+  for (int jj = 0; jj < cnt; ++jj) {
+    const float4 p = P[jj];
+    const float R2 = dist2f(p.x, p.y, p.z, g0, g1, g2);
+    const bool nearp = R2 < lim_near;
+    const bool need7 = !nearp && R2 < lim_far;
+    float sv = 0, ex = 0, ey = 0, ez = 0;
+    if (__any(need7)) {
+      if (!nearp) {
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+          const float w = (m == 0) ? w0 : (m < 4 ? wa : wb);
+          const float ax = p.x - q7[3 * m], ay = p.y - q7[3 * m + 1], az = p.z - q7[3 * m + 2];
+          const float rr = fmaf(ax, ax, fmaf(ay, ay, az * az));
+          const float ri = __builtin_amdgcn_rsqf(rr);
+          const float wr = w * ri;
+          const float t = wr * (ri * ri);
+          sv += wr;
+          ex = fmaf(t, ax, ex);
+          ey = fmaf(t, ay, ey);
+          ez = fmaf(t, az, ez);
+        }
+      }
+    } else if (!nearp) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const float ax = p.x - q3[3 * m], ay = p.y - q3[3 * m + 1], az = p.z - q3[3 * m + 2];
+        const float rr = fmaf(ax, ax, fmaf(ay, ay, az * az));
+        const float ri = __builtin_amdgcn_rsqf(rr);
+        const float wr = w3 * ri;
+        const float t = wr * (ri * ri);
+        sv += wr;
+        ex = fmaf(t, ax, ex);
+        ey = fmaf(t, ay, ey);
+        ez = fmaf(t, az, ez);
+      }
+    }
+    if (FOLDQ) {
+      pv += sv;
+      px += ex;
+      py += ey;
+      pz += ez;
+    } else {
+      pv = fmaf(p.w, sv, pv);
+      px = fmaf(p.w, ex, px);
+      py = fmaf(p.w, ey, py);
+      pz = fmaf(p.w, ez, pz);
+    }
+  }
+}
+
+// Far part of the mixed influence (pairs beyond 3 D), charges in (charge
+// sign, Morton) order so that nearly every LDS tile holds one charge value.
 __global__ __launch_bounds__(kTI) void k_influence_mixed(int N, const double *__restrict__ f,
                                                          const int32_t *__restrict__ ord, int n_s,
                                                          const double *__restrict__ sx,
@@ -77,64 +138,27 @@ __global__ __launch_bounds__(kTI) void k_influence_mixed(int N, const double *__
               w3 = (float)(area / 3.0);
   const float lim_near = (float)(kNearMixed * kNearMixed * D * D), lim_far = (float)(kFar3Mixed * kFar3Mixed * D * D);
   float hv = 0, hx = 0, hy = 0, hz = 0, lv = 0, lx = 0, ly = 0, lz = 0;
-  double nv = 0, nx = 0, ny = 0, nz = 0;
   const int jb = blockIdx.y * chunk, je = min(n_s, jb + chunk);
   for (int jt = jb; jt < je; jt += kTI) {
     const int cnt = min(kTI, je - jt);
+    const float q0 = (float)sq[jt];
+    float qj = q0;
     __syncthreads();
     if (tid < cnt) {
       const int j = jt + tid;
-      P[tid] = make_float4((float)(sx[j] - c0), (float)(sy[j] - c1), (float)(sz[j] - c2), (float)sq[j]);
+      qj = (float)sq[j];
+      P[tid] = make_float4((float)(sx[j] - c0), (float)(sy[j] - c1), (float)(sz[j] - c2), qj);
     }
-    __syncthreads();
+    const bool uniform = __syncthreads_and(qj == q0);
     float pv = 0, px = 0, py = 0, pz = 0;
-    for (int jj = 0; jj < cnt; ++jj) {
-      const float4 p = P[jj];
-      const float dx = p.x - g0, dy = p.y - g1, dz = p.z - g2;
-      const float R2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-      const bool nearp = R2 < lim_near;
-      if (__any(nearp)) {
-        if (nearp && active) {
-          const int j = jt + jj;
-          infl_closed(f, N, kk, sx[j], sy[j], sz[j], sq[j], nv, nx, ny, nz);
-        }
-      }
-      const bool need7 = !nearp && R2 < lim_far;
-      float sv = 0, ex = 0, ey = 0, ez = 0;
-      if (__any(need7)) {
-        if (!nearp) {
-#pragma unroll
-          for (int m = 0; m < 7; ++m) {
-            const float w = (m == 0) ? w0 : (m < 4 ? wa : wb);
-            const float ax = p.x - q7[3 * m], ay = p.y - q7[3 * m + 1], az = p.z - q7[3 * m + 2];
-            const float rr = fmaf(ax, ax, fmaf(ay, ay, az * az));
-            const float ri = __builtin_amdgcn_rsqf(rr);
-            const float wr = w * ri;
-            const float s = wr * (ri * ri);
-            sv += wr;
-            ex = fmaf(s, ax, ex);
-            ey = fmaf(s, ay, ey);
-            ez = fmaf(s, az, ez);
-          }
-        }
-      } else if (!nearp) {
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          const float ax = p.x - q3[3 * m], ay = p.y - q3[3 * m + 1], az = p.z - q3[3 * m + 2];
-          const float rr = fmaf(ax, ax, fmaf(ay, ay, az * az));
-          const float ri = __builtin_amdgcn_rsqf(rr);
-          const float wr = w3 * ri;
-          const float s = wr * (ri * ri);
-          sv += wr;
-          ex = fmaf(s, ax, ex);
-          ey = fmaf(s, ay, ey);
-          ez = fmaf(s, az, ez);
-        }
-      }
-      pv = fmaf(p.w, sv, pv);
-      px = fmaf(p.w, ex, px);
-      py = fmaf(p.w, ey, py);
-      pz = fmaf(p.w, ez, pz);
+    if (uniform) {
+      infl_tile<true>(P, cnt, g0, g1, g2, q7, q3, w0, wa, wb, w3, lim_near, lim_far, pv, px, py, pz);
+      pv *= q0;
+      px *= q0;
+      py *= q0;
+      pz *= q0;
+    } else {
+      infl_tile<false>(P, cnt, g0, g1, g2, q7, q3, w0, wa, wb, w3, lim_near, lim_far, pv, px, py, pz);
     }
     neum_i(hv, lv, pv);
     neum_i(hx, lx, px);
@@ -143,10 +167,74 @@ __global__ __launch_bounds__(kTI) void k_influence_mixed(int N, const double *__
   }
   if (active) {
     const size_t o = (size_t)blockIdx.y * 4 * N;
-    part[o + k] = ((double)hv + (double)lv) + nv;
-    part[o + (size_t)N + k] = ((double)hx + (double)lx) + nx;
-    part[o + 2 * (size_t)N + k] = ((double)hy + (double)ly) + ny;
-    part[o + 3 * (size_t)N + k] = ((double)hz + (double)lz) + nz;
+    part[o + k] = (double)hv + (double)lv;
+    part[o + (size_t)N + k] = (double)hx + (double)lx;
+    part[o + 2 * (size_t)N + k] = (double)hy + (double)ly;
+    part[o + 3 * (size_t)N + k] = (double)hz + (double)lz;
+  }
+}
+
+// Near part of the mixed influence: the pairs that the far kernel's FP32
+// test (same values, recentred on the first cell of the far kernel's 256-cell
+// workgroup) puts within 3 D, in FP64 closed form.  One wave of 64 cells per
+// workgroup; gridDim.y splits the 256-charge tiles, each split writing its
+// own partial slot.  A tile is visited when some lane's cell can reach its
+// box: distance below 3 D (1 + 1e-5) + 1e-6 |c_k - c0|, which exceeds what
+// FP32 rounding of the recentred coordinates can add to the test.
+constexpr int kNW = 64;
+
+__global__ __launch_bounds__(kNW) void k_influence_near(int N, const double *__restrict__ f,
+                                                        const int32_t *__restrict__ ord, int n_s,
+                                                        const double *__restrict__ sx,
+                                                        const double *__restrict__ sy,
+                                                        const double *__restrict__ sz,
+                                                        const double *__restrict__ sq,
+                                                        const double *__restrict__ tbox, int tchunk, double *part) {
+  __shared__ float4 P[kTI];
+  const int lane = threadIdx.x;
+  const int k = blockIdx.x * kNW + lane;
+  const bool active = k < N;
+  const int kk = ord[active ? k : N - 1];
+  const int k0 = ord[(blockIdx.x * kNW / kTI) * kTI];
+  const double c0 = f[(size_t)MF_GX * N + k0], c1 = f[(size_t)MF_GY * N + k0], c2 = f[(size_t)MF_GZ * N + k0];
+  const double G0 = f[(size_t)MF_GX * N + kk], G1 = f[(size_t)MF_GY * N + kk], G2 = f[(size_t)MF_GZ * N + kk];
+  const float g0 = (float)(G0 - c0), g1 = (float)(G1 - c1), g2 = (float)(G2 - c2);
+  const double D = f[(size_t)MF_DIAM * N + kk];
+  const float lim_near = (float)(kNearMixed * kNearMixed * D * D);
+  const double off = sqrt((G0 - c0) * (G0 - c0) + (G1 - c1) * (G1 - c1) + (G2 - c2) * (G2 - c2));
+  const double reach = kNearMixed * D * (1.0 + 1e-5) + 1e-6 * off;
+  const double reach2 = active ? reach * reach : -1.0;
+  double nv = 0, nx = 0, ny = 0, nz = 0;
+  const int ntile = (n_s + kTI - 1) / kTI;
+  const int tb = blockIdx.y * tchunk, te = min(ntile, tb + tchunk);
+  for (int t = tb; t < te; ++t) {
+    const double *bx = tbox + 6 * (size_t)t;
+    const double e0 = fmax(fmax(bx[0] - G0, G0 - bx[3]), 0.0);
+    const double e1 = fmax(fmax(bx[1] - G1, G1 - bx[4]), 0.0);
+    const double e2 = fmax(fmax(bx[2] - G2, G2 - bx[5]), 0.0);
+    if (!__any(e0 * e0 + e1 * e1 + e2 * e2 < reach2)) continue;  // wave-uniform
+    const int jt = t * kTI, cnt = min(kTI, n_s - jt);
+    __syncthreads();
+    for (int jj = lane; jj < cnt; jj += kNW)
+      P[jj] = make_float4((float)(sx[jt + jj] - c0), (float)(sy[jt + jj] - c1), (float)(sz[jt + jj] - c2), 0.f);
+    __syncthreads();
+    for (int jj = 0; jj < cnt; ++jj) {
+      const float4 p = P[jj];
+      const bool nearp = active && dist2f(p.x, p.y, p.z, g0, g1, g2) < lim_near;
+      if (__any(nearp)) {
+        if (nearp) {
+          const int j = jt + jj;
+          infl_closed(f, N, kk, sx[j], sy[j], sz[j], sq[j], nv, nx, ny, nz);
+        }
+      }
+    }
+  }
+  if (active) {
+    const size_t o = (size_t)blockIdx.y * 4 * N;
+    part[o + k] = nv;
+    part[o + (size_t)N + k] = nx;
+    part[o + 2 * (size_t)N + k] = ny;
+    part[o + 3 * (size_t)N + k] = nz;
   }
 }
 
@@ -255,22 +343,33 @@ obem_status influence_rhs(obem_ctx *ctx, const obem_meshh *m, int64_t n_src, con
     chunk = (chunk + kTI - 1) / kTI * kTI;
     nsplit = (n_s + chunk - 1) / chunk;
   }
-  double *part = (double *)ws_get(ctx, WS_MISC3, sizeof(double) * 4 * (size_t)N * nsplit);
+  // mixed: partial slots of the near kernel after those of the far kernel
+  const int ntile = (n_s + kTI - 1) / kTI;
+  const int bn = (N + kNW - 1) / kNW;
+  const int nnear = std::max(1, std::min(ntile, std::min(16, (2048 + bn - 1) / bn)));
+  const int tchunk = std::max(1, (ntile + nnear - 1) / nnear);
+  const int nslot = (n_s > 0 && prec == OBEM_MIXED) ? nsplit + (ntile + tchunk - 1) / tchunk : nsplit;
+  double *part = (double *)ws_get(ctx, WS_MISC3, sizeof(double) * 4 * (size_t)N * nslot);
   if (!part) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
   OBEM_PROF(ctx, "influence");
   if (n_s == 0) {
     obem_status st = launch_fill(ctx, part, 4 * (size_t)N, 0.0);
     if (st) return st;
   } else if (prec == OBEM_MIXED) {
-    hipLaunchKernelGGL(k_influence_mixed, dim3(bc, nsplit), dim3(kTI), 0, ctx->stream, N, m->f, m->order, n_s, sx, sy,
-                       sz, sq, chunk, part);
+    SourceOrder so;
+    obem_status st = order_sources(ctx, n_s, sx, sy, sz, sq, false, &so);
+    if (st) return st;
+    hipLaunchKernelGGL(k_influence_mixed, dim3(bc, nsplit), dim3(kTI), 0, ctx->stream, N, m->f, m->order, n_s, so.x,
+                       so.y, so.z, so.q, chunk, part);
+    hipLaunchKernelGGL(k_influence_near, dim3(bn, nslot - nsplit), dim3(kNW), 0, ctx->stream, N, m->f, m->order, n_s,
+                       so.x, so.y, so.z, so.q, so.tbox, tchunk, part + 4 * (size_t)N * nsplit);
   } else {
     hipLaunchKernelGGL(k_influence_fp64, dim3(bc, nsplit), dim3(kTI), 0, ctx->stream, N, m->f, m->order, n_s, sx, sy,
                        sz, sq, chunk, part);
   }
   OBEM_HIP(ctx, hipGetLastError());
-  hipLaunchKernelGGL(k_influence_rhs, dim3(bc), dim3(256), 0, ctx->stream, N, nsplit, part, m->order, m->f, m->kind, rhs, rhs_out,
-                     vbar, ebx, eby, ebz);
+  hipLaunchKernelGGL(k_influence_rhs, dim3(bc), dim3(256), 0, ctx->stream, N, n_s > 0 ? nslot : 1, part, m->order,
+                     m->f, m->kind, rhs, rhs_out, vbar, ebx, eby, ebz);
   OBEM_HIP(ctx, hipGetLastError());
   return OBEM_OK;
 }
