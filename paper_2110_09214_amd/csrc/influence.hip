@@ -24,15 +24,6 @@ namespace obem {
 
 constexpr int kTI = 256;
 
-__device__ __forceinline__ void neum_i(float &s, float &c, float v) {
-  float t = s + v;
-  if (fabsf(s) >= fabsf(v))
-    c += (s - t) + v;
-  else
-    c += (v - t) + s;
-  s = t;
-}
-
 // FP64 closed form of one cell at one charge: q IV and q IE.
 __device__ __forceinline__ void infl_closed(const double *__restrict__ f, int N, int k, double px, double py,
                                             double pz, double q, double &sv, double &ex, double &ey, double &ez) {
@@ -50,127 +41,157 @@ __device__ __forceinline__ void infl_closed(const double *__restrict__ f, int N,
   ez = fma(q, IE.z, ez);
 }
 
-// One LDS tile of charges (recentred FP32 position, charge) against the
-// thread's cell, pairs beyond 3 D only (the near kernel takes the others):
-// 7-point rule within 64 D, 3-point rule beyond.  FOLDQ: all charges of the
-// tile are equal and the charge is applied by the caller.
-template <bool FOLDQ>
-__device__ __forceinline__ void infl_tile(const float4 *P, int cnt, float g0, float g1, float g2, const float *q7,
-                                          const float *q3, float w0, float wa, float wb, float w3, float lim_near,
-                                          float lim_far, float &pv, float &px, float &py, float &pz) {
-  for (int jj = 0; jj < cnt; ++jj) {
-    const float4 p = P[jj];
-    const float R2 = dist2f(p.x, p.y, p.z, g0, g1, g2);
-    const bool nearp = R2 < lim_near;
-    const bool need7 = !nearp && R2 < lim_far;
-    float sv = 0, ex = 0, ey = 0, ez = 0;
-    if (__any(need7)) {
-      if (!nearp) {
+// Far part of the mixed influence, charge-major: a workgroup owns 8 cells
+// (consecutive in the mesh's Morton order) and streams its chunk of the
+// charges in blocks of 1024, 4 per thread (one from each 256-charge tile of
+// the block, so a wave's lanes hold 64 consecutive, spatially close charges).
+// Per cell the rule is chosen per wave over those close charges (7 points
+// within 64 D, 3 beyond; pairs within 3 D are left to the near kernel), and
+// each thread adds q (IV, IE) of its charges into 8 x 4 FP32 sums.  The sums
+// of a block are reduced over the 256 threads through LDS in fixed order and
+// in FP64 (8 partial sums of 32 threads each, then the 8 in order) and
+// accumulated in FP64 by 32 threads, one per (cell, component).
+constexpr int kCB = 8;   // cells per workgroup
+constexpr int kCS = 4;   // charges per thread and block
+constexpr int kUP = kTI + 4;
+
+// One cell of the far kernel's LDS tile, recentred FP32, 11 float4 records:
+//   c[0] = centroid, (3 D)^2          c[1] = (64 D)^2, area {w0, wa, wb}
+//   c[2..7] = the 7 rule points (21 floats), area / 3
+//   c[8..10] = the 3 rule points (9 floats), 3 unused
+struct ICell {
+  float4 c[11];
+};
+
+// sum over m of w_m {1/|e_m|, e_m/|e_m|^3}, e_m = p - point m
+template <int M>
+__device__ __forceinline__ void infl_points(float px, float py, float pz, const float *q, const float *w, float &sv,
+                                            float &ex, float &ey, float &ez) {
 #pragma unroll
-        for (int m = 0; m < 7; ++m) {
-          const float w = (m == 0) ? w0 : (m < 4 ? wa : wb);
-          const float ax = p.x - q7[3 * m], ay = p.y - q7[3 * m + 1], az = p.z - q7[3 * m + 2];
-          const float rr = fmaf(ax, ax, fmaf(ay, ay, az * az));
-          const float ri = __builtin_amdgcn_rsqf(rr);
-          const float wr = w * ri;
-          const float t = wr * (ri * ri);
-          sv += wr;
-          ex = fmaf(t, ax, ex);
-          ey = fmaf(t, ay, ey);
-          ez = fmaf(t, az, ez);
-        }
-      }
-    } else if (!nearp) {
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        const float ax = p.x - q3[3 * m], ay = p.y - q3[3 * m + 1], az = p.z - q3[3 * m + 2];
-        const float rr = fmaf(ax, ax, fmaf(ay, ay, az * az));
-        const float ri = __builtin_amdgcn_rsqf(rr);
-        const float wr = w3 * ri;
-        const float t = wr * (ri * ri);
-        sv += wr;
-        ex = fmaf(t, ax, ex);
-        ey = fmaf(t, ay, ey);
-        ez = fmaf(t, az, ez);
-      }
-    }
-    if (FOLDQ) {
-      pv += sv;
-      px += ex;
-      py += ey;
-      pz += ez;
-    } else {
-      pv = fmaf(p.w, sv, pv);
-      px = fmaf(p.w, ex, px);
-      py = fmaf(p.w, ey, py);
-      pz = fmaf(p.w, ez, pz);
-    }
+  for (int m = 0; m < M; ++m) {
+    const float ax = px - q[3 * m], ay = py - q[3 * m + 1], az = pz - q[3 * m + 2];
+    const float rr = fmaf(ax, ax, fmaf(ay, ay, az * az));
+    const float ri = __builtin_amdgcn_rsqf(rr);
+    const float wr = w[m] * ri;
+    const float t = wr * (ri * ri);
+    sv += wr;
+    ex = fmaf(t, ax, ex);
+    ey = fmaf(t, ay, ey);
+    ez = fmaf(t, az, ez);
   }
 }
 
-// Far part of the mixed influence (pairs beyond 3 D), charges in (charge
-// sign, Morton) order so that nearly every LDS tile holds one charge value.
 __global__ __launch_bounds__(kTI) void k_influence_mixed(int N, const double *__restrict__ f,
                                                          const int32_t *__restrict__ ord, int n_s,
                                                          const double *__restrict__ sx,
                                                          const double *__restrict__ sy,
                                                          const double *__restrict__ sz,
                                                          const double *__restrict__ sq, int chunk, double *part) {
-  __shared__ float4 P[kTI];
+  __shared__ ICell T[kCB];
+  __shared__ __align__(16) float U[kCB * 4][kUP];
+  __shared__ double red[kTI / (kCB * 4)][kCB * 4];
   const int tid = threadIdx.x;
-  const int k = blockIdx.x * kTI + tid;  // sorted position
-  const bool active = k < N;
-  const int kk = ord[active ? k : N - 1];  // cell index
-  const int k0 = ord[blockIdx.x * kTI];
-  const double c0 = f[(size_t)MF_GX * N + k0], c1 = f[(size_t)MF_GY * N + k0], c2 = f[(size_t)MF_GZ * N + k0];
-  // own cell, FP32 relative to the workgroup centre
-  const float g0 = (float)(f[(size_t)MF_GX * N + kk] - c0), g1 = (float)(f[(size_t)MF_GY * N + kk] - c1),
-              g2 = (float)(f[(size_t)MF_GZ * N + kk] - c2);
-  float q7[21], q3[9];
-#pragma unroll
-  for (int m = 0; m < 21; ++m)
-    q7[m] = (float)(f[(size_t)(MF_Q7 + m) * N + kk] - (m % 3 == 0 ? c0 : (m % 3 == 1 ? c1 : c2)));
-#pragma unroll
-  for (int m = 0; m < 9; ++m)
-    q3[m] = (float)(f[(size_t)(MF_Q3 + m) * N + kk] - (m % 3 == 0 ? c0 : (m % 3 == 1 ? c1 : c2)));
-  const double area = f[(size_t)MF_AREA * N + kk], D = f[(size_t)MF_DIAM * N + kk];
-  const float w0 = (float)(area * Rule7::w0), wa = (float)(area * Rule7::wa), wb = (float)(area * Rule7::wb),
-              w3 = (float)(area / 3.0);
-  const float lim_near = (float)(kNearMixed * kNearMixed * D * D), lim_far = (float)(kFar3Mixed * kFar3Mixed * D * D);
-  float hv = 0, hx = 0, hy = 0, hz = 0, lv = 0, lx = 0, ly = 0, lz = 0;
-  const int jb = blockIdx.y * chunk, je = min(n_s, jb + chunk);
-  for (int jt = jb; jt < je; jt += kTI) {
-    const int cnt = min(kTI, je - jt);
-    const float q0 = (float)sq[jt];
-    float qj = q0;
-    __syncthreads();
-    if (tid < cnt) {
-      const int j = jt + tid;
-      qj = (float)sq[j];
-      P[tid] = make_float4((float)(sx[j] - c0), (float)(sy[j] - c1), (float)(sz[j] - c2), qj);
-    }
-    const bool uniform = __syncthreads_and(qj == q0);
-    float pv = 0, px = 0, py = 0, pz = 0;
-    if (uniform) {
-      infl_tile<true>(P, cnt, g0, g1, g2, q7, q3, w0, wa, wb, w3, lim_near, lim_far, pv, px, py, pz);
-      pv *= q0;
-      px *= q0;
-      py *= q0;
-      pz *= q0;
-    } else {
-      infl_tile<false>(P, cnt, g0, g1, g2, q7, q3, w0, wa, wb, w3, lim_near, lim_far, pv, px, py, pz);
-    }
-    neum_i(hv, lv, pv);
-    neum_i(hx, lx, px);
-    neum_i(hy, ly, py);
-    neum_i(hz, lz, pz);
+  const int kb = blockIdx.x * kCB;  // first sorted position of the workgroup's cells
+  // recentred on the first cell of the 256-cell group, as the near kernel
+  const int kr = ord[(kb / kTI) * kTI];
+  const double c0 = f[(size_t)MF_GX * N + kr], c1 = f[(size_t)MF_GY * N + kr], c2 = f[(size_t)MF_GZ * N + kr];
+  for (int idx = tid; idx < 30 * kCB; idx += kTI) {
+    const int m = idx / kCB, k = idx % kCB;
+    const int kk = ord[min(kb + k, N - 1)];
+    const int src = (m < 21) ? MF_Q7 + m : MF_Q3 + (m - 21);
+    const int c = (m < 21 ? m : m - 21) % 3;
+    reinterpret_cast<float *>(&T[k])[m < 21 ? 8 + m : 32 + (m - 21)] =
+        (float)(f[(size_t)src * N + kk] - (c == 0 ? c0 : (c == 1 ? c1 : c2)));
   }
-  if (active) {
-    const size_t o = (size_t)blockIdx.y * 4 * N;
-    part[o + k] = (double)hv + (double)lv;
-    part[o + (size_t)N + k] = (double)hx + (double)lx;
-    part[o + 2 * (size_t)N + k] = (double)hy + (double)ly;
-    part[o + 3 * (size_t)N + k] = (double)hz + (double)lz;
+  if (tid < kCB) {
+    const int kk = ord[min(kb + tid, N - 1)];
+    const double D = f[(size_t)MF_DIAM * N + kk], ar = f[(size_t)MF_AREA * N + kk];
+    T[tid].c[0] = make_float4((float)(f[(size_t)MF_GX * N + kk] - c0), (float)(f[(size_t)MF_GY * N + kk] - c1),
+                              (float)(f[(size_t)MF_GZ * N + kk] - c2), (float)(kNearMixed * kNearMixed * D * D));
+    T[tid].c[1] = make_float4((float)(kFar3Mixed * kFar3Mixed * D * D), (float)(ar * Rule7::w0),
+                              (float)(ar * Rule7::wa), (float)(ar * Rule7::wb));
+    reinterpret_cast<float *>(&T[tid])[29] = (float)(ar / 3.0);
+    for (int u = 41; u < 44; ++u) reinterpret_cast<float *>(&T[tid])[u] = 0.f;
+  }
+  __syncthreads();
+  double accd = 0.0;  // threads 0..31: (cell tid / 4, component tid % 4)
+  const int jb = blockIdx.y * chunk, je = min(n_s, jb + chunk);
+  for (int j0 = jb; j0 < je; j0 += kTI * kCS) {
+    float px[kCS], py[kCS], pz[kCS], pq[kCS];
+#pragma unroll
+    for (int c = 0; c < kCS; ++c) {
+      const int j = j0 + c * kTI + tid;
+      const bool ok = j < je;
+      const int jj = ok ? j : jb;  // a real position with charge 0
+      px[c] = (float)(sx[jj] - c0);
+      py[c] = (float)(sy[jj] - c1);
+      pz[c] = (float)(sz[jj] - c2);
+      pq[c] = ok ? (float)sq[jj] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < kCB; ++k) {
+      const float4 g = T[k].c[0], h = T[k].c[1];
+      float av = 0.f, ax = 0.f, ay = 0.f, az = 0.f;
+#pragma unroll
+      for (int c = 0; c < kCS; ++c) {
+        const float R2 = dist2f(px[c], py[c], pz[c], g.x, g.y, g.z);
+        const bool nearp = R2 < g.w;  // taken by k_influence_near in FP64
+        const bool need7 = !nearp && R2 < h.x;
+        float sv = 0.f, ex = 0.f, ey = 0.f, ez = 0.f;
+        if (__any(need7)) {
+          if (!nearp) {
+            float q[21];
+#pragma unroll
+            for (int u = 0; u < 21; ++u) q[u] = reinterpret_cast<const float *>(&T[k])[8 + u];
+            const float w[7] = {h.y, h.z, h.z, h.z, h.w, h.w, h.w};
+            infl_points<7>(px[c], py[c], pz[c], q, w, sv, ex, ey, ez);
+          }
+        } else if (!nearp) {
+          float q[9];
+#pragma unroll
+          for (int u = 0; u < 9; ++u) q[u] = reinterpret_cast<const float *>(&T[k])[32 + u];
+          const float w3 = T[k].c[7].y;
+          const float w[3] = {w3, w3, w3};
+          infl_points<3>(px[c], py[c], pz[c], q, w, sv, ex, ey, ez);
+        }
+        av = fmaf(pq[c], sv, av);
+        ax = fmaf(pq[c], ex, ax);
+        ay = fmaf(pq[c], ey, ay);
+        az = fmaf(pq[c], ez, az);
+      }
+      U[4 * k][tid] = av;
+      U[4 * k + 1][tid] = ax;
+      U[4 * k + 2][tid] = ay;
+      U[4 * k + 3][tid] = az;
+    }
+    __syncthreads();
+    {
+      const int row = tid % (kCB * 4), p = tid / (kCB * 4);
+      const float4 *r = reinterpret_cast<const float4 *>(&U[row][p * (kTI / 8)]);
+      // FP64 from here on: the charges come sorted by sign, so the block sums
+      // are large and cancel only between blocks
+      double a = 0.0;
+#pragma unroll
+      for (int m = 0; m < kTI / 8 / 4; ++m) {
+        const float4 v = r[m];
+        a += (double)v.x;
+        a += (double)v.y;
+        a += (double)v.z;
+        a += (double)v.w;
+      }
+      red[p][row] = a;
+    }
+    __syncthreads();
+    if (tid < kCB * 4) {
+      double t = red[0][tid];
+#pragma unroll
+      for (int p = 1; p < kTI / (kCB * 4); ++p) t += red[p][tid];
+      accd += t;
+    }
+  }
+  if (tid < kCB * 4) {
+    const int k = kb + tid / 4;
+    if (k < N) part[(size_t)blockIdx.y * 4 * N + (size_t)(tid % 4) * N + k] = accd;
   }
 }
 
@@ -335,12 +356,14 @@ obem_status influence_rhs(obem_ctx *ctx, const obem_meshh *m, int64_t n_src, con
                           double *vbar, double *ebx, double *eby, double *ebz) {
   const int N = (int)m->n, n_s = (int)n_src;
   const int bc = (N + kTI - 1) / kTI;
+  // workgroups along the cells: 256 cells each (FP64), 8 (mixed far kernel)
+  const int bw = (prec == OBEM_MIXED) ? (N + kCB - 1) / kCB : bc;
   int nsplit = 1, chunk = std::max(n_s, 1);
   if (n_s > 0) {
-    nsplit = std::max(1, std::min((2048 + bc - 1) / bc, (n_s + 1023) / 1024));
+    nsplit = std::max(1, std::min((2048 + bw - 1) / bw, (n_s + 1023) / 1024));
     nsplit = std::min(nsplit, 64);
     chunk = (n_s + nsplit - 1) / nsplit;
-    chunk = (chunk + kTI - 1) / kTI * kTI;
+    chunk = (chunk + kTI * kCS - 1) / (kTI * kCS) * (kTI * kCS);
     nsplit = (n_s + chunk - 1) / chunk;
   }
   // mixed: partial slots of the near kernel after those of the far kernel
@@ -359,7 +382,7 @@ obem_status influence_rhs(obem_ctx *ctx, const obem_meshh *m, int64_t n_src, con
     SourceOrder so;
     obem_status st = order_sources(ctx, n_s, sx, sy, sz, sq, false, &so);
     if (st) return st;
-    hipLaunchKernelGGL(k_influence_mixed, dim3(bc, nsplit), dim3(kTI), 0, ctx->stream, N, m->f, m->order, n_s, so.x,
+    hipLaunchKernelGGL(k_influence_mixed, dim3(bw, nsplit), dim3(kTI), 0, ctx->stream, N, m->f, m->order, n_s, so.x,
                        so.y, so.z, so.q, chunk, part);
     hipLaunchKernelGGL(k_influence_near, dim3(bn, nslot - nsplit), dim3(kNW), 0, ctx->stream, N, m->f, m->order, n_s,
                        so.x, so.y, so.z, so.q, so.tbox, tchunk, part + 4 * (size_t)N * nsplit);
