@@ -151,10 +151,11 @@ __global__ __launch_bounds__(256) void k_mesh_derive(int n, double *f, const int
   }
 }
 
-// Near-zone bounding spheres of consecutive 64-cell tiles: centre = mean
-// centroid, radius = max_k (|c_k - centre| + 3 D_k), inflated by 1e-6
-// relative so FP32 rounding of the per-pair test cannot escape it.
-__global__ __launch_bounds__(64) void k_tile_spheres(int n, const double *f, double *tiles) {
+// Zone bounding spheres of consecutive 64-cell tiles: centre = mean
+// centroid, radius = max_k (|c_k - centre| + zone D_k) (zone 3: the mixed
+// near zone, 48: the FP64 closed-form zone), inflated by 1e-6 relative so
+// FP32 rounding of the per-pair test cannot escape it.
+__global__ __launch_bounds__(64) void k_tile_spheres(int n, const double *f, double zone, double *tiles) {
   const int t = blockIdx.x;
   const int k = t * 64 + threadIdx.x;
   const bool ok = k < n;
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(64) void k_tile_spheres(int n, const double *f, dou
   double r = 0.0;
   if (ok) {
     double dx = f[(size_t)MF_GX * n + k] - c[0], dy = f[(size_t)MF_GY * n + k] - c[1], dz = f[(size_t)MF_GZ * n + k] - c[2];
-    r = sqrt(dx * dx + dy * dy + dz * dz) + 3.0 * f[(size_t)MF_DIAM * n + k];
+    r = sqrt(dx * dx + dy * dy + dz * dz) + zone * f[(size_t)MF_DIAM * n + k];
   }
   for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o));
   if (threadIdx.x == 0) {
@@ -291,6 +292,7 @@ static obem_status bind_fill(obem_ctx *ctx, const obem_mesh *mesh, obem_meshh *m
   const int ntile = (int)((n + 63) / 64);
   if (hipMalloc(&m->f, sizeof(double) * MF_COUNT * (size_t)n) != hipSuccess ||
       hipMalloc(&m->kind, (size_t)n) != hipSuccess || hipMalloc(&m->tiles, sizeof(double) * 4 * ntile) != hipSuccess ||
+      hipMalloc(&m->tiles48, sizeof(double) * 4 * ntile) != hipSuccess ||
       hipMalloc(&m->order, sizeof(int32_t) * n) != hipSuccess) {
     hipGetLastError();
     return fail(ctx, OBEM_ENOMEM, "mesh allocation failed");
@@ -304,7 +306,8 @@ static obem_status bind_fill(obem_ctx *ctx, const obem_mesh *mesh, obem_meshh *m
   hipLaunchKernelGGL(k_mesh_derive, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, (int)n, m->f,
                      m->kind, mesh->eps_r1, mesh->eps_r2, bad);
   OBEM_HIP(ctx, hipGetLastError());
-  hipLaunchKernelGGL(k_tile_spheres, dim3(ntile), dim3(64), 0, ctx->stream, (int)n, m->f, m->tiles);
+  hipLaunchKernelGGL(k_tile_spheres, dim3(ntile), dim3(64), 0, ctx->stream, (int)n, m->f, kNearMixed, m->tiles);
+  hipLaunchKernelGGL(k_tile_spheres, dim3(ntile), dim3(64), 0, ctx->stream, (int)n, m->f, kQuadFp64, m->tiles48);
   OBEM_HIP(ctx, hipGetLastError());
   {
     TargetOrder co;
@@ -341,6 +344,7 @@ static void free_mesh(obem_meshh *m) {
   hipFree(m->f);
   hipFree(m->kind);
   hipFree(m->tiles);
+  hipFree(m->tiles48);
   hipFree(m->order);
   bem_release(m);
   hipFree(m->grid_start);

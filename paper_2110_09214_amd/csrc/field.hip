@@ -458,43 +458,70 @@ __global__ __launch_bounds__(kThreads) void k_panel_near(int n_t, const double *
   }
 }
 
-// FP64 mode: closed form up to 48 diameters, FP64 7-point rule beyond.  All
-// lanes read the same cell, so cell data come through scalar loads.
+// FP64 mode: closed form up to 48 diameters (k_panel_fp64_near), FP64
+// 7-point rule beyond (k_panel_fp64).  Both decide with the same FP64 test
+// |x - c_k|^2 >= (48 D_k)^2 on the unmodified coordinates.
+constexpr int kPF = 32;  // cells per LDS tile of the FP64 far kernel
+
+// One cell of the FP64 far kernel's LDS tile: centroid, (48 D)^2, the 7 rule
+// points, area sigma {w0, wa, wa, wa, wb, wb, wb} folded per point.
+struct CellF64 {
+  double g[3], lim, q[21], w[7];
+};
+
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps
+// y <- y + y (1/2 - x/2 y^2) (quadratic convergence; a few ulp at the end).
+__device__ __forceinline__ double rsqrt_f64(double x) {
+  const double h = 0.5 * x;
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(y, fma(-h * y, y, 0.5), y);
+  y = fma(y, fma(-h * y, y, 0.5), y);
+  return y;
+}
+
 template <bool WANT_V>
 __global__ __launch_bounds__(kThreads) void k_panel_fp64(int n_t, const double *__restrict__ xs, int N,
                                                          const double *__restrict__ f,
                                                          const double *__restrict__ sigma, double *acc) {
-  const int i = blockIdx.x * kThreads + threadIdx.x;
+  __shared__ CellF64 T[kPF];
+  const int tid = threadIdx.x;
+  const int i = blockIdx.x * kThreads + tid;
   const bool active = i < n_t;
   const int ii = active ? i : 0;
   const double x0 = xs[ii], x1 = xs[(size_t)n_t + ii], x2 = xs[2 * (size_t)n_t + ii];
   double ex = 0.0, ey = 0.0, ez = 0.0, ev = 0.0;
-  for (int k = 0; k < N; ++k) {
-    const double dx = x0 - f[(size_t)MF_GX * N + k], dy = x1 - f[(size_t)MF_GY * N + k],
-                 dz = x2 - f[(size_t)MF_GZ * N + k];
-    const double D = f[(size_t)MF_DIAM * N + k];
-    const double R2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    const bool quad = R2 >= kQuadFp64 * kQuadFp64 * D * D;
-    const double sig = sigma[k];
-    if (!__all(quad)) {
-      if (!quad) near_cell<WANT_V>(f, N, k, sig, x0, x1, x2, ex, ey, ez, ev);
+  for (int k0 = 0; k0 < N; k0 += kPF) {
+    const int cnt = min(kPF, N - k0);
+    __syncthreads();
+    for (int idx = tid; idx < 21 * kPF; idx += kThreads) {
+      const int m = idx / kPF, k = idx % kPF;
+      if (k < cnt) T[k].q[m] = f[(size_t)(MF_Q7 + m) * N + k0 + k];
     }
-    if (__any(quad)) {
-      if (quad) {
-        const double as = f[(size_t)MF_AREA * N + k] * sig;
+    if (tid < cnt) {
+      const int kk = k0 + tid;
+      const double D = f[(size_t)MF_DIAM * N + kk];
+      const double as = f[(size_t)MF_AREA * N + kk] * sigma[kk];
+      T[tid].g[0] = f[(size_t)MF_GX * N + kk];
+      T[tid].g[1] = f[(size_t)MF_GY * N + kk];
+      T[tid].g[2] = f[(size_t)MF_GZ * N + kk];
+      T[tid].lim = kQuadFp64 * kQuadFp64 * D * D;
 #pragma unroll
-        for (int q = 0; q < 7; ++q) {
-          const double w = as * (q == 0 ? Rule7::w0 : (q < 4 ? Rule7::wa : Rule7::wb));
-          const double qx = x0 - f[(size_t)(MF_Q7 + 3 * q) * N + k];
-          const double qy = x1 - f[(size_t)(MF_Q7 + 3 * q + 1) * N + k];
-          const double qz = x2 - f[(size_t)(MF_Q7 + 3 * q + 2) * N + k];
-          const double rr = fma(qx, qx, fma(qy, qy, qz * qz));
-          const double ri = 1.0 / sqrt(rr);
-          const double wr = w * ri;
-          const double s = wr * ri * ri;
-          ex = fma(s, qx, ex);
-          ey = fma(s, qy, ey);
-          ez = fma(s, qz, ez);
+      for (int m = 0; m < 7; ++m) T[tid].w[m] = as * (m == 0 ? Rule7::w0 : (m < 4 ? Rule7::wa : Rule7::wb));
+    }
+    __syncthreads();
+    for (int k = 0; k < cnt; ++k) {
+      const double dx = x0 - T[k].g[0], dy = x1 - T[k].g[1], dz = x2 - T[k].g[2];
+      const double R2 = fma(dx, dx, fma(dy, dy, dz * dz));
+      if (R2 >= T[k].lim) {  // the near kernel takes the others
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+          const double qx = x0 - T[k].q[3 * m], qy = x1 - T[k].q[3 * m + 1], qz = x2 - T[k].q[3 * m + 2];
+          const double ri = rsqrt_f64(fma(qx, qx, fma(qy, qy, qz * qz)));
+          const double wr = T[k].w[m] * ri;
+          const double t = wr * ri * ri;
+          ex = fma(t, qx, ex);
+          ey = fma(t, qy, ey);
+          ez = fma(t, qz, ez);
           if (WANT_V) ev += wr;
         }
       }
@@ -505,6 +532,57 @@ __global__ __launch_bounds__(kThreads) void k_panel_fp64(int n_t, const double *
     acc[(size_t)n_t + i] = ey;
     acc[2 * (size_t)n_t + i] = ez;
     acc[3 * (size_t)n_t + i] = ev;
+  }
+}
+
+// FP64 closed-form zone (R < 48 D), added to the far kernel's result.  Each
+// wave bounds its 64 targets by a sphere and visits the 64-cell tiles whose
+// zone sphere (centre, max_k |c_k - centre| + 48 D_k) it meets.
+template <bool WANT_V>
+__global__ __launch_bounds__(kThreads) void k_panel_fp64_near(int n_t, const double *__restrict__ xs, int N,
+                                                              const double *__restrict__ f,
+                                                              const double *__restrict__ sigma,
+                                                              const double *__restrict__ tiles, double *acc) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const bool active = i < n_t;
+  const int i0 = blockIdx.x * kThreads;
+  const int ii = active ? i : i0;
+  const double x0 = xs[ii], x1 = xs[(size_t)n_t + ii], x2 = xs[2 * (size_t)n_t + ii];
+  double lo0 = x0, lo1 = x1, lo2 = x2, hi0 = x0, hi1 = x1, hi2 = x2;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo0 = fmin(lo0, __shfl_xor(lo0, o));
+    lo1 = fmin(lo1, __shfl_xor(lo1, o));
+    lo2 = fmin(lo2, __shfl_xor(lo2, o));
+    hi0 = fmax(hi0, __shfl_xor(hi0, o));
+    hi1 = fmax(hi1, __shfl_xor(hi1, o));
+    hi2 = fmax(hi2, __shfl_xor(hi2, o));
+  }
+  const double wc0 = 0.5 * (lo0 + hi0), wc1 = 0.5 * (lo1 + hi1), wc2 = 0.5 * (lo2 + hi2);
+  const double wr = 0.5 * sqrt((hi0 - lo0) * (hi0 - lo0) + (hi1 - lo1) * (hi1 - lo1) + (hi2 - lo2) * (hi2 - lo2));
+  const int ntile = (N + 63) / 64;
+  double ex = 0.0, ey = 0.0, ez = 0.0, ev = 0.0;
+  for (int t = 0; t < ntile; ++t) {
+    const double dx = wc0 - tiles[4 * t], dy = wc1 - tiles[4 * t + 1], dz = wc2 - tiles[4 * t + 2];
+    const double rs = (wr + tiles[4 * t + 3]) * (1.0 + 1e-9);
+    if (dx * dx + dy * dy + dz * dz > rs * rs) continue;  // wave-uniform
+    const int k0 = t * 64, cnt = min(64, N - k0);
+    for (int k = 0; k < cnt; ++k) {
+      const int kk = k0 + k;
+      const double gx = x0 - f[(size_t)MF_GX * N + kk], gy = x1 - f[(size_t)MF_GY * N + kk],
+                   gz = x2 - f[(size_t)MF_GZ * N + kk];
+      const double D = f[(size_t)MF_DIAM * N + kk];
+      const bool nearp = active && !(fma(gx, gx, fma(gy, gy, gz * gz)) >= kQuadFp64 * kQuadFp64 * D * D);
+      if (__any(nearp)) {
+        if (nearp) near_cell<WANT_V>(f, N, kk, sigma[kk], x0, x1, x2, ex, ey, ez, ev);
+      }
+    }
+  }
+  if (active) {
+    acc[i] += ex;
+    acc[(size_t)n_t + i] += ey;
+    acc[2 * (size_t)n_t + i] += ez;
+    if (WANT_V) acc[3 * (size_t)n_t + i] += ev;
   }
 }
 
@@ -525,10 +603,15 @@ obem_status launch_panel_field(obem_ctx *ctx, const obem_meshh *m, const double 
                          acc);
     }
   } else {
-    if (want_v)
+    if (want_v) {
       hipLaunchKernelGGL(k_panel_fp64<true>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, acc);
-    else
+      hipLaunchKernelGGL(k_panel_fp64_near<true>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma,
+                         m->tiles48, acc);
+    } else {
       hipLaunchKernelGGL(k_panel_fp64<false>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, acc);
+      hipLaunchKernelGGL(k_panel_fp64_near<false>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma,
+                         m->tiles48, acc);
+    }
   }
   OBEM_HIP(ctx, hipGetLastError());
   return OBEM_OK;

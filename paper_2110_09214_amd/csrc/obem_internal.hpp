@@ -66,7 +66,8 @@ struct obem_meshh {
   int8_t *kind = nullptr;
   double bbox_lo[3], bbox_hi[3];
   double max_diam = 0;
-  double *tiles = nullptr;    // per 64-cell tile: centre (3), near-zone radius
+  double *tiles = nullptr;    // per 64-cell tile: centre (3), near-zone radius (3 D)
+  double *tiles48 = nullptr;  // the same for the FP64 closed-form zone (48 D)
   int32_t *order = nullptr;   // cell indices in Morton order of the centroids
   // collocation system (lazy)
   double *A = nullptr;        // n x n column-major
