@@ -40,15 +40,15 @@ void *ws_get(obem_ctx *ctx, int slot, size_t bytes) {
   if (b.bytes >= bytes) return b.p;
   if (b.p) {
     // the buffer may still be in use by queued work on the context stream
-    hipStreamSynchronize(ctx->stream);
-    hipFree(b.p);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(b.p);
     b.p = nullptr;
     b.bytes = 0;
   }
   size_t want = std::max(bytes, (size_t)4096);
   want = (want + 255) / 256 * 256;
   if (hipMalloc(&b.p, want) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     b.p = nullptr;
     return nullptr;
   }
@@ -64,7 +64,7 @@ static hipEvent_t prof_event(obem_ctx *ctx) {
   }
   hipEvent_t e = nullptr;
   if (hipEventCreate(&e) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return nullptr;
   }
   return e;
@@ -74,15 +74,15 @@ int prof_begin(obem_ctx *ctx, const char *name) {
   if (!ctx || !ctx->prof) return -1;
   obem_prof_rec r{name, prof_event(ctx), prof_event(ctx)};
   if (!r.start || !r.stop) return -1;
-  hipEventRecord(r.start, ctx->stream);
-  hipEventRecord(r.stop, ctx->stream);  // overwritten by prof_end
+  (void)hipEventRecord(r.start, ctx->stream);
+  (void)hipEventRecord(r.stop, ctx->stream);  // overwritten by prof_end
   ctx->prof_recs.push_back(r);
   return (int)ctx->prof_recs.size() - 1;
 }
 
 void prof_end(obem_ctx *ctx, int idx) {
   if (!ctx || idx < 0 || idx >= (int)ctx->prof_recs.size()) return;
-  hipEventRecord(ctx->prof_recs[idx].stop, ctx->stream);
+  (void)hipEventRecord(ctx->prof_recs[idx].stop, ctx->stream);
 }
 
 bool is_device_ptr(const void *p) {
@@ -90,7 +90,7 @@ bool is_device_ptr(const void *p) {
   hipPointerAttribute_t attr;
   hipError_t e = hipPointerGetAttributes(&attr, p);
   if (e != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return false;
   }
   return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged ||
@@ -200,12 +200,12 @@ obem_status obem_create(obem_ctx **out, int device, void *hip_stream) {
   *out = nullptr;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return OBEM_EINVAL;
   }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return OBEM_EDEVICE;
   }
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return OBEM_EDEVICE;  // code objects are gfx950 only
@@ -218,17 +218,17 @@ obem_status obem_create(obem_ctx **out, int device, void *hip_stream) {
 
 obem_status obem_destroy(obem_ctx *ctx) {
   if (!ctx) return OBEM_EINVAL;
-  hipSetDevice(ctx->device);
-  hipStreamSynchronize(ctx->stream);
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
   for (auto &r : ctx->prof_recs) {
-    hipEventDestroy(r.start);
-    hipEventDestroy(r.stop);
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
   }
-  for (auto e : ctx->prof_pool) hipEventDestroy(e);
+  for (auto e : ctx->prof_pool) (void)hipEventDestroy(e);
   for (auto &b : ctx->ws)
-    if (b.p) hipFree(b.p);
+    if (b.p) (void)hipFree(b.p);
   solver_release(ctx);
-  hipGetLastError();
+  (void)hipGetLastError();
   delete ctx;
   return OBEM_OK;
 }
@@ -243,7 +243,7 @@ obem_status obem_profile_read(obem_ctx *ctx, int max_entries, char *names, doubl
                               int *n_out) {
   if (!ctx || !n_out || max_entries < 0 || (max_entries > 0 && (!names || !ms || !launches))) return OBEM_EINVAL;
   if (hipSetDevice(ctx->device) != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return fail(ctx, OBEM_EDEVICE, "synchronisation failed while reading the profile");
   }
   std::vector<std::string> keys;
@@ -252,7 +252,7 @@ obem_status obem_profile_read(obem_ctx *ctx, int max_entries, char *names, doubl
   for (auto &r : ctx->prof_recs) {
     float t = 0.f;
     if (hipEventElapsedTime(&t, r.start, r.stop) != hipSuccess) {
-      hipGetLastError();
+      (void)hipGetLastError();
       t = 0.f;
     }
     size_t k = 0;
@@ -294,7 +294,7 @@ static obem_status bind_fill(obem_ctx *ctx, const obem_mesh *mesh, obem_meshh *m
       hipMalloc(&m->kind, (size_t)n) != hipSuccess || hipMalloc(&m->tiles, sizeof(double) * 4 * ntile) != hipSuccess ||
       hipMalloc(&m->tiles48, sizeof(double) * 4 * ntile) != hipSuccess ||
       hipMalloc(&m->order, sizeof(int32_t) * n) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return fail(ctx, OBEM_ENOMEM, "mesh allocation failed");
   }
   for (int k = 0; k < 9; ++k)
@@ -341,15 +341,15 @@ static obem_status bind_fill(obem_ctx *ctx, const obem_mesh *mesh, obem_meshh *m
 }
 
 static void free_mesh(obem_meshh *m) {
-  hipFree(m->f);
-  hipFree(m->kind);
-  hipFree(m->tiles);
-  hipFree(m->tiles48);
-  hipFree(m->order);
+  (void)hipFree(m->f);
+  (void)hipFree(m->kind);
+  (void)hipFree(m->tiles);
+  (void)hipFree(m->tiles48);
+  (void)hipFree(m->order);
   bem_release(m);
-  hipFree(m->grid_start);
-  hipFree(m->grid_items);
-  hipGetLastError();
+  (void)hipFree(m->grid_start);
+  (void)hipFree(m->grid_items);
+  (void)hipGetLastError();
   delete m;
 }
 
@@ -387,8 +387,8 @@ obem_status obem_mesh_bind(obem_ctx *ctx, const obem_mesh *mesh, obem_meshh **ou
 
 obem_status obem_mesh_release(obem_ctx *ctx, obem_meshh *m) {
   if (!ctx || !m) return OBEM_EINVAL;
-  hipSetDevice(ctx->device);
-  hipStreamSynchronize(ctx->stream);
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
   free_mesh(m);
   return OBEM_OK;
 }

@@ -259,12 +259,12 @@ void solver_release(obem_ctx *ctx) {
 }
 
 void bem_release(obem_meshh *m) {
-  hipFree(m->A);
-  hipFree(m->LU);
-  hipFree(m->ipiv);
-  hipFree(m->info);
-  hipFree(m->ipiv64);
-  hipFree(m->info64);
+  (void)hipFree(m->A);
+  (void)hipFree(m->LU);
+  (void)hipFree(m->ipiv);
+  (void)hipFree(m->info);
+  (void)hipFree(m->ipiv64);
+  (void)hipFree(m->info64);
   m->A = m->LU = nullptr;
   m->ipiv = m->info = nullptr;
   m->ipiv64 = m->info64 = nullptr;
@@ -309,7 +309,7 @@ obem_status bem_factor(obem_ctx *ctx, obem_meshh *m) {
     else if (ok)
       ok = hipMalloc(&m->ipiv, sizeof(int32_t) * N) == hipSuccess && hipMalloc(&m->info, sizeof(int32_t)) == hipSuccess;
     if (!ok) {
-      hipGetLastError();
+      (void)hipGetLastError();
       bem_release(m);
       return fail(ctx, OBEM_ENOMEM, "cannot allocate the %d x %d collocation matrix and its factors", N, N);
     }
@@ -377,7 +377,7 @@ obem_status bem_factor(obem_ctx *ctx, obem_meshh *m) {
     // then keep X and release the factors
     double *X = nullptr;
     if (hipMalloc(&X, bytes) != hipSuccess) {
-      hipGetLastError();
+      (void)hipGetLastError();
       return fail(ctx, OBEM_ENOMEM, "cannot allocate the %d x %d inverse", N, N);
     }
     hipLaunchKernelGGL(k_identity, dim3(nb(N), std::min(N, 65535)), dim3(256), 0, ctx->stream, N, X);
@@ -385,12 +385,12 @@ obem_status bem_factor(obem_ctx *ctx, obem_meshh *m) {
     {
       OBEM_PROF(ctx, "lu");
       if (rocsolver_dgetrs_64(h, rocblas_operation_none, N, N, m->LU, N, m->ipiv64, X, N) != rocblas_status_success) {
-        hipFree(X);
+        (void)hipFree(X);
         return fail(ctx, OBEM_EDEVICE, "rocsolver_dgetrs failed");
       }
     }
     OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    hipFree(m->LU);
+    (void)hipFree(m->LU);
     m->LU = X;
   } else {
     {
@@ -482,7 +482,7 @@ extern "C" obem_status bem_solve_charges(obem_ctx *ctx, obem_meshh *mesh, const 
   if (!ctx) return OBEM_EINVAL;
   if (ctx->sticky) return OBEM_ESTATE;
   if (hipSetDevice(ctx->device) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return fail(ctx, OBEM_EDEVICE, "hipSetDevice failed");
   }
   if (!mesh) return fail(ctx, OBEM_EINVAL, "mesh is NULL");
@@ -497,7 +497,7 @@ extern "C" obem_status bem_solve_charges_adjoint(obem_ctx *ctx, obem_meshh *mesh
   if (!ctx) return OBEM_EINVAL;
   if (ctx->sticky) return OBEM_ESTATE;
   if (hipSetDevice(ctx->device) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return fail(ctx, OBEM_EDEVICE, "hipSetDevice failed");
   }
   if (!mesh) return fail(ctx, OBEM_EINVAL, "mesh is NULL");

@@ -408,7 +408,7 @@ extern "C" obem_status bem_influence(obem_ctx *ctx, const obem_meshh *mesh, int6
   if (!ctx) return OBEM_EINVAL;
   if (ctx->sticky) return OBEM_ESTATE;
   if (hipSetDevice(ctx->device) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return fail(ctx, OBEM_EDEVICE, "hipSetDevice failed");
   }
   if (!mesh) return fail(ctx, OBEM_EINVAL, "mesh is NULL");

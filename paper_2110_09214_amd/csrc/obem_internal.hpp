@@ -233,7 +233,7 @@ obem_status launch_map_acc(obem_ctx *ctx, const MapDev &g, const TargetOrder &to
     if (!(ctx)) return OBEM_EINVAL;                                          \
     if ((ctx)->sticky) return OBEM_ESTATE;                                   \
     if (hipSetDevice((ctx)->device) != hipSuccess) {                         \
-      hipGetLastError();                                                     \
+      (void)hipGetLastError();                                               \
       return fail(ctx, OBEM_EDEVICE, "hipSetDevice(%d) failed", (ctx)->device); \
     }                                                                        \
   } while (0)

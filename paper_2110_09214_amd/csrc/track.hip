@@ -880,7 +880,7 @@ static obem_status build_grid(obem_ctx *ctx, obem_meshh *m) {
     if (pass == 1) {
       if (hipMalloc(&m->grid_start, sizeof(int32_t) * (ncell + 1)) != hipSuccess ||
           hipMalloc(&m->grid_items, sizeof(int32_t) * std::max<size_t>(1, items.size())) != hipSuccess) {
-        hipGetLastError();
+        (void)hipGetLastError();
         return fail(ctx, OBEM_ENOMEM, "absorption grid allocation failed");
       }
       OBEM_HIP(ctx, hipMemcpy(m->grid_start, count.data(), sizeof(int32_t) * (ncell + 1), hipMemcpyHostToDevice));
@@ -964,7 +964,7 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
   if (!ctx) return OBEM_EINVAL;
   if (ctx->sticky) return OBEM_ESTATE;
   if (hipSetDevice(ctx->device) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return fail(ctx, OBEM_EDEVICE, "hipSetDevice failed");
   }
   if (!S || !gas || !p) return fail(ctx, OBEM_EINVAL, "state / gas / params is NULL");
