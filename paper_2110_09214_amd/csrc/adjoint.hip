@@ -705,7 +705,7 @@ __global__ __launch_bounds__(256) void k_scatter3(int n, const int32_t *__restri
 }
 
 static void split_for(int nb_rows, int n_cols, int *nsplit, int *chunk) {
-  int s = (2048 + nb_rows - 1) / nb_rows;
+  int s = (kSplitWorkgroups + nb_rows - 1) / nb_rows;
   s = std::max(1, std::min(s, (n_cols + 1023) / 1024));
   s = std::min(s, 64);
   int c = (n_cols + s - 1) / s;

@@ -282,9 +282,12 @@ __device__ __forceinline__ void near_cell(const double *__restrict__ f, int N, i
 }
 
 template <bool WANT_V>
+// gridDim.y splits the cells into ranges of cchunk; split y writes its sums
+// to part + 4 n_t y (part = acc when there is one split).
 __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double *__restrict__ xs, int N,
                                                           const double *__restrict__ f,
-                                                          const double *__restrict__ sigma, double *acc) {
+                                                          const double *__restrict__ sigma, int cchunk,
+                                                          double *part) {
   __shared__ PanelCell T[kPT];
   const int tid = threadIdx.x;
   const int i0 = blockIdx.x * kThreads;
@@ -296,8 +299,9 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
   const double x2 = active ? xs[2 * (size_t)n_t + i] : c2;
   const float r0 = (float)(x0 - c0), r1 = (float)(x1 - c1), r2 = (float)(x2 - c2);
   float hx = 0.f, hy = 0.f, hz = 0.f, hv = 0.f, lx = 0.f, ly = 0.f, lz = 0.f, lv = 0.f;
-  for (int k0 = 0; k0 < N; k0 += kPT) {
-    const int cnt = min(kPT, N - k0);
+  const int kb = blockIdx.y * cchunk, ke = min(N, kb + cchunk);
+  for (int k0 = kb; k0 < ke; k0 += kPT) {
+    const int cnt = min(kPT, ke - k0);
     __syncthreads();
     // staging, coalesced along the cells: the 30 rule coordinates of the
     // 64 cells, then one thread per cell for centroid, limits and weights
@@ -393,6 +397,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
     if (WANT_V) neumaier(hv, lv, pv);
   }
   if (active) {
+    double *acc = part + (size_t)blockIdx.y * 4 * n_t;
     acc[i] = (double)hx + (double)lx;
     acc[(size_t)n_t + i] = (double)hy + (double)ly;
     acc[2 * (size_t)n_t + i] = (double)hz + (double)lz;
@@ -482,7 +487,8 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
 template <bool WANT_V>
 __global__ __launch_bounds__(kThreads) void k_panel_fp64(int n_t, const double *__restrict__ xs, int N,
                                                          const double *__restrict__ f,
-                                                         const double *__restrict__ sigma, double *acc) {
+                                                         const double *__restrict__ sigma, int cchunk,
+                                                         double *part) {
   __shared__ CellF64 T[kPF];
   const int tid = threadIdx.x;
   const int i = blockIdx.x * kThreads + tid;
@@ -490,8 +496,9 @@ __global__ __launch_bounds__(kThreads) void k_panel_fp64(int n_t, const double *
   const int ii = active ? i : 0;
   const double x0 = xs[ii], x1 = xs[(size_t)n_t + ii], x2 = xs[2 * (size_t)n_t + ii];
   double ex = 0.0, ey = 0.0, ez = 0.0, ev = 0.0;
-  for (int k0 = 0; k0 < N; k0 += kPF) {
-    const int cnt = min(kPF, N - k0);
+  const int kb = blockIdx.y * cchunk, ke = min(N, kb + cchunk);
+  for (int k0 = kb; k0 < ke; k0 += kPF) {
+    const int cnt = min(kPF, ke - k0);
     __syncthreads();
     for (int idx = tid; idx < 21 * kPF; idx += kThreads) {
       const int m = idx / kPF, k = idx % kPF;
@@ -528,6 +535,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_fp64(int n_t, const double *
     }
   }
   if (active) {
+    double *acc = part + (size_t)blockIdx.y * 4 * n_t;
     acc[i] = ex;
     acc[(size_t)n_t + i] = ey;
     acc[2 * (size_t)n_t + i] = ez;
@@ -586,32 +594,59 @@ __global__ __launch_bounds__(kThreads) void k_panel_fp64_near(int n_t, const dou
   }
 }
 
+// acc = sum of the cell-split partials, in split order.
+__global__ __launch_bounds__(256) void k_panel_reduce(int n_t, int ns, const double *__restrict__ part, double *acc) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_t) return;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double s = 0.0;
+    for (int y = 0; y < ns; ++y) s += part[((size_t)y * 4 + c) * n_t + i];
+    acc[(size_t)c * n_t + i] = s;
+  }
+}
+
 obem_status launch_panel_field(obem_ctx *ctx, const obem_meshh *m, const double *sigma, const TargetOrder &to,
                                obem_precision prec, bool want_v, double *acc) {
   const int n_t = to.n;
   if (n_t == 0) return OBEM_OK;
   const int N = (int)m->n;
-  dim3 grid(nblk(n_t)), block(kThreads);
+  const int bt = nblk(n_t);
+  // cell ranges of >= 256 cells (a multiple of both LDS tiles), about
+  // kSplitWorkgroups workgroups in all
+  int ns = std::max(1, std::min((kSplitWorkgroups + bt - 1) / bt, (N + 255) / 256));
+  ns = std::min(ns, 64);
+  int cchunk = (N + ns - 1) / ns;
+  cchunk = (cchunk + 63) / 64 * 64;
+  ns = (N + cchunk - 1) / cchunk;
+  double *part = acc;
+  if (ns > 1) {
+    part = (double *)ws_get(ctx, WS_PANEL, sizeof(double) * 4 * (size_t)n_t * ns);
+    if (!part) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  }
+  dim3 grid(bt), gsplit(bt, ns), block(kThreads);
   OBEM_PROF(ctx, "panel");
+#define PANEL_FAR(K, V) hipLaunchKernelGGL(K<V>, gsplit, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, cchunk, part)
   if (prec == OBEM_MIXED) {
-    if (want_v) {
-      hipLaunchKernelGGL(k_panel_mixed<true>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, acc);
+    if (want_v) PANEL_FAR(k_panel_mixed, true); else PANEL_FAR(k_panel_mixed, false);
+  } else {
+    if (want_v) PANEL_FAR(k_panel_fp64, true); else PANEL_FAR(k_panel_fp64, false);
+  }
+#undef PANEL_FAR
+  if (ns > 1) hipLaunchKernelGGL(k_panel_reduce, dim3(nblk(n_t)), dim3(256), 0, ctx->stream, n_t, ns, part, acc);
+  if (prec == OBEM_MIXED) {
+    if (want_v)
       hipLaunchKernelGGL(k_panel_near<true>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, m->tiles, acc);
-    } else {
-      hipLaunchKernelGGL(k_panel_mixed<false>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, acc);
+    else
       hipLaunchKernelGGL(k_panel_near<false>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, m->tiles,
                          acc);
-    }
   } else {
-    if (want_v) {
-      hipLaunchKernelGGL(k_panel_fp64<true>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, acc);
+    if (want_v)
       hipLaunchKernelGGL(k_panel_fp64_near<true>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma,
                          m->tiles48, acc);
-    } else {
-      hipLaunchKernelGGL(k_panel_fp64<false>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, acc);
+    else
       hipLaunchKernelGGL(k_panel_fp64_near<false>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma,
                          m->tiles48, acc);
-    }
   }
   OBEM_HIP(ctx, hipGetLastError());
   return OBEM_OK;
@@ -942,8 +977,10 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
   const int n_s = (int)n_src;
   if (n_t == 0 || n_s == 0) return OBEM_OK;
   const int bt = nblk(n_t);
-  // enough workgroups to fill 256 CUs several times over, chunks >= 1024 sources
-  int nsplit = (2048 + bt - 1) / bt;
+  // about 128k workgroups (64 rounds of the 2048 resident ones), so that the
+  // last workgroups to start are short and the chip drains quickly at the
+  // end; chunks >= 1024 sources
+  int nsplit = (kSplitWorkgroups + bt - 1) / bt;
   nsplit = std::max(1, std::min(nsplit, (n_s + 1023) / 1024));
   nsplit = std::min(nsplit, 64);
   int chunk = (n_s + nsplit - 1) / nsplit;

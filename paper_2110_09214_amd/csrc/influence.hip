@@ -360,7 +360,7 @@ obem_status influence_rhs(obem_ctx *ctx, const obem_meshh *m, int64_t n_src, con
   const int bw = (prec == OBEM_MIXED) ? (N + kCB - 1) / kCB : bc;
   int nsplit = 1, chunk = std::max(n_s, 1);
   if (n_s > 0) {
-    nsplit = std::max(1, std::min((2048 + bw - 1) / bw, (n_s + 1023) / 1024));
+    nsplit = std::max(1, std::min((kSplitWorkgroups + bw - 1) / bw, (n_s + 1023) / 1024));
     nsplit = std::min(nsplit, 64);
     chunk = (n_s + nsplit - 1) / nsplit;
     chunk = (chunk + kTI * kCS - 1) / (kTI * kCS) * (kTI * kCS);

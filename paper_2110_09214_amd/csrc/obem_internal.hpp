@@ -31,6 +31,11 @@ constexpr double kKe = 1.0 / (4.0 * kPi * kEps0);
 constexpr double kNearMixed = 3.0;
 constexpr double kFar3Mixed = 64.0;
 constexpr double kQuadFp64 = 48.0;
+// Workgroup count that the source- or charge-split launches aim at: 64
+// rounds of the 2048 workgroups resident at once (8 per CU, 256 CUs), which
+// keeps the drain at the end of a launch short (measured: 3 % faster pairwise
+// field than one round-robin pass of 15,625 long workgroups at 4M charges).
+constexpr int kSplitWorkgroups = 131072;
 
 // Grow-only device buffer owned by a context.
 struct DevBuf {
@@ -42,7 +47,7 @@ struct DevBuf {
 enum WsSlot {
   WS_BBOX = 0, WS_KEYS0, WS_KEYS1, WS_IDX0, WS_IDX1, WS_SORT_TMP, WS_TSORT, WS_ACC, WS_PART,
   WS_NN, WS_MISC0, WS_MISC1, WS_MISC2, WS_MISC3, WS_MISC4, WS_MISC5, WS_MISC6, WS_MISC7,
-  WS_SOLVE0, WS_SOLVE1, WS_SOLVE2, WS_SRC, WS_SRCPERM, WS_SRCKEY, WS_SORT_TMP2, WS_TBOX, WS_MAP, WS_STATUS, WS_SRCINV,
+  WS_SOLVE0, WS_SOLVE1, WS_SOLVE2, WS_SRC, WS_SRCPERM, WS_SRCKEY, WS_SORT_TMP2, WS_TBOX, WS_MAP, WS_STATUS, WS_SRCINV, WS_PANEL,
   WS_COUNT
 };
 
