@@ -135,11 +135,13 @@ __device__ __forceinline__ void qpt_adj(float aw, float ex, float ey, float ez, 
 // LDS: every thread stores its value for each cell of the tile, then 8
 // threads per cell add 32 targets each (FP32, fixed order) and the 8
 // partials are added in FP64 in fixed order.
+// gridDim.y splits the cells into ranges of cchunk; split y writes its
+// position gradient to gx + 3 n_t y (summed in split order afterwards).
 __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *__restrict__ xs,
                                                         const double *__restrict__ ws, int N,
                                                         const double *__restrict__ f,
-                                                        const double *__restrict__ sigma, int want_x, double *gx,
-                                                        double *gsp) {
+                                                        const double *__restrict__ sigma, int want_x, int cchunk,
+                                                        double *gx, double *gsp) {
   __shared__ BCell T[kPB];
   __shared__ __align__(16) float U[kPB][kUPad];
   __shared__ double red[kParts][kPB];
@@ -155,8 +157,9 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
   const float wx = active ? (float)ws[i] : 0.f, wy = active ? (float)ws[(size_t)n_t + i] : 0.f,
               wz = active ? (float)ws[2 * (size_t)n_t + i] : 0.f;
   float hx = 0, hy = 0, hz = 0, lx = 0, ly = 0, lz = 0;
-  for (int k0 = 0; k0 < N; k0 += kPB) {
-    const int cnt = min(kPB, N - k0);
+  const int kb = blockIdx.y * cchunk, ke = min(N, kb + cchunk);
+  for (int k0 = kb; k0 < ke; k0 += kPB) {
+    const int cnt = min(kPB, ke - k0);
     __syncthreads();
     for (int idx = tid; idx < 30 * kPB; idx += kT) {
       const int m = idx / kPB, k = idx % kPB;
@@ -262,9 +265,10 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
     }
   }
   if (active && want_x) {
-    gx[i] = (double)hx + (double)lx;
-    gx[(size_t)n_t + i] = (double)hy + (double)ly;
-    gx[2 * (size_t)n_t + i] = (double)hz + (double)lz;
+    double *g = gx + (size_t)blockIdx.y * 3 * n_t;
+    g[i] = (double)hx + (double)lx;
+    g[(size_t)n_t + i] = (double)hy + (double)ly;
+    g[2 * (size_t)n_t + i] = (double)hz + (double)lz;
   }
 }
 
@@ -782,8 +786,20 @@ extern "C" obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh
     if (!gsp) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed (%d x %d partials)", bt, N);
     OBEM_PROF(ctx, "panel_bwd");
     if (precision == OBEM_MIXED) {
-      hipLaunchKernelGGL(k_panel_bwd_mixed, dim3(bt), dim3(kT), 0, ctx->stream, n_t, to.xs, wsrt, N, mesh->f, sigma,
-                         1, gx, gsp);
+      // cell ranges of >= 256 cells, about kSplitWorkgroups workgroups in all
+      int ns = std::max(1, std::min((kSplitWorkgroups + bt - 1) / bt, (N + 255) / 256));
+      ns = std::min(ns, 64);
+      int cchunk = (N + ns - 1) / ns;
+      cchunk = (cchunk + kPB - 1) / kPB * kPB;
+      ns = (N + cchunk - 1) / cchunk;
+      double *gxp = gx;
+      if (ns > 1) {
+        gxp = (double *)ws_get(ctx, WS_PANEL, sizeof(double) * 3 * (size_t)n_t * ns);
+        if (!gxp) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+      }
+      hipLaunchKernelGGL(k_panel_bwd_mixed, dim3(bt, ns), dim3(kT), 0, ctx->stream, n_t, to.xs, wsrt, N, mesh->f,
+                         sigma, 1, cchunk, gxp, gsp);
+      if (ns > 1) hipLaunchKernelGGL(k_sum_chunks3, dim3(bt), dim3(256), 0, ctx->stream, n_t, ns, gxp, 0, gx);
       hipLaunchKernelGGL(k_panel_bwd_near, dim3(bt), dim3(kT), 0, ctx->stream, n_t, to.xs, wsrt, N, mesh->f, sigma,
                          mesh->tiles, 1, gx, gsp);
     } else
