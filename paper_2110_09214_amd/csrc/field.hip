@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) void k_bbox_partial(int n, const double *__res
   }
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
+    if ((int)threadIdx.x < w) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         s[c][threadIdx.x] = fmin(s[c][threadIdx.x], s[c][threadIdx.x + w]);
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_bbox_final(int nb, const double *part, 
   }
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
+    if ((int)threadIdx.x < w) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         s[c][threadIdx.x] = fmin(s[c][threadIdx.x], s[c][threadIdx.x + w]);
