@@ -352,7 +352,7 @@ def main():
             p5["step"] += 1
             inter5.append(nl * (nl - 1) + nl * m5.n)
 
-        ms5, _ = timed(step5, 10, 1)
+        ms5, prof5 = timed(step5, 10, 1)
         rate5 = sum(inter5[-10:]) / (10 * ms5 / 1e3)
         X5 = torch.stack([c[:parts5.n_live] for c in parts5.cols[:3]], 1).contiguous()
         Q5 = torch.full((parts5.n_live,), -W.E_CHARGE, dtype=torch.float64, device="cuda")
@@ -365,6 +365,7 @@ def main():
 
         ms5b, _ = timed(bwd5, 1, 1)
         extra["double_gem_step_ms"] = ms5
+        extra["double_gem_kernel_ms_per_step"] = {k: v[0] / 10 for k, v in prof5.items()}
         extra["double_gem_interactions_per_s"] = rate5
         extra["double_gem_n_live_after"] = parts5.n_live
         extra["double_gem_dd_charges"] = int(counts5.abs().sum())
