@@ -313,7 +313,11 @@ typedef struct {
   double r_rec;         /* recombination radius (eq. (distRecomb) as a parameter)  */
   obem_precision precision;
   int32_t resolve;      /* 1: rebuild the RHS from rhs0 + charging counts and
-                           re-solve sigma before the field evaluation             */
+                           re-solve sigma before the field evaluation; 2: the
+                           same, but when the RHS equals, bit for bit, the one
+                           of the mesh's previous re-solve (no new charge, no
+                           influence, same rhs0) that solve's sigma is copied
+                           instead of solving again (the result is identical) */
   int32_t influence;    /* with resolve: also move the live particles' influence
                            onto the RHS before the solve (as bem_influence)       */
   const double *rhs0;   /* device, n_panels: [V_i ; sigma_F0,i]                    */
@@ -343,7 +347,8 @@ typedef struct {
 
 /* One tracking step (ordered as in the paper's dynamic option):
  *  1. if p->resolve: rhs = rhs0 + e * dd_counts / area on dd rows
- *     (eq. (charge-up)), sigma = bem_solve_charges(rhs);
+ *     (eq. (charge-up)), sigma = bem_solve_charges(rhs) (with resolve = 2
+ *     skipped when rhs is unchanged since the mesh's last re-solve);
  *  2. E at every live particle from the cells and all other particles,
  *     and each particle's nearest opposite-species partner;
  *  3. electron-cation pairs closer than r_rec recombine (eq. (distRecomb)):

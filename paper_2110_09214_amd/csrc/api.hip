@@ -346,6 +346,8 @@ static void free_mesh(obem_meshh *m) {
   (void)hipFree(m->tiles);
   (void)hipFree(m->tiles48);
   (void)hipFree(m->order);
+  (void)hipFree(m->rhs_last);
+  (void)hipFree(m->sigma_last);
   bem_release(m);
   (void)hipFree(m->grid_start);
   (void)hipFree(m->grid_items);

@@ -440,6 +440,8 @@ obem_status bem_solve(obem_ctx *ctx, obem_meshh *m, const double *rhs, double *s
   int it = 0;
   double h[3] = {0, 0, 0};
   for (;;) {
+    // without info nobody reads the residual after the last correction
+    if (!info && it >= max_refine) break;
     if (trans) {
       hipLaunchKernelGGL(k_residual_t, dim3((N + 3) / 4), dim3(256), 0, ctx->stream, N, m->A, sigma, b, r);
       OBEM_HIP(ctx, hipGetLastError());
@@ -459,8 +461,6 @@ obem_status bem_solve(obem_ctx *ctx, obem_meshh *m, const double *rhs, double *s
       // stop when the backward error no longer halves
       if (!(berr < 0.5 * best_err) || it >= max_refine) break;
       best_err = berr;
-    } else if (it >= max_refine) {
-      break;
     }
     st = inv_apply(ctx, m, r, d, trans);
     if (st) return st;

@@ -74,6 +74,9 @@ struct obem_meshh {
   double *tiles = nullptr;    // per 64-cell tile: centre (3), near-zone radius (3 D)
   double *tiles48 = nullptr;  // the same for the FP64 closed-form zone (48 D)
   int32_t *order = nullptr;   // cell indices in Morton order of the centroids
+  // last re-solve of a tracking step: its right-hand side and charges (lazy)
+  double *rhs_last = nullptr, *sigma_last = nullptr;
+  bool last_valid = false;
   // collocation system (lazy)
   double *A = nullptr;        // n x n column-major
   double *LU = nullptr;       // n x n column-major

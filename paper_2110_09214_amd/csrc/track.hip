@@ -714,6 +714,15 @@ __global__ __launch_bounds__(256) void k_gather_sources(int n, const int32_t *__
   sp_out[i] = sp[j];
 }
 
+// Number of entries where a and b differ (bit patterns of the doubles).
+__global__ __launch_bounds__(256) void k_count_diff(int n, const double *__restrict__ a, const double *__restrict__ b,
+                                                    unsigned long long *cnt) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const bool d = i < n && __double_as_longlong(a[i]) != __double_as_longlong(b[i]);
+  const unsigned long long m = __ballot(d);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(cnt, (unsigned long long)__popcll(m));
+}
+
 __global__ __launch_bounds__(256) void k_fill_u64(int n, unsigned long long *p, unsigned long long v) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < n) p[i] = v;
@@ -987,6 +996,7 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
   if (mesh) {
     if (!p->map && !is_device_ptr(sigma)) return fail(ctx, OBEM_EINVAL, "sigma must be device memory");
     if (mesh->n_dd && !is_device_ptr(dd_counts)) return fail(ctx, OBEM_EINVAL, "dd_counts must be device memory");
+    if (p->resolve < 0 || p->resolve > 2) return fail(ctx, OBEM_EINVAL, "resolve must be 0, 1 or 2");
     if (p->resolve && !is_device_ptr(p->rhs0)) return fail(ctx, OBEM_EINVAL, "rhs0 must be device memory");
   }
   MapDev gmap;
@@ -1015,8 +1025,40 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
                          nullptr);
       if (st) return st;
     }
-    st = bem_solve(ctx, mesh, rhs, sigma, 2, nullptr);
-    if (st) return st;
+    bool solve = true;
+    if (p->resolve == 2 && mesh->last_valid) {
+      unsigned long long *nd = (unsigned long long *)ws_get(ctx, WS_MISC7, sizeof(unsigned long long));
+      if (!nd) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+      unsigned long long h = 0;
+      hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, ctx->stream, 1, nd, 0ull);
+      hipLaunchKernelGGL(k_count_diff, dim3(nbt(N)), dim3(256), 0, ctx->stream, N, rhs, mesh->rhs_last, nd);
+      OBEM_HIP(ctx, hipGetLastError());
+      OBEM_HIP(ctx, hipMemcpyAsync(&h, nd, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+      OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      if (h == 0) {
+        OBEM_HIP(ctx, hipMemcpyAsync(sigma, mesh->sigma_last, sizeof(double) * N, hipMemcpyDeviceToDevice,
+                                     ctx->stream));
+        solve = false;
+      }
+    }
+    if (solve) {
+      st = bem_solve(ctx, mesh, rhs, sigma, 2, nullptr);
+      if (st) return st;
+      if (!mesh->rhs_last) {
+        if (hipMalloc(&mesh->rhs_last, sizeof(double) * N) != hipSuccess ||
+            hipMalloc(&mesh->sigma_last, sizeof(double) * N) != hipSuccess) {
+          (void)hipGetLastError();
+          (void)hipFree(mesh->rhs_last);
+          mesh->rhs_last = nullptr;
+          mesh->sigma_last = nullptr;
+          return fail(ctx, OBEM_ENOMEM, "allocation of the last re-solve failed");
+        }
+      }
+      OBEM_HIP(ctx, hipMemcpyAsync(mesh->rhs_last, rhs, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
+      OBEM_HIP(ctx, hipMemcpyAsync(mesh->sigma_last, sigma, sizeof(double) * N, hipMemcpyDeviceToDevice,
+                                   ctx->stream));
+      mesh->last_valid = true;
+    }
   }
   if (mesh) {
     st = build_grid(ctx, mesh);

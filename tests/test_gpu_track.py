@@ -126,6 +126,40 @@ def test_track_step_mixed_consistent_with_fp64(ctx, stepper, dt):
     assert np.all(np.abs(t32 - t64) <= 0.05 * t64 + 10)
 
 
+def test_resolve_on_change_matches_always(ctx):
+    """resolve = 2 skips the re-solve only when the right-hand side equals the
+    mesh's previous one bit for bit (the copied charges are that solve's), so
+    the stream is the one of resolve = 1, step by step: particles, charging
+    counts and cell charges identical.  The scenario charges dd cells in the
+    first step and (almost) never later, so both branches run."""
+    m, st0 = _scenario(3)
+    gas = W.synthetic_ar_co2()
+    gas_s, keep = B.gas_struct(gas, "cuda")
+    runs = {}
+    for mode in (1, 2):
+        bm = bind(ctx, m)
+        rhs0 = dev(m.rhs)
+        sig, _ = B.bem_solve_charges(ctx, bm, rhs0)
+        parts = B.Particles(20000, "cuda", dev(st0["x"]), dev(st0["v"]), dev(st0["species"], torch.int8),
+                            dev(st0["id"], torch.int64), st0["next_id"])
+        counts = torch.zeros(m.n, dtype=torch.int64, device="cuda")
+        hist = []
+        for s in range(6):
+            p = _params(s, B.OBEM_FP64)
+            p["resolve"] = mode if s > 0 else 0
+            sg = B.track_step(ctx, bm, parts, gas_s, p, counts, sig, rhs0)
+            g = parts.state()
+            hist.append((host(g["x"]), host(g["id"]), host(counts).copy(), host(sig).copy(), sg["dd_charge_deposited"]))
+        runs[mode] = hist
+    for a, b in zip(runs[1], runs[2]):
+        for u, v in zip(a[:4], b[:4]):
+            assert np.array_equal(u, v)
+    dep = [h[4] for h in runs[1]]
+    print("dd charges deposited per step", dep)
+    assert dep[0] > 0                         # step 1 re-solves (changed RHS) ...
+    assert any(d == 0 for d in dep[1:-1])     # ... and some later step keeps it
+
+
 def test_track_step_capacity_overflow(ctx):
     m, st0 = _scenario(2)
     gas = W.synthetic_ar_co2()
