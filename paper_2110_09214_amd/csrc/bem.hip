@@ -103,23 +103,53 @@ __global__ __launch_bounds__(256) void k_rows_chunk(int N, const double *__restr
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= N) return;
   const int jb = blockIdx.y * chunk, je = min(N, jb + chunk);
-  double s = 0.0, c = 0.0;
-  for (int j = jb; j < je; ++j) {
+  // four independent compensated sums over j = jb + 4k + u (more loads in
+  // flight per thread), combined in fixed order at the end
+  double s[4] = {0.0, 0.0, 0.0, 0.0}, c[4] = {0.0, 0.0, 0.0, 0.0};
+  int j = jb;
+  for (; j + 4 <= je; j += 4) {
+    double a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = A[(size_t)(j + u) * N + i];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (MODE == 0) {
+        const double xj = x[j + u];
+        const double p = a[u] * xj;
+        const double pe = fma(a[u], xj, -p);
+        double t, e;
+        two_sum(s[u], p, t, e);
+        s[u] = t;
+        c[u] += e + pe;
+      } else {
+        s[u] += fabs(a[u]);
+      }
+    }
+  }
+  for (; j < je; ++j) {
     const double a = A[(size_t)j * N + i];
     if (MODE == 0) {
       const double xj = x[j];
       const double p = a * xj;
       const double pe = fma(a, xj, -p);
       double t, e;
-      two_sum(s, p, t, e);
-      s = t;
-      c += e + pe;
+      two_sum(s[0], p, t, e);
+      s[0] = t;
+      c[0] += e + pe;
     } else {
-      s += fabs(a);
+      s[0] += fabs(a);
     }
   }
-  hi_out[(size_t)blockIdx.y * N + i] = s;
-  lo_out[(size_t)blockIdx.y * N + i] = c;
+  double S = s[0], C = c[0];
+#pragma unroll
+  for (int u = 1; u < 4; ++u) {
+    double t, e;
+    two_sum(S, s[u], t, e);
+    S = t;
+    C += e + c[u];
+  }
+  hi_out[(size_t)blockIdx.y * N + i] = S;
+  lo_out[(size_t)blockIdx.y * N + i] = C;
 }
 
 // r_i = b_i - sum over chunks (fixed order), compensated; also max |r|.
