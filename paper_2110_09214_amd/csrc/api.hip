@@ -149,6 +149,15 @@ __global__ __launch_bounds__(256) void k_mesh_derive(int n, double *f, const int
     F(MF_Q3 + 3 * q + 1) = p.y;
     F(MF_Q3 + 3 * q + 2) = p.z;
   }
+  const double bary6[6][3] = {{Rule6::b1, Rule6::a1, Rule6::a1}, {Rule6::a1, Rule6::b1, Rule6::a1},
+                              {Rule6::a1, Rule6::a1, Rule6::b1}, {Rule6::b2, Rule6::a2, Rule6::a2},
+                              {Rule6::a2, Rule6::b2, Rule6::a2}, {Rule6::a2, Rule6::a2, Rule6::b2}};
+  for (int q = 0; q < 6; ++q) {
+    d3 p = a * bary6[q][0] + b * bary6[q][1] + c * bary6[q][2];
+    F(MF_Q6 + 3 * q) = p.x;
+    F(MF_Q6 + 3 * q + 1) = p.y;
+    F(MF_Q6 + 3 * q + 2) = p.z;
+  }
 }
 
 // Zone bounding spheres of consecutive 64-cell tiles: centre = mean

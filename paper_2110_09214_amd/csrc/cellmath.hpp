@@ -95,6 +95,14 @@ __device__ __forceinline__ float dist2f(float a0, float a1, float a2, float b0, 
   return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
 }
 
+// Degree-4, 6-point symmetric rule on the triangle (Dunavant, Int. J.
+// Numer. Methods Eng. 21 (1985) 1129): barycentric (b1, a1, a1) with weight
+// w1 and (b2, a2, a2) with weight w2, each in its 3 permutations.
+struct Rule6 {
+  static constexpr double a1 = 0.445948490915965, b1 = 0.108103018168070, w1 = 0.223381589678011;
+  static constexpr double a2 = 0.091576213509771, b2 = 0.816847572980459, w2 = 0.109951743655322;
+};
+
 struct Rule7 {
   // a = (6 - sqrt 15)/21, b = (6 + sqrt 15)/21
   static constexpr double a = 0.10128650732345633880;

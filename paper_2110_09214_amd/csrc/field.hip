@@ -243,14 +243,48 @@ obem_status order_targets(obem_ctx *ctx, int64_t n64, const double *tx, const do
 // ---------------------------------------------------------------------------
 constexpr int kPT = 64;               // cells per LDS tile
 
-// One cell of an LDS tile, recentred FP32, as 11 float4 records read whole
+// One cell of an LDS tile, recentred FP32, as 16 float4 records read whole
 // (one address per cell, 128-bit LDS reads):
-//   c[0] = centroid, (3 D)^2          c[1] = (64 D)^2, area sigma {w0, wa, wb}
-//   c[2..7] = the 7 points of the degree-5 rule (21 floats), area sigma / 3
-//   c[8..10] = the 3 points of the degree-2 rule (9 floats), 3 unused
+//   c[0] = centroid, (3 D)^2          c[1] = (40 D)^2, area sigma {w0, wa, wb}
+//   c[2..7] = the 7 points of the degree-5 rule (21 floats), area sigma / 3,
+//             (8 D)^2, 0
+//   c[8..10] = the 3 points of the degree-2 rule (9 floats), area sigma
+//             {w1, w2} of the 6-point rule, 0
+//   c[11..15] = the 6 points of the degree-4 rule (18 floats), 0, 0
 struct PanelCell {
-  float4 c[11];
+  float4 c[16];
 };
+
+// sum over the M rule points of w {e/|e|^3, 1/|e|}, e = target - point
+template <int M, bool WANT_V>
+__device__ __forceinline__ void panel_points(const float *q, const float *w, float r0, float r1, float r2,
+                                             float &px, float &py, float &pz, float &pv) {
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const float ex = r0 - q[3 * m], ey = r1 - q[3 * m + 1], ez = r2 - q[3 * m + 2];
+    const float rr = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+    const float ri = __builtin_amdgcn_rsqf(rr);
+    const float wr = w[m] * ri;
+    const float s_ = wr * (ri * ri);
+    px = fmaf(s_, ex, px);
+    py = fmaf(s_, ey, py);
+    pz = fmaf(s_, ez, pz);
+    if (WANT_V) pv += wr;
+  }
+}
+
+// n consecutive float4 records of a cell into registers
+template <int N4>
+__device__ __forceinline__ void load4(const float4 *c, float *q) {
+#pragma unroll
+  for (int u = 0; u < N4; ++u) {
+    const float4 t = c[u];
+    q[4 * u] = t.x;
+    q[4 * u + 1] = t.y;
+    q[4 * u + 2] = t.z;
+    q[4 * u + 3] = t.w;
+  }
+}
 
 __device__ __forceinline__ void neumaier(float &s, float &c, float v) {
   float t = s + v;
@@ -303,22 +337,23 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
   for (int k0 = kb; k0 < ke; k0 += kPT) {
     const int cnt = min(kPT, ke - k0);
     __syncthreads();
-    // staging, coalesced along the cells: the 30 rule coordinates of the
-    // 64 cells, then one thread per cell for centroid, limits and weights
-    for (int idx = tid; idx < 30 * kPT; idx += kThreads) {
+    // staging, coalesced along the cells: the 48 rule coordinates (7-, 3- and
+    // 6-point rules) of the 64 cells, then one thread per cell for centroid,
+    // limits and weights
+    for (int idx = tid; idx < 48 * kPT; idx += kThreads) {
       const int m = idx / kPT, k = idx % kPT;
       float v = 0.f;
+      const int src = (m < 21) ? MF_Q7 + m : (m < 30 ? MF_Q3 + (m - 21) : MF_Q6 + (m - 30));
       if (k < cnt) {
-        const int src = (m < 21) ? MF_Q7 + m : MF_Q3 + (m - 21);
-        const int c = (m < 21 ? m : m - 21) % 3;
+        const int c = (m < 21 ? m : (m < 30 ? m - 21 : m - 30)) % 3;
         v = (float)(f[(size_t)src * N + k0 + k] - (c == 0 ? c0 : (c == 1 ? c1 : c2)));
       }
-      reinterpret_cast<float *>(&T[k])[m < 21 ? 8 + m : 32 + (m - 21)] = v;
+      reinterpret_cast<float *>(&T[k])[m < 21 ? 8 + m : (m < 30 ? 32 + (m - 21) : 44 + (m - 30))] = v;
     }
     if (tid < kPT) {
       const int k = tid;
       float4 g = make_float4(0.f, 0.f, 0.f, 0.f), h = g;
-      float w3 = 0.f;
+      float w3 = 0.f, lim8 = 0.f, w61 = 0.f, w62 = 0.f;
       if (k < cnt) {
         const int kk = k0 + k;
         const double D = f[(size_t)MF_DIAM * N + kk];
@@ -328,10 +363,20 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
         h = make_float4((float)(kFar3Mixed * kFar3Mixed * D * D), (float)(as * Rule7::w0), (float)(as * Rule7::wa),
                         (float)(as * Rule7::wb));
         w3 = (float)(as * (1.0 / 3.0));
+        lim8 = (float)(kMid6Mixed * kMid6Mixed * D * D);
+        w61 = (float)(as * Rule6::w1);
+        w62 = (float)(as * Rule6::w2);
       }
+      float *rec = reinterpret_cast<float *>(&T[k]);
       T[k].c[0] = g;
       T[k].c[1] = h;
-      reinterpret_cast<float *>(&T[k])[29] = w3;
+      rec[29] = w3;
+      rec[30] = lim8;
+      rec[31] = 0.f;
+      rec[41] = w61;
+      rec[42] = w62;
+      rec[43] = 0.f;
+      rec[62] = rec[63] = 0.f;
     }
     __syncthreads();
     float px = 0.f, py = 0.f, pz = 0.f, pv = 0.f;
@@ -340,55 +385,31 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
       const float R2 = dist2f(r0, r1, r2, g.x, g.y, g.z);
       const bool nearp = R2 < g.w;  // taken by k_panel_near in FP64
       const float4 h = T[k].c[1];
-      const bool need7 = (!nearp) && (R2 < h.x);
+      const float4 h7 = T[k].c[7];  // {.., area sigma / 3, (8 D)^2, 0}
+      // the rule by distance (7 points within 8 D, 6 within 40 D, 3 beyond),
+      // taken for the whole wave at the finest rule one of its lanes needs
+      const bool need7 = (!nearp) && (R2 < h7.z);
+      const bool need6 = (!nearp) && (R2 < h.x);
       if (__any(need7)) {
         if (!nearp) {
           float q[24];
-#pragma unroll
-          for (int u = 0; u < 6; ++u) {
-            const float4 t = T[k].c[2 + u];
-            q[4 * u] = t.x;
-            q[4 * u + 1] = t.y;
-            q[4 * u + 2] = t.z;
-            q[4 * u + 3] = t.w;
-          }
-#pragma unroll
-          for (int m = 0; m < 7; ++m) {
-            const float w = (m == 0) ? h.y : (m < 4 ? h.z : h.w);
-            const float ex = r0 - q[3 * m], ey = r1 - q[3 * m + 1], ez = r2 - q[3 * m + 2];
-            const float rr = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
-            const float ri = __builtin_amdgcn_rsqf(rr);
-            const float wr = w * ri;
-            const float s_ = wr * (ri * ri);
-            px = fmaf(s_, ex, px);
-            py = fmaf(s_, ey, py);
-            pz = fmaf(s_, ez, pz);
-            if (WANT_V) pv += wr;
-          }
+          load4<6>(&T[k].c[2], q);
+          const float w[7] = {h.y, h.z, h.z, h.z, h.w, h.w, h.w};
+          panel_points<7, WANT_V>(q, w, r0, r1, r2, px, py, pz, pv);
+        }
+      } else if (__any(need6)) {
+        if (!nearp) {
+          float q[20];
+          load4<5>(&T[k].c[11], q);
+          const float4 h10 = T[k].c[10];
+          const float w[6] = {h10.y, h10.y, h10.y, h10.z, h10.z, h10.z};
+          panel_points<6, WANT_V>(q, w, r0, r1, r2, px, py, pz, pv);
         }
       } else if (!nearp) {
-        const float w = T[k].c[7].y;  // area sigma / 3
         float q[12];
-#pragma unroll
-        for (int u = 0; u < 3; ++u) {
-          const float4 t = T[k].c[8 + u];
-          q[4 * u] = t.x;
-          q[4 * u + 1] = t.y;
-          q[4 * u + 2] = t.z;
-          q[4 * u + 3] = t.w;
-        }
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          const float ex = r0 - q[3 * m], ey = r1 - q[3 * m + 1], ez = r2 - q[3 * m + 2];
-          const float rr = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
-          const float ri = __builtin_amdgcn_rsqf(rr);
-          const float wr = w * ri;
-          const float s_ = wr * (ri * ri);
-          px = fmaf(s_, ex, px);
-          py = fmaf(s_, ey, py);
-          pz = fmaf(s_, ez, pz);
-          if (WANT_V) pv += wr;
-        }
+        load4<3>(&T[k].c[8], q);
+        const float w[3] = {h7.y, h7.y, h7.y};
+        panel_points<3, WANT_V>(q, w, r0, r1, r2, px, py, pz, pv);
       }
     }
     neumaier(hx, lx, px);

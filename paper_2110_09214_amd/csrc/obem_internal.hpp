@@ -29,7 +29,8 @@ constexpr double kKe = 1.0 / (4.0 * kPi * kEps0);
 //          else      -> FP32 3-point degree-2 rule
 //   fp64:  R < 48 D  -> FP64 closed form, else FP64 7-point rule
 constexpr double kNearMixed = 3.0;
-constexpr double kFar3Mixed = 64.0;
+constexpr double kFar3Mixed = 40.0;  // 3-point rule from here on (mixed)
+constexpr double kMid6Mixed = 8.0;   // cell field: 6-point rule from here to kFar3Mixed
 constexpr double kQuadFp64 = 48.0;
 // Workgroup count that the source- or charge-split launches aim at: 64
 // rounds of the 2048 workgroups resident at once (8 per CU, 256 CUs), which
@@ -61,7 +62,8 @@ enum MeshField {
   MF_AREA, MF_DIAM, MF_EPS1, MF_EPS2,
   MF_Q7 = 19,            // 7 quadrature points x 3 coordinates (21 arrays)
   MF_Q3 = MF_Q7 + 21,    // 3 quadrature points x 3 coordinates (9 arrays)
-  MF_COUNT = MF_Q3 + 9
+  MF_Q6 = MF_Q3 + 9,     // 6 quadrature points x 3 coordinates (18 arrays)
+  MF_COUNT = MF_Q6 + 18
 };
 
 struct obem_meshh {
