@@ -84,7 +84,7 @@ __device__ __forceinline__ void cell_grad_closed(const d3 P[3], d3 n, double two
 
 // ---------------------------------------------------------------------------
 // Cell adjoint, mixed precision (regimes as in the forward kernels).  The far
-// kernel takes the pairs beyond 3 D with the FP32 rules (7 points up to 64 D,
+// kernel takes the pairs beyond 3 D with the FP32 rules (7 points up to 40 D,
 // 3 beyond); the near kernel then adds the pairs within 3 D (FP64 closed
 // form), both deciding with the same FP32 test on the same recentred values.
 // gx: 3 x n_t (sorted order) position gradient in units of 1/k_e;
@@ -95,7 +95,7 @@ constexpr int kUPad = kT + 4;  // row pitch of the w . IE buffer (floats)
 constexpr int kParts = kT / kPB;
 
 // One cell of the far kernel's tile, recentred FP32, 11 float4 records:
-//   c[0] = centroid, (3 D)^2          c[1] = (64 D)^2, area {w0, wa, wb}
+//   c[0] = centroid, (3 D)^2          c[1] = (40 D)^2, area {w0, wa, wb}
 //   c[2..7] = the 7 rule points (21 floats), area / 3
 //   c[8..10] = the 3 rule points (9 floats), sigma, 2 unused
 struct BCell {

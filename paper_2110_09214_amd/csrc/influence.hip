@@ -10,7 +10,8 @@
 // close and are recentred on its first centroid), charges staged in LDS
 // tiles, gridDim.y chunks of charges with per-chunk partial sums reduced in
 // chunk order.  Precision regimes as in the field: mixed = FP32 7-point rule
-// within 64 diameters, 3-point rule beyond (far kernel, charges ordered by
+// within 8 diameters, 6-point rule within 40, 3-point rule beyond (far
+// kernel, charges ordered by
 // charge sign, then Morton, so the charge comes out of the pair loop), FP64
 // closed form within 3 diameters (near kernel, its own partial slots);
 // FP64 = closed form within 48 diameters, FP64 7-point rule beyond.
@@ -46,7 +47,8 @@ __device__ __forceinline__ void infl_closed(const double *__restrict__ f, int N,
 // charges in blocks of 1024, 4 per thread (one from each 256-charge tile of
 // the block, so a wave's lanes hold 64 consecutive, spatially close charges).
 // Per cell the rule is chosen per wave over those close charges (7 points
-// within 64 D, 3 beyond; pairs within 3 D are left to the near kernel), and
+// within 8 D, 6 within 40 D, 3 beyond; pairs within 3 D are left to the near
+// kernel), and
 // each thread adds q (IV, IE) of its charges into 8 x 4 FP32 sums.  The sums
 // of a block are reduced over the 256 threads through LDS in fixed order and
 // in FP64 (8 partial sums of 32 threads each, then the 8 in order) and
@@ -55,12 +57,14 @@ constexpr int kCB = 8;   // cells per workgroup
 constexpr int kCS = 4;   // charges per thread and block
 constexpr int kUP = kTI + 4;
 
-// One cell of the far kernel's LDS tile, recentred FP32, 11 float4 records:
-//   c[0] = centroid, (3 D)^2          c[1] = (64 D)^2, area {w0, wa, wb}
-//   c[2..7] = the 7 rule points (21 floats), area / 3
-//   c[8..10] = the 3 rule points (9 floats), 3 unused
+// One cell of the far kernel's LDS tile, recentred FP32, 16 float4 records:
+//   c[0] = centroid, (3 D)^2          c[1] = (40 D)^2, area {w0, wa, wb}
+//   c[2..7] = the 7 rule points (21 floats), area / 3, (8 D)^2, 0
+//   c[8..10] = the 3 rule points (9 floats), area {w1, w2} of the 6-point
+//              rule, 0
+//   c[11..15] = the 6 rule points (18 floats), 0, 0
 struct ICell {
-  float4 c[11];
+  float4 c[16];
 };
 
 // sum over m of w_m {1/|e_m|, e_m/|e_m|^3}, e_m = p - point m
@@ -95,23 +99,28 @@ __global__ __launch_bounds__(kTI) void k_influence_mixed(int N, const double *__
   // recentred on the first cell of the 256-cell group, as the near kernel
   const int kr = ord[(kb / kTI) * kTI];
   const double c0 = f[(size_t)MF_GX * N + kr], c1 = f[(size_t)MF_GY * N + kr], c2 = f[(size_t)MF_GZ * N + kr];
-  for (int idx = tid; idx < 30 * kCB; idx += kTI) {
+  for (int idx = tid; idx < 48 * kCB; idx += kTI) {
     const int m = idx / kCB, k = idx % kCB;
     const int kk = ord[min(kb + k, N - 1)];
-    const int src = (m < 21) ? MF_Q7 + m : MF_Q3 + (m - 21);
-    const int c = (m < 21 ? m : m - 21) % 3;
-    reinterpret_cast<float *>(&T[k])[m < 21 ? 8 + m : 32 + (m - 21)] =
+    const int src = (m < 21) ? MF_Q7 + m : (m < 30 ? MF_Q3 + (m - 21) : MF_Q6 + (m - 30));
+    const int c = (m < 21 ? m : (m < 30 ? m - 21 : m - 30)) % 3;
+    reinterpret_cast<float *>(&T[k])[m < 21 ? 8 + m : (m < 30 ? 32 + (m - 21) : 44 + (m - 30))] =
         (float)(f[(size_t)src * N + kk] - (c == 0 ? c0 : (c == 1 ? c1 : c2)));
   }
   if (tid < kCB) {
     const int kk = ord[min(kb + tid, N - 1)];
     const double D = f[(size_t)MF_DIAM * N + kk], ar = f[(size_t)MF_AREA * N + kk];
+    float *rec = reinterpret_cast<float *>(&T[tid]);
     T[tid].c[0] = make_float4((float)(f[(size_t)MF_GX * N + kk] - c0), (float)(f[(size_t)MF_GY * N + kk] - c1),
                               (float)(f[(size_t)MF_GZ * N + kk] - c2), (float)(kNearMixed * kNearMixed * D * D));
     T[tid].c[1] = make_float4((float)(kFar3Mixed * kFar3Mixed * D * D), (float)(ar * Rule7::w0),
                               (float)(ar * Rule7::wa), (float)(ar * Rule7::wb));
-    reinterpret_cast<float *>(&T[tid])[29] = (float)(ar / 3.0);
-    for (int u = 41; u < 44; ++u) reinterpret_cast<float *>(&T[tid])[u] = 0.f;
+    rec[29] = (float)(ar / 3.0);
+    rec[30] = (float)(kMid6Mixed * kMid6Mixed * D * D);
+    rec[31] = 0.f;
+    rec[41] = (float)(ar * Rule6::w1);
+    rec[42] = (float)(ar * Rule6::w2);
+    rec[43] = rec[62] = rec[63] = 0.f;
   }
   __syncthreads();
   double accd = 0.0;  // threads 0..31: (cell tid / 4, component tid % 4)
@@ -130,13 +139,15 @@ __global__ __launch_bounds__(kTI) void k_influence_mixed(int N, const double *__
     }
 #pragma unroll
     for (int k = 0; k < kCB; ++k) {
-      const float4 g = T[k].c[0], h = T[k].c[1];
+      const float4 g = T[k].c[0], h = T[k].c[1], h7 = T[k].c[7];
       float av = 0.f, ax = 0.f, ay = 0.f, az = 0.f;
 #pragma unroll
       for (int c = 0; c < kCS; ++c) {
         const float R2 = dist2f(px[c], py[c], pz[c], g.x, g.y, g.z);
         const bool nearp = R2 < g.w;  // taken by k_influence_near in FP64
-        const bool need7 = !nearp && R2 < h.x;
+        // 7 points within 8 D, 6 within 40 D, 3 beyond (finest rule of the wave)
+        const bool need7 = !nearp && R2 < h7.z;
+        const bool need6 = !nearp && R2 < h.x;
         float sv = 0.f, ex = 0.f, ey = 0.f, ez = 0.f;
         if (__any(need7)) {
           if (!nearp) {
@@ -146,11 +157,20 @@ __global__ __launch_bounds__(kTI) void k_influence_mixed(int N, const double *__
             const float w[7] = {h.y, h.z, h.z, h.z, h.w, h.w, h.w};
             infl_points<7>(px[c], py[c], pz[c], q, w, sv, ex, ey, ez);
           }
+        } else if (__any(need6)) {
+          if (!nearp) {
+            float q[18];
+#pragma unroll
+            for (int u = 0; u < 18; ++u) q[u] = reinterpret_cast<const float *>(&T[k])[44 + u];
+            const float4 h10 = T[k].c[10];
+            const float w[6] = {h10.y, h10.y, h10.y, h10.z, h10.z, h10.z};
+            infl_points<6>(px[c], py[c], pz[c], q, w, sv, ex, ey, ez);
+          }
         } else if (!nearp) {
           float q[9];
 #pragma unroll
           for (int u = 0; u < 9; ++u) q[u] = reinterpret_cast<const float *>(&T[k])[32 + u];
-          const float w3 = T[k].c[7].y;
+          const float w3 = h7.y;
           const float w[3] = {w3, w3, w3};
           infl_points<3>(px[c], py[c], pz[c], q, w, sv, ex, ey, ez);
         }
