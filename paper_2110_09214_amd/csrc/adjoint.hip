@@ -84,22 +84,27 @@ __device__ __forceinline__ void cell_grad_closed(const d3 P[3], d3 n, double two
 
 // ---------------------------------------------------------------------------
 // Cell adjoint, mixed precision (regimes as in the forward kernels).  The far
-// kernel takes the pairs beyond 3 D with the FP32 rules (7 points up to 40 D,
-// 3 beyond); the near kernel then adds the pairs within 3 D (FP64 closed
-// form), both deciding with the same FP32 test on the same recentred values.
+// kernel takes the pairs beyond 3 D with the FP32 rules (7 points up to 8 D,
+// 6 up to 40 D, 3 beyond); the near kernel then adds the pairs within 3 D
+// (FP64 closed form), both deciding with the same FP32 test on the same
+// recentred values.
 // gx: 3 x n_t (sorted order) position gradient in units of 1/k_e;
 // gsp: partial dL/dsigma per (workgroup, cell), in units of 1/k_e.
 // ---------------------------------------------------------------------------
 constexpr int kPB = 32;        // cells per LDS tile of the far kernel
 constexpr int kUPad = kT + 4;  // row pitch of the w . IE buffer (floats)
 constexpr int kParts = kT / kPB;
+// (8 D)^2 / (40 D)^2: the 7-point bound from the 3-point one
+constexpr float kR76 = (float)((kMid6Mixed / kFar3Mixed) * (kMid6Mixed / kFar3Mixed));
 
-// One cell of the far kernel's tile, recentred FP32, 11 float4 records:
+// One cell of the far kernel's tile, recentred FP32, 15 float4 records
+// (60 floats, so that tile + w . IE buffer fit four workgroups per CU):
 //   c[0] = centroid, (3 D)^2          c[1] = (40 D)^2, area {w0, wa, wb}
-//   c[2..7] = the 7 rule points (21 floats), area / 3
-//   c[8..10] = the 3 rule points (9 floats), sigma, 2 unused
+//   floats 8..28 = the 7 rule points, 29 = area / 3, 30 = sigma,
+//   31 = area w1 of the 6-point rule
+//   floats 32..40 = the 3 rule points, 41 = area w2, 42..59 = the 6 rule points
 struct BCell {
-  float4 c[11];
+  float4 c[15];
 };
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -142,9 +147,14 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
                                                         const double *__restrict__ f,
                                                         const double *__restrict__ sigma, int want_x, int cchunk,
                                                         double *gx, double *gsp) {
-  __shared__ BCell T[kPB];
+  // the FP64 partials of the w . IE sums reuse the tile's memory: they are
+  // written after the pair loop's last read of the tile and read before the
+  // next tile is staged
+  static_assert(sizeof(double) * kParts * kPB <= sizeof(BCell) * kPB, "partials exceed the tile");
+  __shared__ __align__(16) float4 Traw[kPB * 15];
   __shared__ __align__(16) float U[kPB][kUPad];
-  __shared__ double red[kParts][kPB];
+  BCell *T = reinterpret_cast<BCell *>(Traw);
+  double(*red)[kPB] = reinterpret_cast<double(*)[kPB]>(Traw);
   const int tid = threadIdx.x;
   const int i0 = blockIdx.x * kT;
   const int i = i0 + tid;
@@ -161,20 +171,20 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
   for (int k0 = kb; k0 < ke; k0 += kPB) {
     const int cnt = min(kPB, ke - k0);
     __syncthreads();
-    for (int idx = tid; idx < 30 * kPB; idx += kT) {
+    for (int idx = tid; idx < 48 * kPB; idx += kT) {
       const int m = idx / kPB, k = idx % kPB;
       float v = 0.f;
+      const int src = (m < 21) ? MF_Q7 + m : (m < 30 ? MF_Q3 + (m - 21) : MF_Q6 + (m - 30));
       if (k < cnt) {
-        const int src = (m < 21) ? MF_Q7 + m : MF_Q3 + (m - 21);
-        const int c = (m < 21 ? m : m - 21) % 3;
+        const int c = (m < 21 ? m : (m < 30 ? m - 21 : m - 30)) % 3;
         v = (float)(f[(size_t)src * N + k0 + k] - (c == 0 ? c0 : (c == 1 ? c1 : c2)));
       }
-      reinterpret_cast<float *>(&T[k])[m < 21 ? 8 + m : 32 + (m - 21)] = v;
+      reinterpret_cast<float *>(&T[k])[m < 21 ? 8 + m : (m < 30 ? 32 + (m - 21) : 42 + (m - 30))] = v;
     }
     if (tid < kPB) {
       const int k = tid;
       float4 g = make_float4(0.f, 0.f, 0.f, 0.f), h = g;
-      float w3 = 0.f, sg = 0.f;
+      float w3 = 0.f, sg = 0.f, w61 = 0.f, w62 = 0.f;
       if (k < cnt) {
         const int kk = k0 + k;
         const double D = f[(size_t)MF_DIAM * N + kk];
@@ -185,11 +195,16 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
                         (float)(ar * Rule7::wb));
         w3 = (float)(ar * (1.0 / 3.0));
         sg = (float)sigma[kk];
+        w61 = (float)(ar * Rule6::w1);
+        w62 = (float)(ar * Rule6::w2);
       }
+      float *rec = reinterpret_cast<float *>(&T[k]);
       T[k].c[0] = g;
       T[k].c[1] = h;
-      reinterpret_cast<float *>(&T[k])[29] = w3;
-      reinterpret_cast<float *>(&T[k])[41] = sg;
+      rec[29] = w3;
+      rec[30] = sg;
+      rec[31] = w61;
+      rec[41] = w62;
     }
     __syncthreads();
     float px = 0.f, py = 0.f, pz = 0.f;
@@ -198,7 +213,9 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
       const float R2 = dist2f(r0, r1, r2, g.x, g.y, g.z);
       const bool nearp = R2 < g.w;  // taken by k_panel_bwd_near in FP64
       const float4 h = T[k].c[1];
-      const bool need7 = (!nearp) && (R2 < h.x);
+      // 7 points within 8 D, 6 within 40 D, 3 beyond (finest rule of the wave)
+      const bool need7 = (!nearp) && (R2 < h.x * kR76);
+      const bool need6 = (!nearp) && (R2 < h.x);
       float u = 0.f, A = 0.f, Zx = 0.f, Zy = 0.f, Zz = 0.f;
       if (__any(need7)) {
         if (!nearp) {
@@ -216,6 +233,26 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
             qpt_adj((m == 0) ? h.y : (m < 4 ? h.z : h.w), r0 - q[3 * m], r1 - q[3 * m + 1], r2 - q[3 * m + 2], wx,
                     wy, wz, u, A, Zx, Zy, Zz);
         }
+      } else if (__any(need6)) {
+        if (!nearp) {
+          const float4 t10 = T[k].c[10];
+          float q[18];
+          q[0] = t10.z;
+          q[1] = t10.w;
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const float4 t = T[k].c[11 + m];
+            q[2 + 4 * m] = t.x;
+            q[3 + 4 * m] = t.y;
+            q[4 + 4 * m] = t.z;
+            q[5 + 4 * m] = t.w;
+          }
+          const float w1 = T[k].c[7].w, w2 = t10.y;
+#pragma unroll
+          for (int m = 0; m < 6; ++m)
+            qpt_adj(m < 3 ? w1 : w2, r0 - q[3 * m], r1 - q[3 * m + 1], r2 - q[3 * m + 2], wx, wy, wz, u, A, Zx,
+                    Zy, Zz);
+        }
       } else if (!nearp) {
         const float aw = T[k].c[7].y;  // area / 3
         float q[12];
@@ -231,7 +268,7 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
         for (int m = 0; m < 3; ++m)
           qpt_adj(aw, r0 - q[3 * m], r1 - q[3 * m + 1], r2 - q[3 * m + 2], wx, wy, wz, u, A, Zx, Zy, Zz);
       }
-      const float sg = T[k].c[10].y;
+      const float sg = T[k].c[7].z;
       const float sA = sg * A, s3 = -3.0f * sg;
       px = fmaf(sA, wx, fmaf(s3, Zx, px));
       py = fmaf(sA, wy, fmaf(s3, Zy, py));

@@ -26,13 +26,12 @@ constexpr double kKe = 1.0 / (4.0 * kPi * kEps0);
 // cell centroid to the cell diameter D):
 //   mixed: R < 3 D   -> FP64 closed form
 //          R < 8 D   -> FP32 7-point degree-5 rule
-//          R < 40 D  -> FP32 6-point degree-4 rule (field, influence; the
-//                       adjoint keeps the 7-point rule up to 40 D)
+//          R < 40 D  -> FP32 6-point degree-4 rule
 //          else      -> FP32 3-point degree-2 rule
 //   fp64:  R < 48 D  -> FP64 closed form, else FP64 7-point rule
 constexpr double kNearMixed = 3.0;
 constexpr double kFar3Mixed = 40.0;  // 3-point rule from here on (mixed)
-constexpr double kMid6Mixed = 8.0;   // field, influence: 6-point rule from here to kFar3Mixed
+constexpr double kMid6Mixed = 8.0;   // 6-point rule from here to kFar3Mixed (mixed)
 constexpr double kQuadFp64 = 48.0;
 // Workgroup count that the source- or charge-split launches aim at: 64
 // rounds of the 2048 workgroups resident at once (8 per CU, 256 CUs), which
