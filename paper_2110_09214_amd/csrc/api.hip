@@ -453,9 +453,19 @@ obem_status field_eval(obem_ctx *ctx, const obem_meshh *mesh, const double *sigm
     obem_status st = order_sources(ctx, n_src, sx, sy, sz, sq, tis, &so);
     if (st) return st;
   }
+  // targets = sources: with the pair-once evaluation the targets take the
+  // sources' order (same particles, same tiles)
+  const bool once = tis && pair_once_applies(n_tgt, precision, soft, want_v);
   TargetOrder to;
-  obem_status st = order_targets(ctx, n_tgt, tx, ty, tz, &to);
-  if (st) return st;
+  obem_status st = OBEM_OK;
+  if (once) {
+    to.n = (int32_t)n_tgt;
+    to.perm = const_cast<int32_t *>(so.perm);
+    to.xs = const_cast<double *>(so.x);
+  } else {
+    st = order_targets(ctx, n_tgt, tx, ty, tz, &to);
+    if (st) return st;
+  }
   double *acc = (double *)ws_get(ctx, WS_ACC, sizeof(double) * 4 * (size_t)n_tgt);
   if (!acc) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
   if (mesh) {
@@ -466,7 +476,7 @@ obem_status field_eval(obem_ctx *ctx, const obem_meshh *mesh, const double *sigm
   if (st) return st;
   if (n_src > 0) {
     st = launch_pair_field(ctx, n_src, so.x, so.y, so.z, so.q, to, soft, precision, tis, want_v, nullptr, nullptr,
-                           acc, nullptr, nullptr, so.tbox, 0.0, tis ? so.inv : nullptr);
+                           acc, nullptr, nullptr, so.tbox, 0.0, tis ? so.inv : nullptr, once);
     if (st) return st;
   }
   return launch_scatter(ctx, to, acc, kKe, Ex, Ey, Ez, want_v ? V : nullptr);

@@ -206,6 +206,7 @@ obem_status order_sources(obem_ctx *ctx, int64_t n64, const double *sx, const do
   out->q = src + 3 * nz;
   out->tbox = tbox;
   out->inv = inv;
+  out->perm = perm + nz;
   return OBEM_OK;
 }
 
@@ -734,6 +735,60 @@ __device__ __forceinline__ void pair_tile_far(const float4 *S2, int cnt, float m
   }
 }
 
+// Squared gap between the boxes of source tiles a and b (FP64, 256-source
+// tiles), symmetric in a and b bit for bit.
+__device__ __forceinline__ double tiles_gap2(const double *__restrict__ tbox, int a, int b) {
+  const double *p = tbox + 6 * (size_t)a, *q = tbox + 6 * (size_t)b;
+  double g2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double g = fmax(0.0, fmax(q[c] - p[3 + c], p[c] - q[3 + c]));
+    g2 = fma(g, g, g2);
+  }
+  return g2;
+}
+
+// Whether the tile pair (a, b) is left to the directed kernel under the
+// pair-once evaluation (super-blocks of sym_tiles tiles): tiles of one
+// super-block, tiles within the partner cut (nn), and tiles closer than a
+// quarter of the larger radius R of their two super-blocks about the centres
+// the pair-once kernel recentres on (k_sym_radius): beyond that gap the FP32
+// difference r - s it forms, from coordinates of size up to R + |r - s|,
+// carries at most about 9 ulps of |r - s|.  Symmetric in a and b, and
+// evaluated the same way by both kernels, so that every tile pair is taken
+// by exactly one of them.
+__device__ __forceinline__ bool tile_pair_direct(const double *__restrict__ tbox, const double *__restrict__ sb,
+                                                 int a, int b, int sym_tiles, bool nn, double cut2) {
+  const int A = a / sym_tiles, B = b / sym_tiles;
+  if (A == B) return true;
+  const double g2 = tiles_gap2(tbox, a, b);
+  return 16.0 * g2 < fmax(sb[4 * (size_t)A + 3], sb[4 * (size_t)B + 3]) || (nn && g2 <= cut2);
+}
+
+// Per super-block: the centre of the box around its tiles' boxes (the
+// origin the pair-once kernel recentres on) and the squared distance from
+// it to the box's corners, sb[4 A + 0..2] and sb[4 A + 3].
+__global__ __launch_bounds__(256) void k_sym_radius(int n, int ns, int sym_tiles, const double *__restrict__ tbox,
+                                                    double *sb) {
+  const int A = blockIdx.x * 256 + threadIdx.x;
+  if (A >= ns) return;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int k = 0; k < sym_tiles && (A * sym_tiles + k) * kThreads < n; ++k) {
+    const double *bx = tbox + 6 * (size_t)(A * sym_tiles + k);
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = fmin(lo[c], bx[c]);
+      hi[c] = fmax(hi[c], bx[3 + c]);
+    }
+  }
+  double r2 = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    sb[4 * (size_t)A + c] = 0.5 * (lo[c] + hi[c]);
+    const double h = 0.5 * (hi[c] - lo[c]);
+    r2 = fma(h, h, r2);
+  }
+  sb[4 * (size_t)A + 3] = r2;
+}
+
 template <bool WANT_V, bool NN, int EXCL>
 __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const double *__restrict__ xs,
                                                          const int32_t *__restrict__ perm, int n_s,
@@ -745,7 +800,9 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
                                                          const int8_t *__restrict__ species_s, float soft2,
                                                          int chunk, double *part, float *nn_d2p,
                                                          int32_t *nn_ip, const double *__restrict__ tbox,
-                                                         float nn_cut2, const int32_t *__restrict__ self_map) {
+                                                         float nn_cut2, const int32_t *__restrict__ self_map,
+                                                         int sym_tiles, double nn_cut2d,
+                                                         const double *__restrict__ sb) {
   constexpr bool kFar = (EXCL == 0) && !WANT_V;  // expanded far tiles allowed
   __shared__ float4 S[kThreads];
   __shared__ float4 S2[kFar ? kThreads : 1];
@@ -818,6 +875,16 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
       if (NN) nn_tile = gap2 <= nn_cut2;
       far_tile = kFar && !nn_tile && gap2 >= far2;
     }
+    if (sym_tiles) {
+      // targets are the sources in the same order: this workgroup's targets
+      // are source tile blockIdx.x.  The tile pairs that tile_pair_direct
+      // does not keep here are evaluated by k_pair_sym.
+      const int ta = blockIdx.x, tb = jt / kThreads;
+      if (!tile_pair_direct(tbox, sb, ta, tb, sym_tiles, NN, nn_cut2d)) continue;
+      const bool np = NN && tiles_gap2(tbox, ta, tb) <= nn_cut2d;
+      nn_tile = np;
+      far_tile = far_tile && !np;
+    }
     __syncthreads();
     float qj = q0;
     if (tid < cnt) {
@@ -871,6 +938,222 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
       nn_d2p[(size_t)blockIdx.y * n_t + i] = best;
       nn_ip[(size_t)blockIdx.y * n_t + i] = bidx;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pairwise field with every unordered pair evaluated once (targets = sources)
+// ---------------------------------------------------------------------------
+// The softened pair term of eq. (nbody) is antisymmetric: what particle j adds
+// to E_i, with q_j replaced by q_i and the sign reversed, is what i adds to
+// E_j.  The particles (one order for targets and sources) form super-blocks of
+// kSymTiles tiles of 256.  Tile pairs inside one super-block, tile pairs
+// whose boxes are within the partner cut when that search is on, and tile
+// pairs closer than the radius of their super-blocks (tile_pair_direct) stay
+// with the directed kernel (k_pair_mixed with sym_tiles set).  Every other
+// unordered tile pair is evaluated once, here, by the workgroup of its
+// super-block pair: of the ns super-blocks, A owns (A, A + d mod ns) for
+// d = 1 .. sym_h(A), so that each unordered pair has exactly one owner.
+//
+// A workgroup takes one (A, d): thread t holds the kSymTiles particles
+// A kSymSB + k 256 + t of A (FP32, recentred on the centre of A's box),
+// B = A + d streams through LDS
+// tile by tile.  Within a tile, a wave takes the sources in groups of 64 and
+// 64 steps per group: at step m lane l pairs its particles with source
+// (l + m) mod 64 of the group.  The sums for A's particles stay in
+// registers; the running sum of each source travels with it through the
+// wave (after each step a lane passes it to the lane below, which takes that
+// source next, by a lane permutation), so after 64 steps every source's sum
+// over the wave's 64 x kSymTiles particles sits in one lane, in a fixed
+// order of additions, without atomics.  Per pair 14 VALU operations and one
+// reciprocal square root (3 sub, 3 FMA for d^2 + s^2, rsqrt, 2 mul for r^-3,
+// 3 + 3 FMA into the two sums) serve two interactions, plus 3 adds per
+// step.  Super-block pairs with one charge on each side take the charges out
+// of the loop; the others (mixed charges, partial super-blocks) carry both
+// charges per pair.  Tile pairs left to the directed kernel are masked
+// through their softening term, without a branch.
+// Outputs per launch slot dd = d - d0, FP32: Pi[dd][3][n], the field at A's
+// particles from B, and Pj[dd][3][n], the field at B's particles from A;
+// k_sym_reduce adds the slots to acc in order.
+constexpr int kSymTiles = 8;
+constexpr int kSymSB = kSymTiles * kThreads;  // particles per super-block
+constexpr int kSymSlots = 16;                 // values of d per launch
+
+__host__ __device__ __forceinline__ int sym_h(int A, int ns) {
+  return (ns & 1) ? (ns - 1) / 2 : (A < ns / 2 ? ns / 2 : ns / 2 - 1);
+}
+
+template <bool NN>
+__global__ __launch_bounds__(kThreads, 4) void k_pair_sym(int n, const double *__restrict__ sx,
+                                                        const double *__restrict__ sy,
+                                                        const double *__restrict__ sz,
+                                                        const double *__restrict__ sq,
+                                                        const double *__restrict__ tbox, double nn_cut2d,
+                                                        const double *__restrict__ sb, float soft2, int ns,
+                                                        int d0, float *__restrict__ Pi, float *__restrict__ Pj) {
+  __shared__ float4 S[kThreads];
+  __shared__ float J[kThreads / 64][3][kThreads];
+  __shared__ unsigned long long skipS;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nxt = ((lane + 1) & 63) << 2;  // byte address of the next lane
+  const int A = blockIdx.x;
+  const int dd = blockIdx.y;
+  const int d = d0 + dd;
+  if (d > sym_h(A, ns)) return;  // workgroup-uniform, before any barrier
+  const int B = (A + d) % ns;
+  const int a0 = A * kSymSB, b0 = B * kSymSB;
+  const double c0 = sb[4 * (size_t)A], c1 = sb[4 * (size_t)A + 1], c2 = sb[4 * (size_t)A + 2];
+  float r0[kSymTiles], r1[kSymTiles], r2[kSymTiles], qa[kSymTiles];
+  const float qA = (float)sq[a0], qB = (float)sq[b0];
+  bool uni = true;
+#pragma unroll
+  for (int k = 0; k < kSymTiles; ++k) {
+    const int i = a0 + k * kThreads + tid;
+    const bool act = i < n;
+    r0[k] = act ? (float)(sx[i] - c0) : 0.f;
+    r1[k] = act ? (float)(sy[i] - c1) : 0.f;
+    r2[k] = act ? (float)(sz[i] - c2) : 0.f;
+    const float qi = act ? (float)sq[i] : 0.f;
+    qa[k] = qi;
+    const int j = b0 + k * kThreads + tid;
+    uni = uni && act && qi == qA && j < n && (float)sq[j] == qB;
+  }
+  // tile pairs that belong to the directed kernel: bit 8 bt + k for (tile k
+  // of A, tile bt of B)
+  if (wv == 0) {
+    bool near = false;
+    const int ka = lane & 7, kb = lane >> 3;
+    if (a0 + ka * kThreads < n && b0 + kb * kThreads < n)
+      near = tile_pair_direct(tbox, sb, A * kSymTiles + ka, B * kSymTiles + kb, kSymTiles, NN, nn_cut2d);
+    const unsigned long long m = __ballot(near);
+    if (lane == 0) skipS = m;
+  }
+  // one charge on each side: charges out of the loop
+  const bool U = __syncthreads_and(uni);
+  const unsigned long long skip = skipS;
+  float ex[kSymTiles], ey[kSymTiles], ez[kSymTiles];
+#pragma unroll
+  for (int k = 0; k < kSymTiles; ++k) ex[k] = ey[k] = ez[k] = 0.f;
+  for (int bt = 0; bt < kSymTiles; ++bt) {
+    const int jt = b0 + bt * kThreads;
+    if (jt >= n) break;  // workgroup-uniform
+    const int cnt = min(kThreads, n - jt);
+    // tile pairs left to the directed kernel: a softening of 1e36 makes
+    // r^-3 < 1e-54, which is 0 in FP32, so they add exactly nothing
+    const unsigned sk = (unsigned)(skip >> (8 * bt)) & 0xffu;
+    float s2k[kSymTiles];
+#pragma unroll
+    for (int k = 0; k < kSymTiles; ++k) s2k[k] = ((sk >> k) & 1u) ? 1e36f : soft2;
+    __syncthreads();  // the previous tile's S and J are consumed
+    {
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (tid < cnt) {
+        const int j = jt + tid;
+        v = make_float4((float)(sx[j] - c0), (float)(sy[j] - c1), (float)(sz[j] - c2), (float)sq[j]);
+      }
+      S[tid] = v;
+    }
+    __syncthreads();
+    for (int g = 0; g < cnt; g += 64) {
+      // tx, ty, tz: at step m the running sum of source (lane + m) mod 64
+      // over the lanes visited so far; after the step it moves to the lane
+      // below (lane - 1), which takes that source at step m + 1
+      float tx = 0.f, ty = 0.f, tz = 0.f;
+      if (U) {
+        for (int m = 0; m < 64; ++m) {
+          const float4 sj = S[g + ((lane + m) & 63)];
+          float cx = 0.f, cy = 0.f, cz = 0.f;
+#pragma unroll
+          for (int k = 0; k < kSymTiles; ++k) {
+            const float dx = r0[k] - sj.x, dy = r1[k] - sj.y, dz = r2[k] - sj.z;
+            const float rr = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, s2k[k])));
+            const float ri = __builtin_amdgcn_rsqf(rr);
+            const float w = ri * (ri * ri);
+            ex[k] = fmaf(w, dx, ex[k]);
+            ey[k] = fmaf(w, dy, ey[k]);
+            ez[k] = fmaf(w, dz, ez[k]);
+            cx = fmaf(w, dx, cx);
+            cy = fmaf(w, dy, cy);
+            cz = fmaf(w, dz, cz);
+          }
+          tx = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(tx + cx)));
+          ty = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(ty + cy)));
+          tz = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(tz + cz)));
+        }
+      } else {
+        for (int m = 0; m < 64; ++m) {
+          const float4 sj = S[g + ((lane + m) & 63)];
+          float cx = 0.f, cy = 0.f, cz = 0.f;
+#pragma unroll
+          for (int k = 0; k < kSymTiles; ++k) {
+            const float dx = r0[k] - sj.x, dy = r1[k] - sj.y, dz = r2[k] - sj.z;
+            const float rr = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, s2k[k])));
+            const float ri = __builtin_amdgcn_rsqf(rr);
+            const float w = ri * (ri * ri);
+            const float wi = w * sj.w, wj = w * qa[k];
+            ex[k] = fmaf(wi, dx, ex[k]);
+            ey[k] = fmaf(wi, dy, ey[k]);
+            ez[k] = fmaf(wi, dz, ez[k]);
+            cx = fmaf(wj, dx, cx);
+            cy = fmaf(wj, dy, cy);
+            cz = fmaf(wj, dz, cz);
+          }
+          tx = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(tx + cx)));
+          ty = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(ty + cy)));
+          tz = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(tz + cz)));
+        }
+      }
+      // after the 64th step and move the lane holds the full sum of source lane
+      const int jl = g + lane;
+      J[wv][0][jl] = tx;
+      J[wv][1][jl] = ty;
+      J[wv][2][jl] = tz;
+    }
+    __syncthreads();
+    // field at the tile's sources from A: E_j = -sum_i q_i w (r_i - s_j),
+    // the four waves' rows added in order
+    if (tid < cnt) {
+      const float fj = U ? -qA : -1.f;
+      const size_t o = (size_t)dd * 3 * n + jt + tid;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float v = ((J[0][c][tid] + J[1][c][tid]) + J[2][c][tid]) + J[3][c][tid];
+        Pj[o + (size_t)c * n] = fj * v;
+      }
+    }
+  }
+  const float fi = U ? qB : 1.f;
+#pragma unroll
+  for (int k = 0; k < kSymTiles; ++k) {
+    const int i = a0 + k * kThreads + tid;
+    if (i < n) {
+      const size_t o = (size_t)dd * 3 * n + i;
+      Pi[o] = fi * ex[k];
+      Pi[o + (size_t)n] = fi * ey[k];
+      Pi[o + 2 * (size_t)n] = fi * ez[k];
+    }
+  }
+}
+
+// acc[c][p] += the launch's slots that hold a field at p, in slot order: the
+// slot of d as the owner of (A, A + d) and the slot of d as the partner of
+// (A - d, A).
+__global__ __launch_bounds__(256) void k_sym_reduce(int n, int ns, int d0, int dcnt, const float *__restrict__ Pi,
+                                                    const float *__restrict__ Pj, double *acc) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= n) return;
+  const int A = p / kSymSB;
+  const int hA = sym_h(A, ns);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double s = acc[(size_t)c * n + p];
+    for (int dd = 0; dd < dcnt; ++dd) {
+      const int d = d0 + dd;
+      const size_t o = ((size_t)dd * 3 + c) * n + p;
+      if (d <= hA) s += (double)Pi[o];
+      if (d <= sym_h((A - d + ns) % ns, ns)) s += (double)Pj[o];
+    }
+    acc[(size_t)c * n + p] = s;
   }
 }
 
@@ -979,11 +1262,11 @@ static void launch_pair_t(obem_ctx *ctx, dim3 grid, int n_t, const double *xs, c
                           const double *sx, const double *sy, const double *sz, const double *sq,
                           const int8_t *sp, const int8_t *sps, double soft, obem_precision prec, int chunk,
                           double *part, void *nnd, int32_t *nni, const double *tbox, float nn_cut2,
-                          const int32_t *self_map) {
+                          const int32_t *self_map, int sym_tiles, double nn_cut2d, const double *sb) {
   if (prec == OBEM_MIXED)
     hipLaunchKernelGGL((k_pair_mixed<WANT_V, NN, CZ>), grid, dim3(kThreads), 0, ctx->stream, n_t, xs, perm, n_s,
                        sx, sy, sz, sq, sp, sps, (float)(soft * soft), chunk, part, (float *)nnd, nni, tbox, nn_cut2,
-                       self_map);
+                       self_map, sym_tiles, nn_cut2d, sb);
   else
     hipLaunchKernelGGL((k_pair_fp64<WANT_V, NN, CZ>), grid, dim3(kThreads), 0, ctx->stream, n_t, xs, perm, n_s,
                        sx, sy, sz, sq, sp, sps, soft * soft, chunk, part, (double *)nnd, nni, self_map);
@@ -993,10 +1276,12 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
                               const double *sq, const TargetOrder &to, double soft, obem_precision prec,
                               bool tgt_is_src, bool want_v, const int8_t *species, const int8_t *species_s,
                               double *acc, int32_t *nn_idx, double *nn_d2, const double *tbox, double nn_cut,
-                              const int32_t *self_map) {
+                              const int32_t *self_map, bool once) {
   const int n_t = to.n;
   const int n_s = (int)n_src;
   if (n_t == 0 || n_s == 0) return OBEM_OK;
+  if (once && !(tgt_is_src && n_s == n_t && tbox && pair_once_applies(n_t, prec, soft, want_v)))
+    return fail(ctx, OBEM_EINVAL, "pair-once evaluation needs targets = sources in one order");
   const int bt = nblk(n_t);
   // about 128k workgroups (64 rounds of the 2048 resident ones), so that the
   // last workgroups to start are short and the chip drains quickly at the
@@ -1027,13 +1312,22 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
     excl = 2;
   dim3 grid(bt, nsplit);
   // cut with a margin for the FP32 box coordinates (a larger cut only costs time)
-  const float nn_cut2 = tbox ? (float)std::pow(nn_cut * (1.0 + 1e-4) + 1e-9, 2) : INFINITY;
+  const double nn_cut2d = tbox ? std::pow(nn_cut * (1.0 + 1e-4) + 1e-9, 2) : INFINITY;
+  const float nn_cut2 = (float)nn_cut2d;
+  const int sym_tiles = once ? kSymTiles : 0;
+  const int ns = (n_t + kSymSB - 1) / kSymSB;
+  double *sb = nullptr;
+  if (once) {
+    sb = (double *)ws_get(ctx, WS_SYMR, sizeof(double) * 4 * (size_t)ns);
+    if (!sb) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+    hipLaunchKernelGGL(k_sym_radius, dim3((ns + 255) / 256), dim3(256), 0, ctx->stream, n_t, ns, kSymTiles, tbox, sb);
+  }
   {
   OBEM_PROF(ctx, "pair");
 #define PAIR_CASE(V, N, Z)                                                                                   \
   if (want_v == V && nn == N && excl == Z)                                                                   \
     launch_pair_t<V, N, Z>(ctx, grid, n_t, to.xs, to.perm, n_s, sx, sy, sz, sq, species, species_s, soft, prec, \
-                           chunk, part, nnd, nni, tbox, nn_cut2, self_map);
+                           chunk, part, nnd, nni, tbox, nn_cut2, self_map, sym_tiles, nn_cut2d, sb);
   PAIR_CASE(false, false, 0)
   PAIR_CASE(false, false, 1)
   PAIR_CASE(false, false, 2)
@@ -1050,15 +1344,45 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
   }
   OBEM_HIP(ctx, hipGetLastError());
   // the accumulator already holds the cell field when the panel kernel ran
-  OBEM_PROF(ctx, "pair_reduce");
-  if (prec == OBEM_MIXED)
-    hipLaunchKernelGGL(k_pair_reduce<float>, dim3(nblk(n_t)), dim3(256), 0, ctx->stream, n_t, nsplit, part, 1, acc,
-                       (const float *)nnd, nni, nn_d2, nn_idx);
-  else
-    hipLaunchKernelGGL(k_pair_reduce<double>, dim3(nblk(n_t)), dim3(256), 0, ctx->stream, n_t, nsplit, part, 1,
-                       acc, (const double *)nnd, nni, nn_d2, nn_idx);
+  {
+    OBEM_PROF(ctx, "pair_reduce");
+    if (prec == OBEM_MIXED)
+      hipLaunchKernelGGL(k_pair_reduce<float>, dim3(nblk(n_t)), dim3(256), 0, ctx->stream, n_t, nsplit, part, 1,
+                         acc, (const float *)nnd, nni, nn_d2, nn_idx);
+    else
+      hipLaunchKernelGGL(k_pair_reduce<double>, dim3(nblk(n_t)), dim3(256), 0, ctx->stream, n_t, nsplit, part, 1,
+                         acc, (const double *)nnd, nni, nn_d2, nn_idx);
+  }
   OBEM_HIP(ctx, hipGetLastError());
+  if (once) {
+    // the tile pairs between super-blocks, each evaluated once, in launches
+    // of up to kSymSlots values of d (bounded partial buffers)
+    const int hmax = ns / 2;
+    if (hmax > 0) {
+      float *Pi = (float *)ws_get(ctx, WS_SYMI, sizeof(float) * 3 * kSymSlots * (size_t)n_t);
+      float *Pj = (float *)ws_get(ctx, WS_SYMJ, sizeof(float) * 3 * kSymSlots * (size_t)n_t);
+      if (!Pi || !Pj) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+      OBEM_PROF(ctx, "pair_once");
+      for (int d0 = 1; d0 <= hmax; d0 += kSymSlots) {
+        const int dcnt = std::min(kSymSlots, hmax - d0 + 1);
+        const dim3 g(ns, dcnt);
+        if (nn)
+          hipLaunchKernelGGL(k_pair_sym<true>, g, dim3(kThreads), 0, ctx->stream, n_t, sx, sy, sz, sq, tbox,
+                             nn_cut2d, sb, (float)(soft * soft), ns, d0, Pi, Pj);
+        else
+          hipLaunchKernelGGL(k_pair_sym<false>, g, dim3(kThreads), 0, ctx->stream, n_t, sx, sy, sz, sq, tbox,
+                             nn_cut2d, sb, (float)(soft * soft), ns, d0, Pi, Pj);
+        hipLaunchKernelGGL(k_sym_reduce, dim3(nblk(n_t)), dim3(256), 0, ctx->stream, n_t, ns, d0, dcnt, Pi, Pj,
+                           acc);
+      }
+      OBEM_HIP(ctx, hipGetLastError());
+    }
+  }
   return OBEM_OK;
+}
+
+bool pair_once_applies(int64_t n, obem_precision prec, double soft, bool want_v) {
+  return prec == OBEM_MIXED && soft > 0.0 && !want_v && n > 2 * (int64_t)kSymSB;
 }
 
 // ---------------------------------------------------------------------------

@@ -937,13 +937,19 @@ static obem_status step_field(obem_ctx *ctx, obem_meshh *mesh, const double *sig
                      S->species, dead, status, srcb, ssp);
   launch_tile_boxes(ctx, n, srcb, tbox);
   OBEM_HIP(ctx, hipGetLastError());
+  // with the pair-once evaluation the targets take the source copy's order
+  const bool once = pair_once_applies(n, p->precision, p->soft, false);
+  if (once) {
+    to.perm = sperm + nz;
+    to.xs = srcb;
+  }
   if (map)
     st = launch_map_acc(ctx, *map, to, acc);
   else
     st = mesh ? launch_panel_field(ctx, mesh, sigma, to, p->precision, false, acc) : launch_fill(ctx, acc, 4 * nz, 0.0);
   if (st) return st;
   st = launch_pair_field(ctx, n, srcb, srcb + nz, srcb + 2 * nz, srcb + 3 * nz, to, p->soft, p->precision, true,
-                         false, S->species, ssp, acc, nn_s, nnd, tbox, p->r_rec);
+                         false, S->species, ssp, acc, nn_s, nnd, tbox, p->r_rec, nullptr, once);
   if (st) return st;
   st = launch_scatter(ctx, to, acc, kKe, E, E + nz, E + 2 * nz, nullptr);
   if (st) return st;
