@@ -789,6 +789,22 @@ __global__ __launch_bounds__(256) void k_sym_radius(int n, int ns, int sym_tiles
   sb[4 * (size_t)A + 3] = r2;
 }
 
+// Bit b of row a (32 tiles per word): tile_pair_direct(a, b), for the
+// directed kernel to skip the other tiles by one scalar bit test.
+__global__ __launch_bounds__(256) void k_tile_mask(int ntile, int wpr, int sym_tiles, int nn, double cut2,
+                                                   const double *__restrict__ tbox, const double *__restrict__ sb,
+                                                   uint32_t *mask) {
+  const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (size_t)ntile * wpr) return;
+  const int a = (int)(t / wpr), w = (int)(t % wpr);
+  uint32_t m = 0;
+  for (int u = 0; u < 32; ++u) {
+    const int b = w * 32 + u;
+    if (b < ntile && tile_pair_direct(tbox, sb, a, b, sym_tiles, nn != 0, cut2)) m |= 1u << u;
+  }
+  mask[t] = m;
+}
+
 template <bool WANT_V, bool NN, int EXCL>
 __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const double *__restrict__ xs,
                                                          const int32_t *__restrict__ perm, int n_s,
@@ -802,7 +818,7 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
                                                          int32_t *nn_ip, const double *__restrict__ tbox,
                                                          float nn_cut2, const int32_t *__restrict__ self_map,
                                                          int sym_tiles, double nn_cut2d,
-                                                         const double *__restrict__ sb) {
+                                                         const uint32_t *__restrict__ dmask, int dwpr) {
   constexpr bool kFar = (EXCL == 0) && !WANT_V;  // expanded far tiles allowed
   __shared__ float4 S[kThreads];
   __shared__ float4 S2[kFar ? kThreads : 1];
@@ -878,9 +894,9 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
     if (sym_tiles) {
       // targets are the sources in the same order: this workgroup's targets
       // are source tile blockIdx.x.  The tile pairs that tile_pair_direct
-      // does not keep here are evaluated by k_pair_sym.
+      // (dmask) does not keep here are evaluated by k_pair_sym.
       const int ta = blockIdx.x, tb = jt / kThreads;
-      if (!tile_pair_direct(tbox, sb, ta, tb, sym_tiles, NN, nn_cut2d)) continue;
+      if (!((dmask[(size_t)ta * dwpr + (tb >> 5)] >> (tb & 31)) & 1u)) continue;
       const bool np = NN && tiles_gap2(tbox, ta, tb) <= nn_cut2d;
       nn_tile = np;
       far_tile = far_tile && !np;
@@ -1262,11 +1278,12 @@ static void launch_pair_t(obem_ctx *ctx, dim3 grid, int n_t, const double *xs, c
                           const double *sx, const double *sy, const double *sz, const double *sq,
                           const int8_t *sp, const int8_t *sps, double soft, obem_precision prec, int chunk,
                           double *part, void *nnd, int32_t *nni, const double *tbox, float nn_cut2,
-                          const int32_t *self_map, int sym_tiles, double nn_cut2d, const double *sb) {
+                          const int32_t *self_map, int sym_tiles, double nn_cut2d, const uint32_t *dmask,
+                          int dwpr) {
   if (prec == OBEM_MIXED)
     hipLaunchKernelGGL((k_pair_mixed<WANT_V, NN, CZ>), grid, dim3(kThreads), 0, ctx->stream, n_t, xs, perm, n_s,
                        sx, sy, sz, sq, sp, sps, (float)(soft * soft), chunk, part, (float *)nnd, nni, tbox, nn_cut2,
-                       self_map, sym_tiles, nn_cut2d, sb);
+                       self_map, sym_tiles, nn_cut2d, dmask, dwpr);
   else
     hipLaunchKernelGGL((k_pair_fp64<WANT_V, NN, CZ>), grid, dim3(kThreads), 0, ctx->stream, n_t, xs, perm, n_s,
                        sx, sy, sz, sq, sp, sps, soft * soft, chunk, part, (double *)nnd, nni, self_map);
@@ -1317,17 +1334,24 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
   const int sym_tiles = once ? kSymTiles : 0;
   const int ns = (n_t + kSymSB - 1) / kSymSB;
   double *sb = nullptr;
+  uint32_t *dmask = nullptr;
+  const int ntile = nblk(n_t);
+  const int dwpr = (ntile + 31) / 32;
   if (once) {
     sb = (double *)ws_get(ctx, WS_SYMR, sizeof(double) * 4 * (size_t)ns);
-    if (!sb) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+    dmask = (uint32_t *)ws_get(ctx, WS_SYMM, sizeof(uint32_t) * (size_t)ntile * dwpr);
+    if (!sb || !dmask) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
     hipLaunchKernelGGL(k_sym_radius, dim3((ns + 255) / 256), dim3(256), 0, ctx->stream, n_t, ns, kSymTiles, tbox, sb);
+    const size_t nw = (size_t)ntile * dwpr;
+    hipLaunchKernelGGL(k_tile_mask, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, ctx->stream, ntile, dwpr,
+                       kSymTiles, nn ? 1 : 0, nn_cut2d, tbox, sb, dmask);
   }
   {
   OBEM_PROF(ctx, "pair");
 #define PAIR_CASE(V, N, Z)                                                                                   \
   if (want_v == V && nn == N && excl == Z)                                                                   \
     launch_pair_t<V, N, Z>(ctx, grid, n_t, to.xs, to.perm, n_s, sx, sy, sz, sq, species, species_s, soft, prec, \
-                           chunk, part, nnd, nni, tbox, nn_cut2, self_map, sym_tiles, nn_cut2d, sb);
+                           chunk, part, nnd, nni, tbox, nn_cut2, self_map, sym_tiles, nn_cut2d, dmask, dwpr);
   PAIR_CASE(false, false, 0)
   PAIR_CASE(false, false, 1)
   PAIR_CASE(false, false, 2)
@@ -1381,8 +1405,10 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
   return OBEM_OK;
 }
 
+// Up to 2^24 particles: the tile-pair mask takes at most 512 MB and the
+// partial slots 6.4 GB; larger sets keep the directed evaluation.
 bool pair_once_applies(int64_t n, obem_precision prec, double soft, bool want_v) {
-  return prec == OBEM_MIXED && soft > 0.0 && !want_v && n > 2 * (int64_t)kSymSB;
+  return prec == OBEM_MIXED && soft > 0.0 && !want_v && n > 2 * (int64_t)kSymSB && n <= ((int64_t)1 << 24);
 }
 
 // ---------------------------------------------------------------------------

@@ -50,7 +50,7 @@ enum WsSlot {
   WS_BBOX = 0, WS_KEYS0, WS_KEYS1, WS_IDX0, WS_IDX1, WS_SORT_TMP, WS_TSORT, WS_ACC, WS_PART,
   WS_NN, WS_MISC0, WS_MISC1, WS_MISC2, WS_MISC3, WS_MISC4, WS_MISC5, WS_MISC6, WS_MISC7,
   WS_SOLVE0, WS_SOLVE1, WS_SOLVE2, WS_SRC, WS_SRCPERM, WS_SRCKEY, WS_SORT_TMP2, WS_TBOX, WS_MAP, WS_STATUS, WS_SRCINV, WS_PANEL,
-  WS_SYMI, WS_SYMJ, WS_SYMR, WS_COUNT
+  WS_SYMI, WS_SYMJ, WS_SYMR, WS_SYMM, WS_COUNT
 };
 
 }  // namespace obem
@@ -170,7 +170,7 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
 // Whether the pair-once evaluation (targets = sources in one order, every
 // unordered pair of particles in different super-blocks evaluated once for
 // both) applies: mixed precision, softened, no potential, more than two
-// super-blocks of 2048 particles.
+// super-blocks of 2048 particles and at most 2^24 particles.
 bool pair_once_applies(int64_t n, obem_precision prec, double soft, bool want_v);
 
 // Copy of the point sources in (charge sign, Morton) order with per-256-tile
