@@ -750,11 +750,11 @@ __device__ __forceinline__ double tiles_gap2(const double *__restrict__ tbox, in
 
 // Whether the tile pair (a, b) is left to the directed kernel under the
 // pair-once evaluation (super-blocks of sym_tiles tiles): tiles of one
-// super-block, tiles within the partner cut (nn), and tiles closer than a
-// quarter of the larger radius R of their two super-blocks about the centres
+// super-block, tiles within the partner cut (nn), and tiles closer than an
+// eighth of the larger radius R of their two super-blocks about the centres
 // the pair-once kernel recentres on (k_sym_radius): beyond that gap the FP32
 // difference r - s it forms, from coordinates of size up to R + |r - s|,
-// carries at most about 9 ulps of |r - s|.  Symmetric in a and b, and
+// carries at most about 17 ulps of |r - s|.  Symmetric in a and b, and
 // evaluated the same way by both kernels, so that every tile pair is taken
 // by exactly one of them.
 __device__ __forceinline__ bool tile_pair_direct(const double *__restrict__ tbox, const double *__restrict__ sb,
@@ -762,7 +762,7 @@ __device__ __forceinline__ bool tile_pair_direct(const double *__restrict__ tbox
   const int A = a / sym_tiles, B = b / sym_tiles;
   if (A == B) return true;
   const double g2 = tiles_gap2(tbox, a, b);
-  return 16.0 * g2 < fmax(sb[4 * (size_t)A + 3], sb[4 * (size_t)B + 3]) || (nn && g2 <= cut2);
+  return 64.0 * g2 < fmax(sb[4 * (size_t)A + 3], sb[4 * (size_t)B + 3]) || (nn && g2 <= cut2);
 }
 
 // Per super-block: the centre of the box around its tiles' boxes (the
@@ -878,6 +878,12 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
   float best = INFINITY;
   int bidx = -1;
   for (int jt = jb; jt < je; jt += kThreads) {
+    // targets are the sources in the same order under sym_tiles: this
+    // workgroup's targets are source tile blockIdx.x, and the tile pairs
+    // that tile_pair_direct (dmask) does not keep here are evaluated by
+    // k_pair_sym
+    if (sym_tiles && !((dmask[(size_t)blockIdx.x * dwpr + ((jt / kThreads) >> 5)] >> ((jt / kThreads) & 31)) & 1u))
+      continue;
     const int cnt = min(kThreads, je - jt);
     const float q0 = (float)sq[jt];
     bool nn_tile = NN;
@@ -892,12 +898,7 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
       far_tile = kFar && !nn_tile && gap2 >= far2;
     }
     if (sym_tiles) {
-      // targets are the sources in the same order: this workgroup's targets
-      // are source tile blockIdx.x.  The tile pairs that tile_pair_direct
-      // (dmask) does not keep here are evaluated by k_pair_sym.
-      const int ta = blockIdx.x, tb = jt / kThreads;
-      if (!((dmask[(size_t)ta * dwpr + (tb >> 5)] >> (tb & 31)) & 1u)) continue;
-      const bool np = NN && tiles_gap2(tbox, ta, tb) <= nn_cut2d;
+      const bool np = NN && tiles_gap2(tbox, blockIdx.x, jt / kThreads) <= nn_cut2d;
       nn_tile = np;
       far_tile = far_tile && !np;
     }
@@ -993,7 +994,7 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
 // k_sym_reduce adds the slots to acc in order.
 constexpr int kSymTiles = 8;
 constexpr int kSymSB = kSymTiles * kThreads;  // particles per super-block
-constexpr int kSymSlots = 16;                 // values of d per launch
+constexpr int kSymSlots = 32;                 // values of d per launch
 
 __host__ __device__ __forceinline__ int sym_h(int A, int ns) {
   return (ns & 1) ? (ns - 1) / 2 : (A < ns / 2 ? ns / 2 : ns / 2 - 1);
@@ -1406,7 +1407,7 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
 }
 
 // Up to 2^24 particles: the tile-pair mask takes at most 512 MB and the
-// partial slots 6.4 GB; larger sets keep the directed evaluation.
+// partial slots 12.9 GB; larger sets keep the directed evaluation.
 bool pair_once_applies(int64_t n, obem_precision prec, double soft, bool want_v) {
   return prec == OBEM_MIXED && soft > 0.0 && !want_v && n > 2 * (int64_t)kSymSB && n <= ((int64_t)1 << 24);
 }
