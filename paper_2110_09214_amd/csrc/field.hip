@@ -1008,7 +1008,9 @@ __global__ __launch_bounds__(kThreads, 4) void k_pair_sym(int n, const double *_
                                                         const double *__restrict__ tbox, double nn_cut2d,
                                                         const double *__restrict__ sb, float soft2, int ns,
                                                         int d0, float *__restrict__ Pi, float *__restrict__ Pj) {
-  __shared__ float4 S[kThreads];
+  // each group of 64 sources twice in a row, so that step m of lane l reads
+  // entry l + m without a wrap (constant offsets in the unrolled steps)
+  __shared__ float4 S[kThreads / 64][128];
   __shared__ float J[kThreads / 64][3][kThreads];
   __shared__ unsigned long long skipS;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1068,7 +1070,8 @@ __global__ __launch_bounds__(kThreads, 4) void k_pair_sym(int n, const double *_
         const int j = jt + tid;
         v = make_float4((float)(sx[j] - c0), (float)(sy[j] - c1), (float)(sz[j] - c2), (float)sq[j]);
       }
-      S[tid] = v;
+      S[tid >> 6][tid & 63] = v;
+      S[tid >> 6][(tid & 63) + 64] = v;
     }
     __syncthreads();
     for (int g = 0; g < cnt; g += 64) {
@@ -1077,8 +1080,10 @@ __global__ __launch_bounds__(kThreads, 4) void k_pair_sym(int n, const double *_
       // below (lane - 1), which takes that source at step m + 1
       float tx = 0.f, ty = 0.f, tz = 0.f;
       if (U) {
+        const float4 *sg = &S[g >> 6][lane];
+#pragma unroll 8
         for (int m = 0; m < 64; ++m) {
-          const float4 sj = S[g + ((lane + m) & 63)];
+          const float4 sj = sg[m];
           float cx = 0.f, cy = 0.f, cz = 0.f;
 #pragma unroll
           for (int k = 0; k < kSymTiles; ++k) {
@@ -1098,8 +1103,10 @@ __global__ __launch_bounds__(kThreads, 4) void k_pair_sym(int n, const double *_
           tz = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(tz + cz)));
         }
       } else {
+        const float4 *sg = &S[g >> 6][lane];
+#pragma unroll 8
         for (int m = 0; m < 64; ++m) {
-          const float4 sj = S[g + ((lane + m) & 63)];
+          const float4 sj = sg[m];
           float cx = 0.f, cy = 0.f, cz = 0.f;
 #pragma unroll
           for (int k = 0; k < kSymTiles; ++k) {
