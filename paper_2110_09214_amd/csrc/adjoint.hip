@@ -18,10 +18,13 @@
 
 #include "cellmath.hpp"
 #include "obem_internal.hpp"
+#include "paironce.hpp"
 
 namespace obem {
 
 constexpr int kT = 256;
+constexpr int kBwdTiles = 4;   // tiles per super-block of the pair-once adjoint
+constexpr int kBwdSlots = 32;  // values of d per pair-once launch
 constexpr int kPTb = 64;
 
 static inline int nbk(int64_t n) { return (int)((n + kT - 1) / kT); }
@@ -522,7 +525,8 @@ __global__ __launch_bounds__(kT) void k_pair_bwd_t_mixed(int n_t, const double *
                                                          const double *__restrict__ gEx,
                                                          const double *__restrict__ gEy,
                                                          const double *__restrict__ gEz, float soft2, int chunk,
-                                                         double *part) {
+                                                         double *part, const uint32_t *__restrict__ dmask,
+                                                         int dwpr) {
   __shared__ float4 S[kT];
   __shared__ float4 Wq[kT];
   const int tid = threadIdx.x;
@@ -535,10 +539,14 @@ __global__ __launch_bounds__(kT) void k_pair_bwd_t_mixed(int n_t, const double *
   const float wx = active ? (float)ws[i] : 0.f, wy = active ? (float)ws[(size_t)n_t + i] : 0.f,
               wz = active ? (float)ws[2 * (size_t)n_t + i] : 0.f;
   const int self = active ? perm[i] : -1;
-  const float qi = (TIS && active) ? (float)sq[self] : 0.f;
+  // with dmask the sources are the targets in the same order (pair-once
+  // mode): the target's own charge is source i's, and only the tile pairs
+  // the mask keeps are evaluated here
+  const float qi = (TIS && active) ? (float)sq[dmask ? i : self] : 0.f;
   const int jb = blockIdx.y * chunk, je = min(n_s, jb + chunk);
   float hx = 0, hy = 0, hz = 0, lx = 0, ly = 0, lz = 0;
   for (int jt = jb; jt < je; jt += kT) {
+    if (dmask && !((dmask[(size_t)blockIdx.x * dwpr + ((jt / kT) >> 5)] >> ((jt / kT) & 31)) & 1u)) continue;
     const int cnt = min(kT, je - jt);
     const float q0 = (float)sq[jt];
     __syncthreads();
@@ -568,6 +576,173 @@ __global__ __launch_bounds__(kT) void k_pair_bwd_t_mixed(int n_t, const double *
     part[o + i] = (double)hx + (double)lx;
     part[o + (size_t)n_t + i] = (double)hy + (double)ly;
     part[o + 2 * (size_t)n_t + i] = (double)hz + (double)lz;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pairwise adjoint with every unordered pair evaluated once (targets =
+// sources, mixed, softened).  The term of the pair (i, j) in g_i is
+// v = J(d) a with d = x_i - x_j and a = q_j w_i - q_i w_j; in g_j it is
+// J(-d)(-a) = -v, since J is even in d.  Super-blocks, ownership, the lane
+// rotation of the sources' sums and the partial slots are those of the
+// field's pair-once kernel (k_pair_sym); tile pairs that the mask leaves to
+// k_pair_bwd_t_mixed are masked here by a softening of 1e36 (r^-3 and r^-5
+// underflow to 0).  Per pair 26 VALU operations and one reciprocal square
+// root for two terms: 3 sub, 3 FMA (d^2 + s^2), rsqrt, 2 mul (r^-2, r^-3),
+// 3 sub (a), 3 (d . a), 2 mul (3 r^-2 d . a), 3 FMA (a - u d), 3 + 3 FMA into
+// the two sums.  Pi / Pj as in k_pair_sym (g in units of 1/k_e).
+template <int T>
+__global__ __launch_bounds__(kT, 4) void k_pair_bwd_sym(int n, const double *__restrict__ sx,
+                                                      const double *__restrict__ sy,
+                                                      const double *__restrict__ sz,
+                                                      const double *__restrict__ sq,
+                                                      const double *__restrict__ w, const double *__restrict__ sb,
+                                                      const uint32_t *__restrict__ dmask, int dwpr, float soft2,
+                                                      int ns, int d0, float *__restrict__ Pi,
+                                                      float *__restrict__ Pj) {
+  // positions and charges, and the weights (q_A w_j with one charge per
+  // side, else w_j), each group of 64 sources twice in a row
+  __shared__ float4 S[kT / 64][128];
+  __shared__ float4 Wl[kT / 64][128];
+  __shared__ float J[kT / 64][3][kT];
+  __shared__ unsigned long long skipS;
+  static_assert(T * T <= 64, "one mask bit per lane of a wave");
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nxt = ((lane + 1) & 63) << 2;
+  const int A = blockIdx.x;
+  const int dd = blockIdx.y;
+  const int d = d0 + dd;
+  if (d > sym_h(A, ns)) return;  // workgroup-uniform, before any barrier
+  const int B = (A + d) % ns;
+  const int a0 = A * T * kT, b0 = B * T * kT;
+  const double c0 = sb[4 * (size_t)A], c1 = sb[4 * (size_t)A + 1], c2 = sb[4 * (size_t)A + 2];
+  float r0[T], r1[T], r2[T], wx[T], wy[T], wz[T], qa[T];
+  const float qA = (float)sq[a0], qB = (float)sq[b0];
+  bool uni = true;
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    const int i = a0 + k * kT + tid;
+    const bool act = i < n;
+    r0[k] = act ? (float)(sx[i] - c0) : 0.f;
+    r1[k] = act ? (float)(sy[i] - c1) : 0.f;
+    r2[k] = act ? (float)(sz[i] - c2) : 0.f;
+    wx[k] = act ? (float)w[i] : 0.f;
+    wy[k] = act ? (float)w[(size_t)n + i] : 0.f;
+    wz[k] = act ? (float)w[2 * (size_t)n + i] : 0.f;
+    qa[k] = act ? (float)sq[i] : 0.f;
+    const int j = b0 + k * kT + tid;
+    uni = uni && act && qa[k] == qA && j < n && (float)sq[j] == qB;
+  }
+  if (wv == 0) {
+    bool near = false;
+    if (lane < T * T) {
+      const int ka = lane % T, kb = lane / T;
+      const int ta = A * T + ka, tb = B * T + kb;
+      if (a0 + ka * kT < n && b0 + kb * kT < n) near = (dmask[(size_t)ta * dwpr + (tb >> 5)] >> (tb & 31)) & 1u;
+    }
+    const unsigned long long m = __ballot(near);
+    if (lane == 0) skipS = m;
+  }
+  const bool U = __syncthreads_and(uni);
+  const unsigned long long skip = skipS;
+  if (U) {
+    // a = q_B w_i - q_A w_j: the target part once per particle
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      wx[k] *= qB;
+      wy[k] *= qB;
+      wz[k] *= qB;
+    }
+  }
+  float gx[T], gy[T], gz[T];
+#pragma unroll
+  for (int k = 0; k < T; ++k) gx[k] = gy[k] = gz[k] = 0.f;
+  for (int bt = 0; bt < T; ++bt) {
+    const int jt = b0 + bt * kT;
+    if (jt >= n) break;  // workgroup-uniform
+    const int cnt = min(kT, n - jt);
+    const unsigned sk = (unsigned)(skip >> (T * bt)) & ((1u << T) - 1u);
+    float s2k[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) s2k[k] = ((sk >> k) & 1u) ? 1e36f : soft2;
+    __syncthreads();  // the previous tile's S, Wl and J are consumed
+    {
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f), u = v;
+      if (tid < cnt) {
+        const int j = jt + tid;
+        const float f = U ? qA : 1.f;
+        v = make_float4((float)(sx[j] - c0), (float)(sy[j] - c1), (float)(sz[j] - c2), (float)sq[j]);
+        u = make_float4(f * (float)w[j], f * (float)w[(size_t)n + j], f * (float)w[2 * (size_t)n + j], 0.f);
+      }
+      S[tid >> 6][tid & 63] = v;
+      S[tid >> 6][(tid & 63) + 64] = v;
+      Wl[tid >> 6][tid & 63] = u;
+      Wl[tid >> 6][(tid & 63) + 64] = u;
+    }
+    __syncthreads();
+    for (int g = 0; g < cnt; g += 64) {
+      const float4 *sg = &S[g >> 6][lane];
+      const float4 *wg = &Wl[g >> 6][lane];
+      float tx = 0.f, ty = 0.f, tz = 0.f;
+#pragma unroll 4
+      for (int m = 0; m < 64; ++m) {
+        const float4 sj = sg[m];
+        const float4 wj = wg[m];
+        float cx = 0.f, cy = 0.f, cz = 0.f;
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+          const float dx = r0[k] - sj.x, dy = r1[k] - sj.y, dz = r2[k] - sj.z;
+          const float rr = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, s2k[k])));
+          const float ri = __builtin_amdgcn_rsqf(rr);
+          const float ri2 = ri * ri;
+          const float ri3 = ri * ri2;
+          float ax, ay, az;
+          if (U) {
+            ax = wx[k] - wj.x;
+            ay = wy[k] - wj.y;
+            az = wz[k] - wj.z;
+          } else {
+            ax = fmaf(sj.w, wx[k], -qa[k] * wj.x);
+            ay = fmaf(sj.w, wy[k], -qa[k] * wj.y);
+            az = fmaf(sj.w, wz[k], -qa[k] * wj.z);
+          }
+          const float u = (3.0f * ri2) * fmaf(dx, ax, fmaf(dy, ay, dz * az));
+          const float vx = fmaf(-u, dx, ax), vy = fmaf(-u, dy, ay), vz = fmaf(-u, dz, az);
+          gx[k] = fmaf(ri3, vx, gx[k]);
+          gy[k] = fmaf(ri3, vy, gy[k]);
+          gz[k] = fmaf(ri3, vz, gz[k]);
+          cx = fmaf(ri3, vx, cx);
+          cy = fmaf(ri3, vy, cy);
+          cz = fmaf(ri3, vz, cz);
+        }
+        tx = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(tx + cx)));
+        ty = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(ty + cy)));
+        tz = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(tz + cz)));
+      }
+      J[wv][0][g + lane] = tx;
+      J[wv][1][g + lane] = ty;
+      J[wv][2][g + lane] = tz;
+    }
+    __syncthreads();
+    // the sources' terms: -v, the four waves' rows added in order
+    if (tid < cnt) {
+      const size_t o = (size_t)dd * 3 * n + jt + tid;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float v = ((J[0][c][tid] + J[1][c][tid]) + J[2][c][tid]) + J[3][c][tid];
+        Pj[o + (size_t)c * n] = -v;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    const int i = a0 + k * kT + tid;
+    if (i < n) {
+      const size_t o = (size_t)dd * 3 * n + i;
+      Pi[o] = gx[k];
+      Pi[o + (size_t)n] = gy[k];
+      Pi[o + 2 * (size_t)n] = gz[k];
+    }
   }
 }
 
@@ -807,9 +982,24 @@ extern "C" obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh
   }
   if (n_tgt == 0) return OBEM_OK;
 
+  int excl = 0;
+  if (!(soft > 0.0)) excl = 1;
+  // targets = sources: with the pair-once evaluation the targets take the
+  // sources' order (charge sign, then Morton; same particles, same tiles)
+  const bool once = tis && want_t && excl == 0 && pair_once_applies(n_tgt, precision, soft, false);
+  SourceOrder so;
   TargetOrder to;
-  obem_status st = order_targets(ctx, n_tgt, tx, ty, tz, &to);
-  if (st) return st;
+  obem_status st = OBEM_OK;
+  if (once) {
+    st = order_sources(ctx, n_src, sx, sy, sz, sq, false, &so);
+    if (st) return st;
+    to.n = (int32_t)n_tgt;
+    to.perm = const_cast<int32_t *>(so.perm);
+    to.xs = const_cast<double *>(so.x);
+  } else {
+    st = order_targets(ctx, n_tgt, tx, ty, tz, &to);
+    if (st) return st;
+  }
   const int n_t = (int)n_tgt, n_s = (int)n_src;
   double *wsrt = (double *)ws_get(ctx, WS_MISC1, sizeof(double) * 3 * (size_t)n_t);
   double *gx = (double *)ws_get(ctx, WS_ACC, sizeof(double) * 4 * (size_t)n_t);
@@ -849,8 +1039,6 @@ extern "C" obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh
       OBEM_HIP(ctx, hipGetLastError());
     }
   }
-  int excl = 0;
-  if (!(soft > 0.0)) excl = 1;
   if (n_s > 0 && want_t) {
     int nsplit, chunk;
     split_for(bt, n_s, &nsplit, &chunk);
@@ -858,11 +1046,22 @@ extern "C" obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh
     if (!part) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
     dim3 grid(bt, nsplit);
     OBEM_PROF(ctx, "pair_bwd");
+    double *sb = nullptr;
+    uint32_t *dmask = nullptr;
+    int dwpr = 0;
+    if (once) {
+      st = pair_once_setup(ctx, n_t, kBwdTiles, so.tbox, false, 0.0, &sb, &dmask, &dwpr);
+      if (st) return st;
+    }
+    // sources: the caller's arrays, or the ordered copy (and the weights in
+    // that order) under the pair-once evaluation
+    const double *px = once ? so.x : sx, *py = once ? so.y : sy, *pz = once ? so.z : sz, *pq = once ? so.q : sq;
+    const double *wjx = once ? wsrt : gEx, *wjy = once ? wsrt + n_t : gEy, *wjz = once ? wsrt + 2 * (size_t)n_t : gEz;
 #define BWD_T(TIS, EX)                                                                                            \
   if (tis == TIS && excl == EX) {                                                                                 \
     if (precision == OBEM_MIXED)                                                                                  \
       hipLaunchKernelGGL((k_pair_bwd_t_mixed<TIS, EX>), grid, dim3(kT), 0, ctx->stream, n_t, to.xs, to.perm, wsrt, \
-                         n_s, sx, sy, sz, sq, gEx, gEy, gEz, (float)(soft * soft), chunk, part);                 \
+                         n_s, px, py, pz, pq, wjx, wjy, wjz, (float)(soft * soft), chunk, part, dmask, dwpr);    \
     else                                                                                                          \
       hipLaunchKernelGGL((k_pair_bwd_t_fp64<TIS, EX>), grid, dim3(kT), 0, ctx->stream, n_t, to.xs, to.perm, wsrt,  \
                          n_s, sx, sy, sz, sq, gEx, gEy, gEz, soft * soft, chunk, part);                          \
@@ -876,6 +1075,24 @@ extern "C" obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh
     hipLaunchKernelGGL(k_sum_chunks3, dim3(bt), dim3(256), 0, ctx->stream, n_t, nsplit, part, have_gx ? 1 : 0, gx);
     OBEM_HIP(ctx, hipGetLastError());
     have_gx = true;
+    if (once) {
+      // the tile pairs between super-blocks, each evaluated once for both
+      const int sbsz = kBwdTiles * kT;
+      const int ns = (n_t + sbsz - 1) / sbsz;
+      const int hmax = ns / 2;
+      if (hmax > 0) {
+        float *Pi = (float *)ws_get(ctx, WS_SYMI, sizeof(float) * 3 * kBwdSlots * (size_t)n_t);
+        float *Pj = (float *)ws_get(ctx, WS_SYMJ, sizeof(float) * 3 * kBwdSlots * (size_t)n_t);
+        if (!Pi || !Pj) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+        for (int d0 = 1; d0 <= hmax; d0 += kBwdSlots) {
+          const int dcnt = std::min(kBwdSlots, hmax - d0 + 1);
+          hipLaunchKernelGGL(k_pair_bwd_sym<kBwdTiles>, dim3(ns, dcnt), dim3(kT), 0, ctx->stream, n_t, so.x, so.y,
+                             so.z, so.q, wsrt, sb, dmask, dwpr, (float)(soft * soft), ns, d0, Pi, Pj);
+          launch_sym_reduce(ctx, n_t, sbsz, ns, d0, dcnt, Pi, Pj, gx);
+        }
+        OBEM_HIP(ctx, hipGetLastError());
+      }
+    }
   }
   if (want_t) {
     if (!have_gx) {

@@ -13,6 +13,7 @@
 
 #include "cellmath.hpp"
 #include "obem_internal.hpp"
+#include "paironce.hpp"
 
 namespace obem {
 
@@ -735,36 +736,6 @@ __device__ __forceinline__ void pair_tile_far(const float4 *S2, int cnt, float m
   }
 }
 
-// Squared gap between the boxes of source tiles a and b (FP64, 256-source
-// tiles), symmetric in a and b bit for bit.
-__device__ __forceinline__ double tiles_gap2(const double *__restrict__ tbox, int a, int b) {
-  const double *p = tbox + 6 * (size_t)a, *q = tbox + 6 * (size_t)b;
-  double g2 = 0.0;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const double g = fmax(0.0, fmax(q[c] - p[3 + c], p[c] - q[3 + c]));
-    g2 = fma(g, g, g2);
-  }
-  return g2;
-}
-
-// Whether the tile pair (a, b) is left to the directed kernel under the
-// pair-once evaluation (super-blocks of sym_tiles tiles): tiles of one
-// super-block, tiles within the partner cut (nn), and tiles closer than an
-// eighth of the larger radius R of their two super-blocks about the centres
-// the pair-once kernel recentres on (k_sym_radius): beyond that gap the FP32
-// difference r - s it forms, from coordinates of size up to R + |r - s|,
-// carries at most about 17 ulps of |r - s|.  Symmetric in a and b, and
-// evaluated the same way by both kernels, so that every tile pair is taken
-// by exactly one of them.
-__device__ __forceinline__ bool tile_pair_direct(const double *__restrict__ tbox, const double *__restrict__ sb,
-                                                 int a, int b, int sym_tiles, bool nn, double cut2) {
-  const int A = a / sym_tiles, B = b / sym_tiles;
-  if (A == B) return true;
-  const double g2 = tiles_gap2(tbox, a, b);
-  return 64.0 * g2 < fmax(sb[4 * (size_t)A + 3], sb[4 * (size_t)B + 3]) || (nn && g2 <= cut2);
-}
-
 // Per super-block: the centre of the box around its tiles' boxes (the
 // origin the pair-once kernel recentres on) and the squared distance from
 // it to the box's corners, sb[4 A + 0..2] and sb[4 A + 3].
@@ -996,10 +967,6 @@ constexpr int kSymTiles = 8;
 constexpr int kSymSB = kSymTiles * kThreads;  // particles per super-block
 constexpr int kSymSlots = 32;                 // values of d per launch
 
-__host__ __device__ __forceinline__ int sym_h(int A, int ns) {
-  return (ns & 1) ? (ns - 1) / 2 : (A < ns / 2 ? ns / 2 : ns / 2 - 1);
-}
-
 template <bool NN>
 __global__ __launch_bounds__(kThreads, 4) void k_pair_sym(int n, const double *__restrict__ sx,
                                                         const double *__restrict__ sy,
@@ -1162,11 +1129,12 @@ __global__ __launch_bounds__(kThreads, 4) void k_pair_sym(int n, const double *_
 // acc[c][p] += the launch's slots that hold a field at p, in slot order: the
 // slot of d as the owner of (A, A + d) and the slot of d as the partner of
 // (A - d, A).
-__global__ __launch_bounds__(256) void k_sym_reduce(int n, int ns, int d0, int dcnt, const float *__restrict__ Pi,
-                                                    const float *__restrict__ Pj, double *acc) {
+__global__ __launch_bounds__(256) void k_sym_reduce(int n, int sbsz, int ns, int d0, int dcnt,
+                                                    const float *__restrict__ Pi, const float *__restrict__ Pj,
+                                                    double *acc) {
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= n) return;
-  const int A = p / kSymSB;
+  const int A = p / sbsz;
   const int hA = sym_h(A, ns);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -1343,16 +1311,10 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
   const int ns = (n_t + kSymSB - 1) / kSymSB;
   double *sb = nullptr;
   uint32_t *dmask = nullptr;
-  const int ntile = nblk(n_t);
-  const int dwpr = (ntile + 31) / 32;
+  int dwpr = 0;
   if (once) {
-    sb = (double *)ws_get(ctx, WS_SYMR, sizeof(double) * 4 * (size_t)ns);
-    dmask = (uint32_t *)ws_get(ctx, WS_SYMM, sizeof(uint32_t) * (size_t)ntile * dwpr);
-    if (!sb || !dmask) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
-    hipLaunchKernelGGL(k_sym_radius, dim3((ns + 255) / 256), dim3(256), 0, ctx->stream, n_t, ns, kSymTiles, tbox, sb);
-    const size_t nw = (size_t)ntile * dwpr;
-    hipLaunchKernelGGL(k_tile_mask, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, ctx->stream, ntile, dwpr,
-                       kSymTiles, nn ? 1 : 0, nn_cut2d, tbox, sb, dmask);
+    obem_status st = pair_once_setup(ctx, n_t, kSymTiles, tbox, nn, nn_cut2d, &sb, &dmask, &dwpr);
+    if (st) return st;
   }
   {
   OBEM_PROF(ctx, "pair");
@@ -1404,8 +1366,7 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
         else
           hipLaunchKernelGGL(k_pair_sym<false>, g, dim3(kThreads), 0, ctx->stream, n_t, sx, sy, sz, sq, tbox,
                              nn_cut2d, sb, (float)(soft * soft), ns, d0, Pi, Pj);
-        hipLaunchKernelGGL(k_sym_reduce, dim3(nblk(n_t)), dim3(256), 0, ctx->stream, n_t, ns, d0, dcnt, Pi, Pj,
-                           acc);
+        launch_sym_reduce(ctx, n_t, kSymSB, ns, d0, dcnt, Pi, Pj, acc);
       }
       OBEM_HIP(ctx, hipGetLastError());
     }
@@ -1415,6 +1376,27 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
 
 // Up to 2^24 particles: the tile-pair mask takes at most 512 MB and the
 // partial slots 12.9 GB; larger sets keep the directed evaluation.
+obem_status pair_once_setup(obem_ctx *ctx, int n, int sym_tiles, const double *tbox, bool nn, double cut2d,
+                            double **sb, uint32_t **dmask, int *dwpr) {
+  const int ns = (n + sym_tiles * kThreads - 1) / (sym_tiles * kThreads);
+  const int ntile = nblk(n);
+  *dwpr = (ntile + 31) / 32;
+  *sb = (double *)ws_get(ctx, WS_SYMR, sizeof(double) * 4 * (size_t)ns);
+  *dmask = (uint32_t *)ws_get(ctx, WS_SYMM, sizeof(uint32_t) * (size_t)ntile * *dwpr);
+  if (!*sb || !*dmask) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  hipLaunchKernelGGL(k_sym_radius, dim3((ns + 255) / 256), dim3(256), 0, ctx->stream, n, ns, sym_tiles, tbox, *sb);
+  const size_t nw = (size_t)ntile * *dwpr;
+  hipLaunchKernelGGL(k_tile_mask, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, ctx->stream, ntile, *dwpr,
+                     sym_tiles, nn ? 1 : 0, cut2d, tbox, *sb, *dmask);
+  OBEM_HIP(ctx, hipGetLastError());
+  return OBEM_OK;
+}
+
+void launch_sym_reduce(obem_ctx *ctx, int n, int sbsz, int ns, int d0, int dcnt, const float *Pi, const float *Pj,
+                       double *acc) {
+  hipLaunchKernelGGL(k_sym_reduce, dim3(nblk(n)), dim3(256), 0, ctx->stream, n, sbsz, ns, d0, dcnt, Pi, Pj, acc);
+}
+
 bool pair_once_applies(int64_t n, obem_precision prec, double soft, bool want_v) {
   return prec == OBEM_MIXED && soft > 0.0 && !want_v && n > 2 * (int64_t)kSymSB && n <= ((int64_t)1 << 24);
 }

@@ -172,6 +172,16 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
 // both) applies: mixed precision, softened, no potential, more than two
 // super-blocks of 2048 particles and at most 2^24 particles.
 bool pair_once_applies(int64_t n, obem_precision prec, double soft, bool want_v);
+// Pair-once set-up for n particles in super-blocks of sym_tiles tiles: the
+// super-blocks' centres and squared radii (sb, 4 per super-block) and the
+// mask of tile pairs left to the directed kernel (dwpr 32-bit words per row,
+// nn: also the pairs within the partner cut cut2d).  Workspace owned by ctx.
+obem_status pair_once_setup(obem_ctx *ctx, int n, int sym_tiles, const double *tbox, bool nn, double cut2d,
+                            double **sb, uint32_t **dmask, int *dwpr);
+// Adds the FP32 partial slots of one pair-once launch (d = d0 .. d0 + dcnt - 1)
+// to the FP64 sums acc[3][n], in slot order; sbsz particles per super-block.
+void launch_sym_reduce(obem_ctx *ctx, int n, int sbsz, int ns, int d0, int dcnt, const float *Pi, const float *Pj,
+                       double *acc);
 
 // Copy of the point sources in (charge sign, Morton) order with per-256-tile
 // boxes (field.hip); inv (caller index -> position) when asked for.  Uses the

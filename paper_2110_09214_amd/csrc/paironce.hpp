@@ -1,0 +1,47 @@
+// Pair-once evaluation of pairwise sums (targets = sources): ownership of
+// super-block pairs and the rule that leaves tile pairs to the directed
+// kernels, shared by the field and its adjoint.
+#pragma once
+
+#include <cstdint>
+
+namespace obem {
+
+// Number of partners d = 1 .. sym_h(A) that super-block A owns among ns:
+// A owns (A, A + d mod ns), so that every unordered pair of super-blocks has
+// one owner and the owners' shares differ by at most one.
+__host__ __device__ __forceinline__ int sym_h(int A, int ns) {
+  return (ns & 1) ? (ns - 1) / 2 : (A < ns / 2 ? ns / 2 : ns / 2 - 1);
+}
+
+// Squared gap between the boxes of source tiles a and b (FP64, 256-source
+// tiles), symmetric in a and b bit for bit.
+__device__ __forceinline__ double tiles_gap2(const double *__restrict__ tbox, int a, int b) {
+  const double *p = tbox + 6 * (size_t)a, *q = tbox + 6 * (size_t)b;
+  double g2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double g = fmax(0.0, fmax(q[c] - p[3 + c], p[c] - q[3 + c]));
+    g2 = fma(g, g, g2);
+  }
+  return g2;
+}
+
+// Whether the tile pair (a, b) is left to the directed kernel under the
+// pair-once evaluation (super-blocks of sym_tiles tiles): tiles of one
+// super-block, tiles within the partner cut (nn), and tiles closer than an
+// eighth of the larger radius R of their two super-blocks about the centres
+// the pair-once kernel recentres on (k_sym_radius): beyond that gap the FP32
+// difference r - s it forms, from coordinates of size up to R + |r - s|,
+// carries at most about 17 ulps of |r - s|.  Symmetric in a and b, and
+// evaluated the same way by both kernels, so that every tile pair is taken
+// by exactly one of them.
+__device__ __forceinline__ bool tile_pair_direct(const double *__restrict__ tbox, const double *__restrict__ sb,
+                                                 int a, int b, int sym_tiles, bool nn, double cut2) {
+  const int A = a / sym_tiles, B = b / sym_tiles;
+  if (A == B) return true;
+  const double g2 = tiles_gap2(tbox, a, b);
+  return 64.0 * g2 < fmax(sb[4 * (size_t)A + 3], sb[4 * (size_t)B + 3]) || (nn && g2 <= cut2);
+}
+
+}  // namespace obem
