@@ -73,3 +73,23 @@ def test_pair_once_against_directed_and_oracle(ctx, orc, n, kind):
     assert e_w1.max() <= 1.5 * max(e_wd.max(), 1e-6)
     assert err_o <= (1e-5 if kind == "electrons" else 3e-5)
     assert err_d <= 2.0 * err_do + 1e-7
+
+
+@pytest.mark.parametrize("n,kind", [(4097, "electrons"), (9001, "both"), (9001, "with_zeros")])
+def test_pair_once_adjoint_against_oracle(ctx, orc, n, kind):
+    """The pair-once pairwise adjoint (the term J(d) a of a pair, with
+    a = q_j w_i - q_i w_j, evaluated once for both particles) against the
+    oracle's gradient at every particle: super-blocks of 1024, so 5 and 9
+    super-blocks with ragged last ones."""
+    x, q = _cloud(n, 60 + n % 89, kind)
+    w = np.random.default_rng(n + 1).normal(size=x.shape)
+    g_ref, _ = orc.pair_backward(x, x, q, 1e-7, w, tgt_is_src=True)
+    _, gt, _ = B.field_eval_backward(ctx, None, None, dev(x), dev(q), dev(x), 1e-7, dev(w), B.OBEM_MIXED,
+                                     tgt_is_src=True)
+    _, gt2, _ = B.field_eval_backward(ctx, None, None, dev(x), dev(q), dev(x), 1e-7, dev(w), B.OBEM_MIXED,
+                                      tgt_is_src=True)
+    gt = host(gt)
+    assert np.array_equal(gt, host(gt2))
+    err = rel_l2(gt, g_ref)
+    print(f"pair-once adjoint n={n} {kind}: rel L2 vs oracle {err:.3g}")
+    assert err <= 1e-4
