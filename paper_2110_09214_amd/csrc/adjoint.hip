@@ -615,7 +615,8 @@ __global__ __launch_bounds__(kT, 4) void k_pair_bwd_sym(int n, const double *__r
   if (d > sym_h(A, ns)) return;  // workgroup-uniform, before any barrier
   const int B = (A + d) % ns;
   const int a0 = A * T * kT, b0 = B * T * kT;
-  const double c0 = sb[4 * (size_t)A], c1 = sb[4 * (size_t)A + 1], c2 = sb[4 * (size_t)A + 2];
+  const double *org = sym_origin(sb, A, B);
+  const double c0 = org[0], c1 = org[1], c2 = org[2];
   float r0[T], r1[T], r2[T], wx[T], wy[T], wz[T], qa[T];
   const float qA = (float)sq[a0], qB = (float)sq[b0];
   bool uni = true;

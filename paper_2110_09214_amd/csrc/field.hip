@@ -944,8 +944,8 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
 // d = 1 .. sym_h(A), so that each unordered pair has exactly one owner.
 //
 // A workgroup takes one (A, d): thread t holds the kSymTiles particles
-// A kSymSB + k 256 + t of A (FP32, recentred on the centre of A's box),
-// B = A + d streams through LDS
+// A kSymSB + k 256 + t of A (FP32, recentred on sym_origin, the centre of
+// the more compact of A and B), B = A + d streams through LDS
 // tile by tile.  Within a tile, a wave takes the sources in groups of 64 and
 // 64 steps per group: at step m lane l pairs its particles with source
 // (l + m) mod 64 of the group.  The sums for A's particles stay in
@@ -988,7 +988,8 @@ __global__ __launch_bounds__(kThreads, 4) void k_pair_sym(int n, const double *_
   if (d > sym_h(A, ns)) return;  // workgroup-uniform, before any barrier
   const int B = (A + d) % ns;
   const int a0 = A * kSymSB, b0 = B * kSymSB;
-  const double c0 = sb[4 * (size_t)A], c1 = sb[4 * (size_t)A + 1], c2 = sb[4 * (size_t)A + 2];
+  const double *org = sym_origin(sb, A, B);
+  const double c0 = org[0], c1 = org[1], c2 = org[2];
   float r0[kSymTiles], r1[kSymTiles], r2[kSymTiles], qa[kSymTiles];
   const float qA = (float)sq[a0], qB = (float)sq[b0];
   bool uni = true;

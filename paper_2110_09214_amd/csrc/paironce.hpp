@@ -30,18 +30,25 @@ __device__ __forceinline__ double tiles_gap2(const double *__restrict__ tbox, in
 // Whether the tile pair (a, b) is left to the directed kernel under the
 // pair-once evaluation (super-blocks of sym_tiles tiles): tiles of one
 // super-block, tiles within the partner cut (nn), and tiles closer than an
-// eighth of the larger radius R of their two super-blocks about the centres
-// the pair-once kernel recentres on (k_sym_radius): beyond that gap the FP32
-// difference r - s it forms, from coordinates of size up to R + |r - s|,
-// carries at most about 17 ulps of |r - s|.  Symmetric in a and b, and
-// evaluated the same way by both kernels, so that every tile pair is taken
-// by exactly one of them.
+// eighth of the smaller radius R of their two super-blocks (sb: centre and
+// R^2 per super-block).  The pair-once kernels recentre a super-block pair
+// on the centre of the super-block with the smaller radius
+// (sym_origin), so beyond that gap the FP32 difference r - s they form, from
+// coordinates of size up to R + |r - s|, carries at most about 17 ulps of
+// |r - s|.  Symmetric in a and b, and evaluated the same way by both sides,
+// so that every tile pair is taken by exactly one of them.
 __device__ __forceinline__ bool tile_pair_direct(const double *__restrict__ tbox, const double *__restrict__ sb,
                                                  int a, int b, int sym_tiles, bool nn, double cut2) {
   const int A = a / sym_tiles, B = b / sym_tiles;
   if (A == B) return true;
   const double g2 = tiles_gap2(tbox, a, b);
-  return 64.0 * g2 < fmax(sb[4 * (size_t)A + 3], sb[4 * (size_t)B + 3]) || (nn && g2 <= cut2);
+  return 64.0 * g2 < fmin(sb[4 * (size_t)A + 3], sb[4 * (size_t)B + 3]) || (nn && g2 <= cut2);
+}
+
+// The origin of the super-block pair (A, B): the centre of the one with the
+// smaller radius (A on a tie).
+__device__ __forceinline__ const double *sym_origin(const double *__restrict__ sb, int A, int B) {
+  return sb[4 * (size_t)B + 3] < sb[4 * (size_t)A + 3] ? sb + 4 * (size_t)B : sb + 4 * (size_t)A;
 }
 
 }  // namespace obem
