@@ -177,7 +177,13 @@ obem_status bem_influence(obem_ctx *ctx, const obem_meshh *mesh, int64_t n_src, 
  * overwritten.  A target exactly in a cell's plane inside the cell gets the
  * principal value of that cell's normal field (0).  soft >= 0 is the Plummer
  * softening length; with soft == 0 coincident distinct points are the
- * caller's responsibility (their term is dropped). */
+ * caller's responsibility (their term is dropped).
+ * With OBEM_TGT_IS_SRC, OBEM_MIXED, soft > 0, no potential and 4097 to 2^24
+ * charges, the pairwise sum evaluates every unordered pair of charges in
+ * different 2048-charge blocks once for both (the pair term is
+ * antisymmetric); its FP32 partial sums take 2 x 96 n bytes of context
+ * workspace (1.5 GB at n = 4M) and are summed in FP64 in a fixed order.
+ * track_step uses the same evaluation for its field. */
 obem_status field_eval(obem_ctx *ctx, const obem_meshh *mesh, const double *sigma, int64_t n_src,
                        const double *sx, const double *sy, const double *sz, const double *sq,
                        int64_t n_tgt, const double *tx, const double *ty, const double *tz, double soft,
@@ -192,7 +198,9 @@ obem_status field_eval(obem_ctx *ctx, const obem_meshh *mesh, const double *sigm
  * and g_sx/g_sy/g_sz are ignored.  Any output may be NULL (not computed);
  * outputs are overwritten.  Sums are deterministic (fixed-order reductions,
  * no floating-point atomics); source tiles are recomputed, nothing is kept
- * from the forward call. */
+ * from the forward call.  With OBEM_TGT_IS_SRC under the conditions of
+ * field_eval's pair-once evaluation, the pairwise term J(d) a of each pair
+ * of charges in different 1024-charge blocks is evaluated once for both. */
 obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh, const double *sigma,
                                 int64_t n_src, const double *sx, const double *sy, const double *sz,
                                 const double *sq, int64_t n_tgt, const double *tx, const double *ty,
