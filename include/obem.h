@@ -181,8 +181,9 @@ obem_status bem_influence(obem_ctx *ctx, const obem_meshh *mesh, int64_t n_src, 
  * With OBEM_TGT_IS_SRC, OBEM_MIXED, soft > 0, no potential and 4097 to 2^24
  * charges, the pairwise sum evaluates every unordered pair of charges in
  * different 2048-charge blocks once for both (the pair term is
- * antisymmetric); its FP32 partial sums take 2 x 96 n bytes of context
- * workspace (1.5 GB at n = 4M) and are summed in FP64 in a fixed order.
+ * antisymmetric); its FP32 partial sums take 768 n bytes of context
+ * workspace (3.1 GB at n = 4M), its tile-pair mask (n / 256)^2 / 8 bytes, and
+ * the partial sums are added in FP64 in a fixed order.
  * track_step uses the same evaluation for its field. */
 obem_status field_eval(obem_ctx *ctx, const obem_meshh *mesh, const double *sigma, int64_t n_src,
                        const double *sx, const double *sy, const double *sz, const double *sq,
