@@ -75,12 +75,13 @@ def test_pair_once_against_directed_and_oracle(ctx, orc, n, kind):
     assert err_d <= 2.0 * err_do + 1e-7
 
 
-@pytest.mark.parametrize("n,kind", [(4097, "electrons"), (9001, "both"), (9001, "with_zeros")])
+@pytest.mark.parametrize("n,kind", [(4097, "electrons"), (8000, "both"), (9001, "both"), (9001, "with_zeros")])
 def test_pair_once_adjoint_against_oracle(ctx, orc, n, kind):
     """The pair-once pairwise adjoint (the term J(d) a of a pair, with
     a = q_j w_i - q_i w_j, evaluated once for both particles) against the
-    oracle's gradient at every particle: super-blocks of 1024, so 5 and 9
-    super-blocks with ragged last ones."""
+    oracle's gradient at every particle: super-blocks of 1024, so 5, 8 (an
+    even count: one more partner for the first half) and 9 super-blocks,
+    with ragged last ones."""
     x, q = _cloud(n, 60 + n % 89, kind)
     w = np.random.default_rng(n + 1).normal(size=x.shape)
     g_ref, _ = orc.pair_backward(x, x, q, 1e-7, w, tgt_is_src=True)
