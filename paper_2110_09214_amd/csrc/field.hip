@@ -1049,7 +1049,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_pair_sym(int n, const double *_
       float tx = 0.f, ty = 0.f, tz = 0.f;
       if (U) {
         const float4 *sg = &S[g >> 6][lane];
-#pragma unroll 8
+#pragma unroll 4
         for (int m = 0; m < 64; ++m) {
           const float4 sj = sg[m];
           float cx = 0.f, cy = 0.f, cz = 0.f;
@@ -1072,7 +1072,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_pair_sym(int n, const double *_
         }
       } else {
         const float4 *sg = &S[g >> 6][lane];
-#pragma unroll 8
+#pragma unroll 4
         for (int m = 0; m < 64; ++m) {
           const float4 sj = sg[m];
           float cx = 0.f, cy = 0.f, cz = 0.f;
