@@ -92,8 +92,9 @@ def main():
                          "WRITE_SIZE runs), print the sizes and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path shards by targets across "
-              f"GPUs (an all-gather of positions per step), which is not implemented here", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the pairwise sum would shard by "
+              "its (super-block, partner) work items with one reduce-scatter of the partial fields per step, "
+              "which is not implemented here", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
