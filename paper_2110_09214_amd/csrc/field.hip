@@ -323,7 +323,7 @@ template <bool WANT_V>
 __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double *__restrict__ xs, int N,
                                                           const double *__restrict__ f,
                                                           const double *__restrict__ sigma, int cchunk,
-                                                          double *part) {
+                                                          double *part, const double *__restrict__ tiles40) {
   __shared__ PanelCell T[kPT];
   const int tid = threadIdx.x;
   const int i0 = blockIdx.x * kThreads;
@@ -382,7 +382,23 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
     }
     __syncthreads();
     float px = 0.f, py = 0.f, pz = 0.f, pv = 0.f;
-    for (int k = 0; k < cnt; ++k) {
+    // a wave whose targets all lie outside the tile's 40 D sphere (tile
+    // centre, max over its cells of |c_k - centre| + 40 D_k) needs the
+    // 3-point rule for every cell of the tile: no per-cell test
+    const double *ts = tiles40 + 4 * (size_t)(k0 / kPT);
+    const float tr = (float)ts[3] * 1.001f;
+    const bool allfar = __all(dist2f(r0, r1, r2, (float)(ts[0] - c0), (float)(ts[1] - c1), (float)(ts[2] - c2)) >
+                              tr * tr);
+    if (allfar) {
+      for (int k = 0; k < cnt; ++k) {
+        float q[12];
+        load4<3>(&T[k].c[8], q);
+        const float w3 = T[k].c[7].y;
+        const float w[3] = {w3, w3, w3};
+        panel_points<3, WANT_V>(q, w, r0, r1, r2, px, py, pz, pv);
+      }
+    }
+    for (int k = 0; k < (allfar ? 0 : cnt); ++k) {
       const float4 g = T[k].c[0];
       const float R2 = dist2f(r0, r1, r2, g.x, g.y, g.z);
       const bool nearp = R2 < g.w;  // taken by k_panel_near in FP64
@@ -649,9 +665,10 @@ obem_status launch_panel_field(obem_ctx *ctx, const obem_meshh *m, const double 
   }
   dim3 grid(bt), gsplit(bt, ns), block(kThreads);
   OBEM_PROF(ctx, "panel");
-#define PANEL_FAR(K, V) hipLaunchKernelGGL(K<V>, gsplit, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, cchunk, part)
+#define PANEL_FAR(K, V, ...) \
+  hipLaunchKernelGGL(K<V>, gsplit, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, cchunk, part __VA_ARGS__)
   if (prec == OBEM_MIXED) {
-    if (want_v) PANEL_FAR(k_panel_mixed, true); else PANEL_FAR(k_panel_mixed, false);
+    if (want_v) PANEL_FAR(k_panel_mixed, true, , m->tiles40); else PANEL_FAR(k_panel_mixed, false, , m->tiles40);
   } else {
     if (want_v) PANEL_FAR(k_panel_fp64, true); else PANEL_FAR(k_panel_fp64, false);
   }

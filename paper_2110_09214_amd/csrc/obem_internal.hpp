@@ -76,6 +76,7 @@ struct obem_meshh {
   double max_diam = 0;
   double *tiles = nullptr;    // per 64-cell tile: centre (3), near-zone radius (3 D)
   double *tiles48 = nullptr;  // the same for the FP64 closed-form zone (48 D)
+  double *tiles40 = nullptr;  // the same for the 3-point zone of the mixed cell field (40 D)
   int32_t *order = nullptr;   // cell indices in Morton order of the centroids
   // last re-solve of a tracking step: its right-hand side and charges (lazy)
   double *rhs_last = nullptr, *sigma_last = nullptr;
