@@ -48,9 +48,21 @@ typedef enum {
 } obem_status;
 
 typedef enum {
-  OBEM_FP64 = 0,   /* every sum and integral in float64                        */
-  OBEM_MIXED = 1   /* far cells and pairwise sums in float32 with compensated
-                      accumulation; cells nearer than 3 diameters in float64  */
+  OBEM_FP64 = 0,   /* every sum and integral in float64: cells nearer than 48
+                      diameters by the closed-form integrals, farther ones by
+                      a 7-point rule; pairwise terms and sums in float64      */
+  OBEM_MIXED = 1   /* cells nearer than 3 diameters: float64 closed-form
+                      integrals.  Farther cells: float32 quadrature of the
+                      cell (7 points up to 8 diameters, 6 up to 40, 3
+                      beyond).  Pairwise terms in float32 from coordinates
+                      recentred near the targets (float32 hi + lo pairs for
+                      the sources near them, so close pairs keep their
+                      separation exactly).  Sums: float32 over blocks of
+                      sources (one 256-source tile, or with targets = sources
+                      the 2048-particle super-blocks of the pair-once
+                      evaluation), the blocks added with compensation or in
+                      float64 in a fixed order; nothing depends on timing.
+                      Positions, charges and outputs stay float64. */
 } obem_precision;
 
 /* field_eval / field_eval_backward flags */
@@ -103,6 +115,16 @@ void obem_constants(double *out);
 obem_status obem_profile_enable(obem_ctx *ctx, int enable);
 obem_status obem_profile_read(obem_ctx *ctx, int max_entries, char *names, double *ms, int64_t *launches,
                               int *n_out);
+/* Work done by the forward pairwise kernels (eq. (nbody)) while profiling
+ * was enabled, since the last call: host outputs *directed = (target,
+ * source) terms evaluated by the directed kernel (targets and sources of the
+ * tile pairs it takes, the zero self terms included) and *once = unordered
+ * pairs evaluated once for both particles by the pair-once kernel (the pairs
+ * of the tile pairs it does not leave to the directed kernel).  Together
+ * they cover every pair: n (n - 1) interactions = (*directed - n) + 2 *once
+ * for one field evaluation of n particles with targets = sources.
+ * Synchronises the stream; either pointer may be NULL.  Resets the counts. */
+obem_status obem_profile_work(obem_ctx *ctx, int64_t *directed, int64_t *once);
 
 /* Bind a mesh: copies the cell data into the handle and derives normals,
  * areas, centroids, diameters and the far-field quadrature points.  The

@@ -76,7 +76,7 @@ class StepStats_t(C.Structure):
 
 
 SYMBOLS = ["obem_create", "obem_destroy", "obem_last_error", "obem_constants", "obem_profile_enable",
-           "obem_profile_read", "obem_mesh_bind",
+           "obem_profile_read", "obem_profile_work", "obem_mesh_bind",
            "obem_mesh_release", "obem_mesh_geometry", "bem_solve_charges", "bem_solve_charges_adjoint", "bem_influence",
            "field_eval", "field_eval_backward", "field_map_build", "field_map_eval", "induced_current", "track_step"]
 
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
     lib.obem_constants.restype = None
     lib.obem_profile_enable.argtypes = [vp, i32]
     lib.obem_profile_read.argtypes = [vp, i32, vp, vp, vp, C.POINTER(C.c_int)]
+    lib.obem_profile_work.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
     lib.obem_mesh_bind.argtypes = [vp, C.POINTER(Mesh_t), C.POINTER(vp)]
     lib.obem_mesh_release.argtypes = [vp, vp]
     lib.obem_mesh_geometry.argtypes = [vp, vp, vp, vp, vp, vp, vp]
@@ -175,6 +176,13 @@ class Context:
         self.check(self.lib.obem_profile_read(self.h, m, names, ms, cnt, C.byref(n)))
         raw = names.raw
         return {raw[32 * k:32 * k + 32].split(b"\0")[0].decode(): (ms[k], cnt[k]) for k in range(n.value)}
+
+    def profile_work(self):
+        """(directed terms, pair-once pairs) of the forward pairwise kernels
+        since the last read (synchronises)."""
+        d, o = C.c_int64(), C.c_int64()
+        self.check(self.lib.obem_profile_work(self.h, C.byref(d), C.byref(o)))
+        return d.value, o.value
 
     def close(self):
         if getattr(self, "h", None):

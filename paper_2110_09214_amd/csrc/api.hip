@@ -234,6 +234,7 @@ obem_status obem_destroy(obem_ctx *ctx) {
     (void)hipEventDestroy(r.stop);
   }
   for (auto e : ctx->prof_pool) (void)hipEventDestroy(e);
+  if (ctx->work_dev) (void)hipFree(ctx->work_dev);
   for (auto &b : ctx->ws)
     if (b.p) (void)hipFree(b.p);
   solver_release(ctx);
@@ -244,7 +245,34 @@ obem_status obem_destroy(obem_ctx *ctx) {
 
 obem_status obem_profile_enable(obem_ctx *ctx, int enable) {
   if (!ctx) return OBEM_EINVAL;
+  if (enable && !ctx->work_dev) {
+    if (hipSetDevice(ctx->device) != hipSuccess ||
+        hipMalloc((void **)&ctx->work_dev, sizeof(unsigned long long)) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->work_dev = nullptr;
+      return fail(ctx, OBEM_ENOMEM, "profile counter allocation failed");
+    }
+    OBEM_HIP(ctx, hipMemsetAsync(ctx->work_dev, 0, sizeof(unsigned long long), ctx->stream));
+  }
   ctx->prof = enable != 0;
+  return OBEM_OK;
+}
+
+obem_status obem_profile_work(obem_ctx *ctx, int64_t *directed, int64_t *once) {
+  if (!ctx) return OBEM_EINVAL;
+  unsigned long long dev = 0;
+  if (ctx->work_dev) {
+    OBEM_HIP(ctx, hipSetDevice(ctx->device));
+    OBEM_HIP(ctx, hipMemcpyAsync(&dev, ctx->work_dev, sizeof(dev), hipMemcpyDeviceToHost, ctx->stream));
+    OBEM_HIP(ctx, hipMemsetAsync(ctx->work_dev, 0, sizeof(unsigned long long), ctx->stream));
+    OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  // the pair-once kernel covers the n^2 ordered terms the directed kernel
+  // does not take, two per unordered pair
+  if (directed) *directed = ctx->work_directed + (int64_t)dev;
+  if (once) *once = (ctx->work_once_n2 - (int64_t)dev) / 2;
+  ctx->work_directed = 0;
+  ctx->work_once_n2 = 0;
   return OBEM_OK;
 }
 

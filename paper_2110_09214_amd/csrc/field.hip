@@ -707,29 +707,64 @@ __device__ __forceinline__ int want_key(int8_t s) { return s == 0 ? 1 : (s == 1 
 // EXCL: 0 = no exclusion (a coincident term contributes exactly 0 to E when
 // soft > 0), 1 = drop zero-distance terms (soft == 0), 2 = drop the source
 // whose index equals the target's caller index (targets are the sources).
-template <bool WANT_V, bool NN, int EXCL, bool FOLDQ>
-__device__ __forceinline__ void pair_tile(const float4 *S, const int *K, int cnt, int jt, float r0, float r1,
-                                          float r2, float soft2, int self, int want, float &px, float &py,
-                                          float &pz, float &pv, float &best, int &bidx) {
-  for (int jj = 0; jj < cnt; ++jj) {
-    const float4 s = S[jj];
-    const float dx = r0 - s.x, dy = r1 - s.y, dz = r2 - s.z;
-    const float rr = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, soft2)));
-    float ri = __builtin_amdgcn_rsqf(rr);
-    if (EXCL == 1) ri = rr > 0.f ? ri : 0.f;
-    if (EXCL == 2) ri = (jt + jj == self) ? 0.f : ri;
-    const float qr = FOLDQ ? ri : s.w * ri;
-    const float w = qr * (ri * ri);
-    px = fmaf(w, dx, px);
-    py = fmaf(w, dy, py);
-    pz = fmaf(w, dz, pz);
-    if (WANT_V) pv += qr;
-    if (NN) {
-      if (K[jj] == want && rr < best && (EXCL != 1 || rr > 0.f)) {
-        best = rr;
-        bidx = jt + jj;
-      }
+// HL: the recentred coordinates are carried as FP32 pairs (hi, lo) with
+// hi + lo = the FP64 difference to the origin to about 2^-48 of it, and
+// r - s = (r_hi - s_hi) + (r_lo - s_lo): both differences are exact or
+// nearly so, so the separation keeps a relative error of a few 2^-24 however
+// close the pair is, instead of 2^-24 (|r| + |s|) / |r - s| with the hi parts
+// alone (tiles near the workgroup's targets, where the closest pairs are).
+template <bool WANT_V, bool NN, int EXCL, bool FOLDQ, bool HL>
+__device__ __forceinline__ void pair_term(const float4 *S, const float4 *SL, const int *K, int jj, int jt,
+                                          float r0, float r1, float r2, float rl0, float rl1, float rl2,
+                                          float soft2, int self, int want, float &px, float &py, float &pz,
+                                          float &pv, float &best, int &bidx) {
+  const float4 s = S[jj];
+  float dx = r0 - s.x, dy = r1 - s.y, dz = r2 - s.z;
+  if (HL) {
+    const float4 l = SL[jj];
+    dx += rl0 - l.x;
+    dy += rl1 - l.y;
+    dz += rl2 - l.z;
+  }
+  const float rr = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, soft2)));
+  float ri = __builtin_amdgcn_rsqf(rr);
+  if (EXCL == 1) ri = rr > 0.f ? ri : 0.f;
+  if (EXCL == 2) ri = (jt + jj == self) ? 0.f : ri;
+  const float qr = FOLDQ ? ri : s.w * ri;
+  const float w = qr * (ri * ri);
+  px = fmaf(w, dx, px);
+  py = fmaf(w, dy, py);
+  pz = fmaf(w, dz, pz);
+  if (WANT_V) pv += qr;
+  if (NN) {
+    if (K[jj] == want && rr < best && (EXCL != 1 || rr > 0.f)) {
+      best = rr;
+      bidx = jt + jj;
     }
+  }
+}
+
+// The (hi, lo) loop serves only the few tiles near the targets: it is kept
+// rolled so that its extra registers do not lower the occupancy of the
+// kernel's main loop.
+template <bool WANT_V, bool NN, int EXCL, bool FOLDQ, bool HL>
+__device__ __forceinline__ void pair_tile(const float4 *S, const float4 *SL, const float (*RL)[kThreads],
+                                          const int *K, int cnt, int jt, float r0, float r1, float r2, float soft2,
+                                          int self, int want, float &px, float &py, float &pz, float &pv,
+                                          float &best, int &bidx) {
+  float rl0 = 0.f, rl1 = 0.f, rl2 = 0.f;
+  if constexpr (HL) {
+    rl0 = RL[0][threadIdx.x];
+    rl1 = RL[1][threadIdx.x];
+    rl2 = RL[2][threadIdx.x];
+#pragma unroll 1
+    for (int jj = 0; jj < cnt; ++jj)
+      pair_term<WANT_V, NN, EXCL, FOLDQ, true>(S, SL, K, jj, jt, r0, r1, r2, rl0, rl1, rl2, soft2, self, want, px,
+                                               py, pz, pv, best, bidx);
+  } else {
+    for (int jj = 0; jj < cnt; ++jj)
+      pair_term<WANT_V, NN, EXCL, FOLDQ, false>(S, SL, K, jj, jt, r0, r1, r2, rl0, rl1, rl2, soft2, self, want, px,
+                                                py, pz, pv, best, bidx);
   }
 }
 
@@ -809,6 +844,8 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
                                                          const uint32_t *__restrict__ dmask, int dwpr) {
   constexpr bool kFar = (EXCL == 0) && !WANT_V;  // expanded far tiles allowed
   __shared__ float4 S[kThreads];
+  __shared__ float4 SL[kThreads];
+  __shared__ float RL[3][kThreads];  // lo parts of the targets (read by the (hi, lo) tiles only)
   __shared__ float4 S2[kFar ? kThreads : 1];
   __shared__ int K[kThreads];
   __shared__ float WB[kThreads / 64][6];
@@ -820,7 +857,11 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
   const double x0 = active ? xs[i] : c0;
   const double x1 = active ? xs[(size_t)n_t + i] : c1;
   const double x2 = active ? xs[2 * (size_t)n_t + i] : c2;
-  const float r0 = (float)(x0 - c0), r1 = (float)(x1 - c1), r2 = (float)(x2 - c2);
+  const double e0 = x0 - c0, e1 = x1 - c1, e2 = x2 - c2;
+  const float r0 = (float)e0, r1 = (float)e1, r2 = (float)e2;
+  RL[0][tid] = (float)(e0 - (double)r0);
+  RL[1][tid] = (float)(e1 - (double)r1);
+  RL[2][tid] = (float)(e2 - (double)r2);
   const float m0 = -2.f * r0, m1 = -2.f * r1, m2 = -2.f * r2;
   const float a_t = fmaf(r0, r0, fmaf(r1, r1, fmaf(r2, r2, soft2)));
   int want = -2;
@@ -828,12 +869,13 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
   const int self = active ? (self_map ? self_map[perm[i]] : perm[i]) : -1;
   const int jb = blockIdx.y * chunk;
   const int je = min(n_s, jb + chunk);
-  // Nearest-partner search limited to nn_cut: bounding box of the
-  // workgroup's targets (recentred FP32), tested against each source tile's
-  // box (tbox, FP64, 256-source tiles); tiles farther than the cut skip the
-  // search.  Inactive lanes hold the first target, which is inside the box.
+  // Bounding box of the workgroup's targets (recentred FP32), tested against
+  // each source tile's box (tbox, FP64, 256-source tiles): tiles farther
+  // than the partner cut skip the nearest-partner search, far tiles take the
+  // expanded form, near ones the (hi, lo) separation.  Inactive lanes hold
+  // the first target, which is inside the box.
   float bl0 = r0, bl1 = r1, bl2 = r2, bh0 = r0, bh1 = r1, bh2 = r2;
-  if ((NN || kFar) && tbox) {
+  if (tbox) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       bl0 = fminf(bl0, __shfl_xor(bl0, o));
@@ -858,10 +900,15 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
       bh2 = fmaxf(bh2, WB[k][5]);
     }
   }
-  // 4 R_b^2 (with a margin for the FP32 boxes): tiles at least this far
-  // (squared gap) take the expanded form
-  const float far2 = 4.f * (fmaxf(bl0 * bl0, bh0 * bh0) + fmaxf(bl1 * bl1, bh1 * bh1) + fmaxf(bl2 * bl2, bh2 * bh2)) *
-                         1.001f + 1e-30f;
+  // R_b^2: squared distance from the origin to the farthest corner of the
+  // targets' box.  Tiles at least 2 R_b away (squared gap, with a margin
+  // for the FP32 boxes) take the expanded form; tiles nearer than R_b / 4
+  // take the (hi, lo) separation: beyond that |r - s| >= R_b / 4 and
+  // |r|, |s| - |r - s| <= R_b bound the hi-only separation's relative error
+  // by about 10 * 2^-24.
+  const float rb2 = fmaxf(bl0 * bl0, bh0 * bh0) + fmaxf(bl1 * bl1, bh1 * bh1) + fmaxf(bl2 * bl2, bh2 * bh2);
+  const float far2 = 4.f * rb2 * 1.001f + 1e-30f;
+  const float close2 = 0.0625f * rb2 * 1.001f + 1e-30f;
   float hx = 0.f, hy = 0.f, hz = 0.f, hv = 0.f, lx = 0.f, ly = 0.f, lz = 0.f, lv = 0.f;
   float best = INFINITY;
   int bidx = -1;
@@ -876,7 +923,8 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
     const float q0 = (float)sq[jt];
     bool nn_tile = NN;
     bool far_tile = false;
-    if ((NN || kFar) && tbox) {
+    bool close_tile = true;
+    if (tbox) {
       const double *b = tbox + 6 * (size_t)(jt / kThreads);
       const float g0 = fmaxf(0.f, fmaxf((float)(b[0] - c0) - bh0, bl0 - (float)(b[3] - c0)));
       const float g1 = fmaxf(0.f, fmaxf((float)(b[1] - c1) - bh1, bl1 - (float)(b[4] - c1)));
@@ -884,6 +932,7 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
       const float gap2 = fmaf(g0, g0, fmaf(g1, g1, g2 * g2));
       if (NN) nn_tile = gap2 <= nn_cut2;
       far_tile = kFar && !nn_tile && gap2 >= far2;
+      close_tile = gap2 < close2;
     }
     if (sym_tiles) {
       const bool np = NN && tiles_gap2(tbox, blockIdx.x, jt / kThreads) <= nn_cut2d;
@@ -895,8 +944,11 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
     if (tid < cnt) {
       const int j = jt + tid;
       qj = (float)sq[j];
-      const float s0 = (float)(sx[j] - c0), s1 = (float)(sy[j] - c1), s2 = (float)(sz[j] - c2);
+      const double f0 = sx[j] - c0, f1 = sy[j] - c1, f2 = sz[j] - c2;
+      const float s0 = (float)f0, s1 = (float)f1, s2 = (float)f2;
       S[tid] = make_float4(s0, s1, s2, qj);
+      if (close_tile)
+        SL[tid] = make_float4((float)(f0 - (double)s0), (float)(f1 - (double)s1), (float)(f2 - (double)s2), 0.f);
       if (kFar) S2[tid] = make_float4(s0, s1, s2, fmaf(s0, s0, fmaf(s1, s1, s2 * s2)));
       if (NN) K[tid] = species_s[j];
     }
@@ -904,30 +956,43 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
     // out of the inner loop: 12 instead of 13 VALU operations per pair
     const bool uniform = __syncthreads_and(qj == q0);
     float px = 0.f, py = 0.f, pz = 0.f, pv = 0.f;
+#define PAIR_TILE(NNT, FQ, HLT)                                                                                \
+  pair_tile<WANT_V, NNT, EXCL, FQ, HLT>(S, SL, RL, K, cnt, jt, r0, r1, r2, soft2, self, want, px, py, pz, pv, best, \
+                                        bidx)
     if (uniform) {
       if (nn_tile) {
-        pair_tile<WANT_V, NN, EXCL, true>(S, K, cnt, jt, r0, r1, r2, soft2, self, want, px, py, pz, pv, best, bidx);
+        if (close_tile)
+          PAIR_TILE(NN, true, true);
+        else
+          PAIR_TILE(NN, true, false);
       } else if (kFar && far_tile) {
         float sw = 0.f, sxx = 0.f, syy = 0.f, szz = 0.f;
         pair_tile_far(S2, cnt, m0, m1, m2, a_t, sw, sxx, syy, szz);
         px = fmaf(r0, sw, -sxx);
         py = fmaf(r1, sw, -syy);
         pz = fmaf(r2, sw, -szz);
+      } else if (close_tile) {
+        PAIR_TILE(false, true, true);
       } else {
-        pair_tile<WANT_V, false, EXCL, true>(S, K, cnt, jt, r0, r1, r2, soft2, self, want, px, py, pz, pv, best,
-                                             bidx);
+        PAIR_TILE(false, true, false);
       }
       px *= q0;
       py *= q0;
       pz *= q0;
       pv *= q0;
     } else {
-      if (nn_tile)
-        pair_tile<WANT_V, NN, EXCL, false>(S, K, cnt, jt, r0, r1, r2, soft2, self, want, px, py, pz, pv, best, bidx);
-      else
-        pair_tile<WANT_V, false, EXCL, false>(S, K, cnt, jt, r0, r1, r2, soft2, self, want, px, py, pz, pv, best,
-                                              bidx);
+      if (nn_tile) {
+        if (close_tile)
+          PAIR_TILE(NN, false, true);
+        else
+          PAIR_TILE(NN, false, false);
+      } else if (close_tile) {
+        PAIR_TILE(false, false, true);
+      } else {
+        PAIR_TILE(false, false, false);
+      }
     }
+#undef PAIR_TILE
     neumaier(hx, lx, px);
     neumaier(hy, ly, py);
     neumaier(hz, lz, pz);
@@ -972,8 +1037,8 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
 // over the wave's 64 x kSymTiles particles sits in one lane, in a fixed
 // order of additions, without atomics.  Per pair 14 VALU operations and one
 // reciprocal square root (3 sub, 3 FMA for d^2 + s^2, rsqrt, 2 mul for r^-3,
-// 3 + 3 FMA into the two sums) serve two interactions, plus 3 adds per
-// step.  Super-block pairs with one charge on each side take the charges out
+// 3 + 3 FMA into the two sums, the source's straight into its running
+// sum) serve two interactions.  Super-block pairs with one charge on each side take the charges out
 // of the loop; the others (mixed charges, partial super-blocks) carry both
 // charges per pair.  Tile pairs left to the directed kernel are masked
 // through their softening term, without a branch.
@@ -1069,7 +1134,8 @@ __global__ __launch_bounds__(kThreads, 4) void k_pair_sym(int n, const double *_
 #pragma unroll 4
         for (int m = 0; m < 64; ++m) {
           const float4 sj = sg[m];
-          float cx = 0.f, cy = 0.f, cz = 0.f;
+          // this lane's terms go straight into the running sum of the source
+          float cx = tx, cy = ty, cz = tz;
 #pragma unroll
           for (int k = 0; k < kSymTiles; ++k) {
             const float dx = r0[k] - sj.x, dy = r1[k] - sj.y, dz = r2[k] - sj.z;
@@ -1083,16 +1149,17 @@ __global__ __launch_bounds__(kThreads, 4) void k_pair_sym(int n, const double *_
             cy = fmaf(w, dy, cy);
             cz = fmaf(w, dz, cz);
           }
-          tx = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(tx + cx)));
-          ty = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(ty + cy)));
-          tz = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(tz + cz)));
+          tx = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(cx)));
+          ty = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(cy)));
+          tz = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(cz)));
         }
       } else {
         const float4 *sg = &S[g >> 6][lane];
 #pragma unroll 4
         for (int m = 0; m < 64; ++m) {
           const float4 sj = sg[m];
-          float cx = 0.f, cy = 0.f, cz = 0.f;
+          // this lane's terms go straight into the running sum of the source
+          float cx = tx, cy = ty, cz = tz;
 #pragma unroll
           for (int k = 0; k < kSymTiles; ++k) {
             const float dx = r0[k] - sj.x, dy = r1[k] - sj.y, dz = r2[k] - sj.z;
@@ -1107,9 +1174,9 @@ __global__ __launch_bounds__(kThreads, 4) void k_pair_sym(int n, const double *_
             cy = fmaf(wj, dy, cy);
             cz = fmaf(wj, dz, cz);
           }
-          tx = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(tx + cx)));
-          ty = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(ty + cy)));
-          tz = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(tz + cz)));
+          tx = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(cx)));
+          ty = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(cy)));
+          tz = __int_as_float(__builtin_amdgcn_ds_bpermute(nxt, __float_as_int(cz)));
         }
       }
       // after the 64th step and move the lane holds the full sum of source lane
@@ -1267,6 +1334,26 @@ __global__ __launch_bounds__(256) void k_pair_reduce(int n_t, int nsplit, const 
   }
 }
 
+// Terms of the tile pairs kept by the directed kernel (mask bits weighted
+// by the two tiles' particle counts), added to *work; profiling only.
+__global__ __launch_bounds__(256) void k_mask_work(int ntile, int wpr, int n, const uint32_t *__restrict__ mask,
+                                                   unsigned long long *work) {
+  const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+  unsigned long long w = 0;
+  if (t < (size_t)ntile * wpr) {
+    const int a = (int)(t / wpr), wd = (int)(t % wpr);
+    const unsigned long long ca = (unsigned long long)min(kThreads, n - a * kThreads);
+    uint32_t m = mask[t];
+    while (m) {
+      const int u = __builtin_ctz(m);
+      m &= m - 1;
+      const int b = wd * 32 + u;
+      w += ca * (unsigned long long)min(kThreads, n - b * kThreads);
+    }
+  }
+  if (w) atomicAdd(work, w);
+}
+
 template <bool WANT_V, bool NN, int CZ>
 static void launch_pair_t(obem_ctx *ctx, dim3 grid, int n_t, const double *xs, const int32_t *perm, int n_s,
                           const double *sx, const double *sy, const double *sz, const double *sq,
@@ -1333,6 +1420,15 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
   if (once) {
     obem_status st = pair_once_setup(ctx, n_t, kSymTiles, tbox, nn, nn_cut2d, &sb, &dmask, &dwpr);
     if (st) return st;
+    if (ctx->prof && ctx->work_dev) {
+      const int ntile = nblk(n_t);
+      const size_t nw = (size_t)ntile * dwpr;
+      hipLaunchKernelGGL(k_mask_work, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, ctx->stream, ntile, dwpr,
+                         n_t, dmask, ctx->work_dev);
+      ctx->work_once_n2 += (int64_t)n_t * n_t;
+    }
+  } else if (ctx->prof) {
+    ctx->work_directed += (int64_t)n_t * n_s;
   }
   {
   OBEM_PROF(ctx, "pair");

@@ -111,6 +111,11 @@ struct obem_ctx {
   obem::DevBuf ws[obem::WS_COUNT];
   void *rocblas = nullptr;   // rocblas_handle, created on first solve
   bool prof = false;         // per-kernel event timing
+  // pairwise work while profiling: device count of the directed kernel's
+  // terms of pair-once calls (filled from the tile-pair mask), host counts of
+  // the directed terms of the other calls and of the pair-once calls' n^2
+  unsigned long long *work_dev = nullptr;
+  int64_t work_directed = 0, work_once_n2 = 0;
   std::vector<obem_prof_rec> prof_recs;
   std::vector<hipEvent_t> prof_pool;
 };

@@ -3,10 +3,9 @@ precision, softened, no potential): every unordered pair of particles in
 different super-blocks of 2048 is evaluated once for both particles, using
 the antisymmetry of the softened pair term of eq. (nbody).
 
-Checked on sampled particles (and on the particles where the two differ
-most) against the oracle, side by side with the directed evaluation of the
-same call with the potential requested (which never takes the pair-once
-path), and for run-to-run bit equality.  The
+Checked at every particle against the oracle, side by side with the
+directed evaluation of the same call with the potential requested (which
+never takes the pair-once path), and for run-to-run bit equality.  The
 sizes are ragged (a last super-block of one particle, partial tiles, two
 launches of the slot loop), the charges mix both signs and zeros (the
 general form with both charges per pair) and one sign only (charges out of
@@ -41,8 +40,8 @@ def _cloud(n, seed, kind):
     return x, q
 
 
-@pytest.mark.parametrize("n,kind", [(4097, "electrons"), (20011, "both"), (20011, "with_zeros"),
-                                    (70001, "both")])
+@pytest.mark.parametrize("n,kind", [(4097, "electrons"), (4097, "both"), (20011, "both"), (20011, "with_zeros"),
+                                    (70001, "both"), (70001, "electrons")])
 def test_pair_once_against_directed_and_oracle(ctx, orc, n, kind):
     x, q = _cloud(n, 40 + n % 97, kind)
     X, Q = dev(x), dev(q)
@@ -51,28 +50,23 @@ def test_pair_once_against_directed_and_oracle(ctx, orc, n, kind):
     Ed, _ = B.field_eval(ctx, None, None, X, Q, X, 1e-7, B.OBEM_MIXED, tgt_is_src=True, want_v=True)
     Ed = host(Ed)
     assert np.array_equal(E1, E1b)
-    rms = np.sqrt(np.mean(np.sum(Ed ** 2, axis=1)))
-    dmax = np.abs(E1 - Ed).max() / rms
+    # the contract's metric: relative L2 over every particle
+    ref = orc.pair_field(x, x, q, 1e-7, tgt_is_src=True)
+    rms = np.sqrt(np.mean(np.sum(ref ** 2, axis=1)))
+    err_o = rel_l2(E1, ref)
+    err_do = rel_l2(Ed, ref)
     err_d = rel_l2(E1, Ed)
-    # sampled particles plus the ones where the two evaluations differ most
-    worst = np.argsort(np.abs(E1 - Ed).max(axis=1))[-8:]
-    rows = np.unique(np.concatenate([np.random.default_rng(n).choice(n, 600, replace=False), worst]))
-    ref = orc.pair_field(x[rows], x, q, 1e-7)
-    err_o = rel_l2(E1[rows], ref)
-    err_do = rel_l2(Ed[rows], ref)
-    wi = np.searchsorted(rows, worst)
-    e_w1 = np.abs(E1[worst] - ref[wi]).max(axis=1) / rms
-    e_wd = np.abs(Ed[worst] - ref[wi]).max(axis=1) / rms
-    print(f"pair-once n={n} {kind}: vs directed rel L2 {err_d:.3g} max/rms {dmax:.3g}; vs oracle {err_o:.3g} "
-          f"(directed {err_do:.3g}); worst points vs oracle / rms: pair-once {e_w1.max():.3g}, directed {e_wd.max():.3g}")
-    # The two evaluations round differently; each is held to the oracle.  A
-    # cloud of both signs without cells is nearly neutral: its field is a
-    # small difference of large sums, so both FP32 paths sit near 1e-5
-    # there; the pair-once path must be no less accurate than the directed.
-    assert err_o <= 1.25 * err_do + 1e-7
-    assert e_w1.max() <= 1.5 * max(e_wd.max(), 1e-6)
-    assert err_o <= (1e-5 if kind == "electrons" else 3e-5)
-    assert err_d <= 2.0 * err_do + 1e-7
+    e_w1 = np.abs(E1 - ref).max() / rms
+    e_wd = np.abs(Ed - ref).max() / rms
+    print(f"pair-once n={n} {kind}: vs oracle rel L2 {err_o:.3g} (directed {err_do:.3g}), vs directed {err_d:.3g}; "
+          f"worst component error / rms: pair-once {e_w1:.3g}, directed {e_wd:.3g}")
+    # A cloud of both signs is nearly neutral and its field is dominated by
+    # the few closest pairs; those go through the directed kernel's exact
+    # (hi, lo) separation, so both paths meet the mixed-precision bound on
+    # every kind of cloud.
+    assert err_o <= 1e-5
+    assert err_do <= 1e-5
+    assert e_w1 <= 2e-5 and e_wd <= 2e-5
 
 
 @pytest.mark.parametrize("n,kind", [(4097, "electrons"), (8000, "both"), (9001, "both"), (9001, "with_zeros")])
