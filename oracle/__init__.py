@@ -38,12 +38,25 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_sanitized(out_path: str) -> str:
+    """Compile oracle.c with AddressSanitizer and UndefinedBehaviorSanitizer
+    (any report aborts) into out_path, for the sanitizer test."""
+    cmd = ["gcc", "-std=gnu11", "-O1", "-g", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", _SRC, "-o",
+           out_path, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out_path
+
+
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        _lib = C.CDLL(_LIB)
+        path = os.environ.get("OBEM_ORACLE_LIB")     # a sanitizer build (tests only)
+        if path is None:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+        _lib = C.CDLL(path)
     return _lib
 
 
