@@ -213,6 +213,28 @@ obem_status field_eval(obem_ctx *ctx, const obem_meshh *mesh, const double *sigm
                        obem_precision precision, unsigned flags, double *Ex, double *Ey, double *Ez,
                        double *V);
 
+/* field_eval without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and error behaviour as
+ * field_eval, but at most OBEM_NOALLOC_MAX_POINTS targets and sources
+ * (larger counts: OBEM_EINVAL before any launch), and the workspace comes
+ * from one static device array of OBEM_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each device it runs on until the process ends; no
+ * hipMalloc, hipFree or allocating library call is made (OBEM_ENOMEM with a
+ * message if a call ever needed more than the array).  Every call on one
+ * device shares that device's array: calls that overlap on one GPU (other
+ * contexts, other streams, other host threads) race and must be ordered by
+ * the caller.  The kernels write every workspace entry they read, so the
+ * array's contents left by an earlier call do not matter.  Kernel timing is
+ * off during the call. */
+#define OBEM_NOALLOC_MAX_POINTS 16384
+#define OBEM_NOALLOC_SCRATCH_BYTES (80ull << 20)
+obem_status field_eval_noalloc(obem_ctx *ctx, const obem_meshh *mesh, const double *sigma, int64_t n_src,
+                               const double *sx, const double *sy, const double *sz, const double *sq,
+                               int64_t n_tgt, const double *tx, const double *ty, const double *tz, double soft,
+                               obem_precision precision, unsigned flags, double *Ex, double *Ey, double *Ez,
+                               double *V);
+
 /* Adjoint of field_eval for L = sum_t gE_t . E(x_t) (not in the paper):
  *   g_sigma_k = k_e sum_t gE_t . int_{C_k} (x_t - r')/|x_t - r'|^3 dS'
  *   g_t       = (dE(x_t)/dx_t)^T gE_t        (cells and point charges)

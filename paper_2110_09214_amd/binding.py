@@ -78,7 +78,7 @@ class StepStats_t(C.Structure):
 SYMBOLS = ["obem_create", "obem_destroy", "obem_last_error", "obem_constants", "obem_profile_enable",
            "obem_profile_read", "obem_profile_work", "obem_mesh_bind",
            "obem_mesh_release", "obem_mesh_geometry", "bem_solve_charges", "bem_solve_charges_adjoint", "bem_influence",
-           "field_eval", "field_eval_backward", "field_map_build", "field_map_eval", "induced_current", "track_step"]
+           "field_eval", "field_eval_noalloc", "field_eval_backward", "field_map_build", "field_map_eval", "induced_current", "track_step"]
 
 _lib = None
 
@@ -111,6 +111,7 @@ def load(path: str = LIB_PATH):
     lib.field_map_eval.argtypes = [vp, C.POINTER(FieldMap_t), i64, vp, vp, vp, vp, vp, vp]
     lib.induced_current.argtypes = [vp, vp, vp, C.POINTER(FieldMap_t), i64, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp]
     lib.field_eval.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, d, i32, C.c_uint, vp, vp, vp, vp]
+    lib.field_eval_noalloc.argtypes = lib.field_eval.argtypes
     lib.field_eval_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, d, i32, C.c_uint,
                                         vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.track_step.argtypes = [vp, vp, C.POINTER(Particles_t), C.POINTER(Gas_t), C.POINTER(StepParams_t), vp, vp,
@@ -296,6 +297,28 @@ def field_eval(ctx: Context, mesh, sigma, xs, q, xt, soft, precision=OBEM_MIXED,
                                  _ptr(sigma) if mesh is not None else None, n_s, *[_ptr(t) for t in sx],
                                  _ptr(q) if n_s else None, n_t, *[_ptr(t) for t in tx], float(soft), int(precision),
                                  flags, *[_ptr(t) for t in E], _ptr(V)))
+    Et = torch.stack(E, 1)
+    return (Et, V) if want_v else Et
+
+
+def field_eval_noalloc(ctx: Context, mesh, sigma, xs, q, xt, soft, precision=OBEM_MIXED, tgt_is_src=False,
+                       want_v=False, out=None):
+    """field_eval through the allocation-free entry point (at most
+    OBEM_NOALLOC_MAX_POINTS targets and sources; the library's workspace comes
+    from its static scratch array).  Pass `out` (three n_t device tensors) for
+    a call that allocates nothing on the Python side either."""
+    n_t = int(xt.shape[0])
+    n_s = 0 if xs is None else int(xs.shape[0])
+    tx = _soa(xt)
+    sx = _soa(xs) if n_s else [None] * 3
+    dev = xt.device
+    E = [torch.empty(n_t, dtype=torch.float64, device=dev) for _ in range(3)] if out is None else out
+    V = torch.empty(n_t, dtype=torch.float64, device=dev) if want_v else None
+    flags = (OBEM_TGT_IS_SRC if tgt_is_src else 0) | (OBEM_WANT_V if want_v else 0)
+    ctx.check(ctx.lib.field_eval_noalloc(ctx.h, mesh.h if mesh is not None else None,
+                                         _ptr(sigma) if mesh is not None else None, n_s, *[_ptr(t) for t in sx],
+                                         _ptr(q) if n_s else None, n_t, *[_ptr(t) for t in tx], float(soft),
+                                         int(precision), flags, *[_ptr(t) for t in E], _ptr(V)))
     Et = torch.stack(E, 1)
     return (Et, V) if want_v else Et
 

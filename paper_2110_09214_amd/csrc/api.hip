@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "cellmath.hpp"
@@ -35,8 +36,24 @@ obem_status hip_fail(obem_ctx *ctx, hipError_t e, const char *what, int line) {
 
 void *ws_get(obem_ctx *ctx, int slot, size_t bytes) {
   if (slot < 0 || slot >= WS_COUNT) return nullptr;
-  DevBuf &b = ctx->ws[slot];
   if (bytes == 0) bytes = 1;
+  if (ctx->arena) {
+    // allocation-free call: slices of the scratch array, one per slot (a
+    // slot asked for again gets its slice back if it is large enough, as a
+    // grow-only buffer would be)
+    if (ctx->arena_slot_bytes[slot] >= bytes) return ctx->arena_slot[slot];
+    const size_t want = (bytes + 255) / 256 * 256;
+    if (want > ctx->arena_bytes - ctx->arena_used) {
+      ctx->arena_overflow = true;
+      return nullptr;
+    }
+    void *p = ctx->arena + ctx->arena_used;
+    ctx->arena_used += want;
+    ctx->arena_slot[slot] = p;
+    ctx->arena_slot_bytes[slot] = want;
+    return p;
+  }
+  DevBuf &b = ctx->ws[slot];
   if (b.bytes >= bytes) return b.p;
   if (b.p) {
     // the buffer may still be in use by queued work on the context stream
@@ -204,6 +221,40 @@ void obem_constants(double *out) {
   out[5] = kAmu;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch array of the allocation-free entry point (field_eval_noalloc)
+// ---------------------------------------------------------------------------
+// Each device the library runs on holds its own copy for the life of the
+// process.  In host code the name is only a stand-in for the symbol: kernels
+// and copies get the device address taken with hipGetSymbolAddress, once per
+// device, kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[OBEM_NOALLOC_SCRATCH_BYTES];
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[kScratchDevices] = {};
+
+static obem_status scratch_setup(obem_ctx *c) {
+  if (c->device >= kScratchDevices) return OBEM_OK;  // field_eval_noalloc then reports the missing scratch
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[c->device]) {
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(c->device) != hipSuccess) {
+      (void)hipGetLastError();
+      return OBEM_EDEVICE;
+    }
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return OBEM_EDEVICE;
+    }
+    g_scratch_ptr[c->device] = (char *)p;
+  }
+  c->scratch = g_scratch_ptr[c->device];
+  return OBEM_OK;
+}
+
 obem_status obem_create(obem_ctx **out, int device, void *hip_stream) {
   if (!out) return OBEM_EINVAL;
   *out = nullptr;
@@ -221,6 +272,10 @@ obem_status obem_create(obem_ctx **out, int device, void *hip_stream) {
   obem_ctx *c = new obem_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
+  if (scratch_setup(c) != OBEM_OK) {
+    delete c;
+    return OBEM_EDEVICE;
+  }
   *out = c;
   return OBEM_OK;
 }
@@ -450,11 +505,11 @@ obem_status obem_mesh_geometry(obem_ctx *ctx, const obem_meshh *m, double *area,
   return OBEM_OK;
 }
 
-obem_status field_eval(obem_ctx *ctx, const obem_meshh *mesh, const double *sigma, int64_t n_src,
-                       const double *sx, const double *sy, const double *sz, const double *sq, int64_t n_tgt,
-                       const double *tx, const double *ty, const double *tz, double soft,
-                       obem_precision precision, unsigned flags, double *Ex, double *Ey, double *Ez, double *V) {
-  CHECK_CTX(ctx);
+static obem_status field_eval_impl(obem_ctx *ctx, const obem_meshh *mesh, const double *sigma, int64_t n_src,
+                                   const double *sx, const double *sy, const double *sz, const double *sq,
+                                   int64_t n_tgt, const double *tx, const double *ty, const double *tz,
+                                   double soft, obem_precision precision, unsigned flags, double *Ex, double *Ey,
+                                   double *Ez, double *V) {
   if (n_tgt < 0 || n_tgt >= kMaxCount || n_src < 0 || n_src >= kMaxCount)
     return fail(ctx, OBEM_EINVAL, "n_tgt/n_src out of range");
   if (!(soft >= 0.0) || !std::isfinite(soft)) return fail(ctx, OBEM_EINVAL, "soft must be finite and >= 0");
@@ -511,6 +566,46 @@ obem_status field_eval(obem_ctx *ctx, const obem_meshh *mesh, const double *sigm
     if (st) return st;
   }
   return launch_scatter(ctx, to, acc, kKe, Ex, Ey, Ez, want_v ? V : nullptr);
+}
+
+obem_status field_eval(obem_ctx *ctx, const obem_meshh *mesh, const double *sigma, int64_t n_src,
+                       const double *sx, const double *sy, const double *sz, const double *sq, int64_t n_tgt,
+                       const double *tx, const double *ty, const double *tz, double soft,
+                       obem_precision precision, unsigned flags, double *Ex, double *Ey, double *Ez, double *V) {
+  CHECK_CTX(ctx);
+  return field_eval_impl(ctx, mesh, sigma, n_src, sx, sy, sz, sq, n_tgt, tx, ty, tz, soft, precision, flags, Ex,
+                         Ey, Ez, V);
+}
+
+obem_status field_eval_noalloc(obem_ctx *ctx, const obem_meshh *mesh, const double *sigma, int64_t n_src,
+                               const double *sx, const double *sy, const double *sz, const double *sq,
+                               int64_t n_tgt, const double *tx, const double *ty, const double *tz, double soft,
+                               obem_precision precision, unsigned flags, double *Ex, double *Ey, double *Ez,
+                               double *V) {
+  CHECK_CTX(ctx);
+  if (n_tgt < 0 || n_src < 0 || n_tgt > OBEM_NOALLOC_MAX_POINTS || n_src > OBEM_NOALLOC_MAX_POINTS)
+    return fail(ctx, OBEM_EINVAL, "field_eval_noalloc: n_tgt and n_src must lie in [0, %d] (got %lld, %lld)",
+                OBEM_NOALLOC_MAX_POINTS, (long long)n_tgt, (long long)n_src);
+  if (!ctx->scratch) return fail(ctx, OBEM_EDEVICE, "field_eval_noalloc: no scratch array on device %d", ctx->device);
+  // workspace from the scratch array; no event timing (its events are created on demand)
+  ctx->arena = ctx->scratch;
+  ctx->arena_bytes = OBEM_NOALLOC_SCRATCH_BYTES;
+  ctx->arena_used = 0;
+  ctx->arena_overflow = false;
+  for (int k = 0; k < WS_COUNT; ++k) {
+    ctx->arena_slot[k] = nullptr;
+    ctx->arena_slot_bytes[k] = 0;
+  }
+  const bool prof = ctx->prof;
+  ctx->prof = false;
+  obem_status st = field_eval_impl(ctx, mesh, sigma, n_src, sx, sy, sz, sq, n_tgt, tx, ty, tz, soft, precision,
+                                   flags, Ex, Ey, Ez, V);
+  ctx->prof = prof;
+  ctx->arena = nullptr;
+  if (st == OBEM_ENOMEM && ctx->arena_overflow)
+    st = fail(ctx, OBEM_ENOMEM, "field_eval_noalloc: the call needs more than the %llu-byte scratch array",
+              (unsigned long long)OBEM_NOALLOC_SCRATCH_BYTES);
+  return st;
 }
 
 }  // extern "C"

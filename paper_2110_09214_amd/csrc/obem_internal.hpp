@@ -116,6 +116,15 @@ struct obem_ctx {
   // the directed terms of the other calls and of the pair-once calls' n^2
   unsigned long long *work_dev = nullptr;
   int64_t work_directed = 0, work_once_n2 = 0;
+  // the device address of the library's static scratch array on this
+  // context's device, and while an allocation-free call runs, the arena that
+  // ws_get carves the workspace slots from instead of allocating
+  char *scratch = nullptr;
+  char *arena = nullptr;
+  size_t arena_bytes = 0, arena_used = 0;
+  bool arena_overflow = false;
+  void *arena_slot[obem::WS_COUNT] = {};
+  size_t arena_slot_bytes[obem::WS_COUNT] = {};
   std::vector<obem_prof_rec> prof_recs;
   std::vector<hipEvent_t> prof_pool;
 };
