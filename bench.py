@@ -20,8 +20,10 @@ copy inside the timed region), so each step does the same work.  `value` is
 step (re-solve + field, no transport), the influence of the 4M charges on the
 40,776 cell equations, the GEM cell with 1M field points in mixed precision
 and in FP64 (interactions/s each, and the relative L2 difference between the
-two), and the adjoint's backward/forward time ratio on 1M charges with the
-refined (49,128-cell) mesh.
+two), the double-GEM tracking run (1000 steps from 200k electrons released
+in the holes of the upper foil, with its population, event totals and the
+final dL/dsigma), and the adjoint's backward/forward time ratio on 1M
+charges with the refined (49,128-cell) mesh.
 
 `roofline` is for the dominant work, the pairwise sum: per step one launch of
 the directed kernel (tile pairs inside a super-block or near each other) and
@@ -90,9 +92,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true",
-                    help="run one plain 1 GiB device copy and one tracking step of the 4M-charge cloud without "
-                         "cells (the same pairwise kernel as the timed step; for rocprofv3 --pmc FETCH_SIZE / "
-                         "WRITE_SIZE runs), print the sizes and exit")
+                    help="run one plain 1 GiB device copy, one 1 GiB read-only sum and one tracking step of the "
+                         "4M-charge cloud without cells (the same pairwise kernel as the timed step; for "
+                         "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs), print the sizes and exit")
+    ap.add_argument("--pmc-probe-cells", action="store_true",
+                    help="run one 1 GiB device copy and the mixed cell field of the 40,776-cell GEM mesh at the "
+                         "4M charges of the cloud (the cell kernels of the timed step, cell charges from a "
+                         "smooth synthetic density), print the sizes and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the pairwise sum would shard by "
@@ -126,6 +132,8 @@ def main():
         torch.cuda.synchronize()
         b.copy_(a)                                     # reads and writes 1 GiB each
         torch.cuda.synchronize()
+        float(b.sum())                                 # reads 1 GiB (a second calibration of FETCH_SIZE)
+        torch.cuda.synchronize()
         x, q, sp = W.space_charge_cloud()
         gas_s, gas_keep = B.gas_struct(W.synthetic_ar_co2(), "cuda")
         parts = B.Particles(len(q) + len(q) // 4, "cuda", dev(x), dev(np.zeros_like(x)), dev(sp, torch.int8),
@@ -140,6 +148,27 @@ def main():
         return
 
     work = {}
+
+    if args.pmc_probe_cells:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        mesh = W.gem_cell_mesh()
+        x, q, sp = W.space_charge_cloud()
+        bm = bind(ctx, mesh)
+        c = (mesh.a + mesh.b + mesh.c) / 3
+        sig = dev(1e-6 * np.sin(c @ np.array([3e4, 2e4, 1e4])))
+        E = B.field_eval(ctx, bm, sig, None, None, dev(x), 0.0, B.OBEM_MIXED)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "n_points": len(q),
+                          "n_cells": mesh.n, "E_rms": float(E.pow(2).sum(1).mean().sqrt()),
+                          "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
+        ctx.close()
+        return
 
     def timed(fn, steps, warmup):
         for _ in range(warmup):
@@ -350,13 +379,14 @@ def main():
         log(f"[bench] gem cell: mixed {extra['gem_cell_mixed_interactions_per_s']:.3e}/s, "
             f"fp64 {extra['gem_cell_fp64_interactions_per_s']:.3e}/s, rel L2 {float(d):.2e}")
         del outs, pts
-        # double-GEM run: 200k electron-cation pairs at the central hole of the
-        # upper foil, 60,752 cells, charging-up re-solve every step; then the
+        # double-GEM run (the tracking configuration): 200k electrons released
+        # at rest in the holes of the upper foil, 60,752 cells, 1000 steps of
+        # 1 ps with the charging-up re-solve every step, capacity 2M; then the
         # final-step backward dL/dsigma of L = sum w . E(x)
         geo5 = W.GemGeometry(m=10, n_r=5, n_cone=6)
         top5 = geo5.t_kapton / 2 + geo5.t_cu
         m5 = W.double_gem_mesh(geo5)
-        x5, sp5 = W.double_gem_initial(geo=geo5)
+        x5, sp5 = W.double_gem_avalanche_start(geo=geo5)
         n5 = len(sp5)
         bm5 = bind(ctx, m5)
         rhs5 = dev(m5.rhs)
@@ -371,53 +401,51 @@ def main():
                   box_lo=(-geo5.half_x, -geo5.half_y, -2e-3 - top5 - 2e-3),
                   box_hi=(geo5.half_x, geo5.half_y, top5 + 3e-3), soft=1e-7, r_rec=1e-6,
                   precision=B.OBEM_MIXED, resolve=1)
-        inter5 = []
+        steps5 = 1000
+        tot5 = dict(children=0, recombined=0, absorbed=0, left_world=0, dd_charge_deposited=0, ionisations=0,
+                    attachments=0, children_dropped=0)
+        live5, inter5 = [], []
 
         def step5():
             nl = parts5.n_live
-            B.track_step(ctx, bm5, parts5, gas_s, p5, counts5, sig5, rhs5)
+            st = B.track_step(ctx, bm5, parts5, gas_s, p5, counts5, sig5, rhs5)
             p5["step"] += 1
             inter5.append(nl * (nl - 1) + nl * m5.n)
+            for k in ("children", "recombined", "absorbed", "left_world", "dd_charge_deposited", "children_dropped"):
+                tot5[k] += st[k]
+            tot5["ionisations"] += st["real_collisions"][3]
+            tot5["attachments"] += st["real_collisions"][4]
+            if p5["step"] % 50 == 0:
+                live5.append(parts5.n_live)
 
-        ms5, prof5 = timed(step5, 10, 1)
-        rate5 = sum(inter5[-10:]) / (10 * ms5 / 1e3)
-        X5 = torch.stack([c[:parts5.n_live] for c in parts5.cols[:3]], 1).contiguous()
-        Q5 = torch.full((parts5.n_live,), -W.E_CHARGE, dtype=torch.float64, device="cuda")
-        Q5[parts5.species[:parts5.n_live] == 1] = W.E_CHARGE
-        W5 = dev(np.random.default_rng(6).normal(size=(parts5.n_live, 3)))
+        ms5, prof5 = timed(step5, steps5, 0)
+        rate5 = sum(inter5) / (steps5 * ms5 / 1e3)
+        nl5 = parts5.n_live
+        X5 = torch.stack([c[:nl5] for c in parts5.cols[:3]], 1).contiguous()
+        Q5 = torch.full((nl5,), -W.E_CHARGE, dtype=torch.float64, device="cuda")
+        Q5[parts5.species[:nl5] == 1] = W.E_CHARGE
+        W5 = dev(np.random.default_rng(6).normal(size=(nl5, 3)))
 
         def bwd5():
             B.field_eval_backward(ctx, bm5, sig5, X5, Q5, X5, 1e-7, W5, B.OBEM_MIXED, tgt_is_src=True,
                                   want_t=False, want_s=False)
 
         ms5b, _ = timed(bwd5, 1, 1)
-        # the same run with resolve = 2: the re-solve is skipped on steps whose
-        # right-hand side is unchanged (no new charge on the dielectric)
-        parts5b = B.Particles(2_000_000, "cuda", dev(x5), dev(np.zeros_like(x5)), dev(sp5, torch.int8),
-                              torch.arange(n5, dtype=torch.int64, device="cuda"), n5)
-        counts5b = torch.zeros(m5.n, dtype=torch.int64, device="cuda")
-        sig5b = sig5.clone()
-        p5b = dict(p5, step=0, resolve=2)
-
-        def step5b():
-            B.track_step(ctx, bm5, parts5b, gas_s, p5b, counts5b, sig5b, rhs5)
-            p5b["step"] += 1
-
-        ms5c, _ = timed(step5b, 10, 1)
-        del parts5b
+        extra["double_gem_steps"] = steps5
         extra["double_gem_step_ms"] = ms5
-        extra["double_gem_step_ms_resolve_on_change"] = ms5c
-        extra["double_gem_kernel_ms_per_step"] = {k: v[0] / 10 for k, v in prof5.items()}
+        extra["double_gem_kernel_ms_per_step"] = {k: v[0] / steps5 for k, v in prof5.items()}
         extra["double_gem_interactions_per_s"] = rate5
-        extra["double_gem_n_live_after"] = parts5.n_live
-        extra["double_gem_dd_charges"] = int(counts5.abs().sum())
+        extra["double_gem_interactions_total"] = int(sum(inter5))
+        extra["double_gem_n_live_every_50_steps"] = live5
+        extra["double_gem_totals"] = dict(tot5, dd_charges_on_cells=int(counts5.abs().sum()))
         extra["double_gem_final_backward_ms"] = ms5b
-        extra["double_gem_workload"] = (f"{n5} charges (electron-cation pairs at the central hole of the upper "
-                                        f"foil) + {m5.n} cells, charging-up re-solve each step, mixed; 10 steps "
-                                        f"after 1, setup (assembly + LU + inverse) {t_setup5:.1f} s; then "
-                                        f"dL/dsigma of L = sum w.E")
-        log(f"[bench] double GEM: {ms5:.1f} ms per step, {rate5:.3e} interactions/s, n_live {parts5.n_live}, "
-            f"backward {ms5b:.1f} ms; {ms5c:.1f} ms per step re-solving only on a changed right-hand side")
+        extra["double_gem_workload"] = (f"{n5} electrons released at rest in the holes of the upper foil, "
+                                        f"{m5.n} cells, {steps5} steps of 1 ps, charging-up re-solve every "
+                                        f"step, recombination within 1 um, capacity 2M, mixed; setup (assembly "
+                                        f"+ LU + inverse) {t_setup5:.1f} s; then dL/dsigma of L = sum w.E at "
+                                        f"the {nl5} final charges")
+        log(f"[bench] double GEM: {steps5} steps, {ms5:.1f} ms per step, {rate5:.3e} interactions/s, n_live "
+            f"{n5} -> {nl5}, totals {tot5}, backward {ms5b:.1f} ms")
         del bm5, parts5, X5, Q5, W5
         # adjoint bwd/fwd on 1M charges + refined mesh (synthetic cell charges)
         m4 = W.gem_cell_mesh(W.gem_cell_refined_geometry())

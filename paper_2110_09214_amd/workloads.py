@@ -395,6 +395,26 @@ def double_gem_initial(n_pairs=200_000, seed=4, geo: GemGeometry | None = None, 
     return x, sp
 
 
+def double_gem_avalanche_start(n_e=200_000, seed=4, geo: GemGeometry | None = None, margin=0.9):
+    """Initial population of the double-GEM tracking run: n_e electrons at
+    rest inside the 9 holes of the upper foil (the electrons an avalanche
+    starts from), no ions.  Per electron: a hole (uniform), a height z
+    uniform over the foil (copper and kapton), a point uniform over the disk
+    of `margin` times the hole radius at that height (biconical in the
+    kapton, r_outer in the copper).  Returns positions, species."""
+    geo = geo or GemGeometry(m=10, n_r=5, n_cone=6)
+    tk, tc = geo.t_kapton / 2, geo.t_cu
+    rng = np.random.default_rng(seed)
+    cen = np.array(geo.hole_centres())
+    h = rng.integers(0, len(cen), n_e)
+    z = rng.uniform(-(tk + tc), tk + tc, n_e)
+    r_hole = np.where(np.abs(z) < tk, geo.r_inner + (geo.r_outer - geo.r_inner) * np.abs(z) / tk, geo.r_outer)
+    r = margin * r_hole * np.sqrt(rng.uniform(size=n_e))
+    t = rng.uniform(0.0, 2 * math.pi, n_e)
+    x = np.stack([cen[h, 0] + r * np.cos(t), cen[h, 1] + r * np.sin(t), z], axis=1)
+    return x, np.full(n_e, SPECIES_ELECTRON, np.int8)
+
+
 # --------------------------------------------------------------------------
 # Test fixtures
 # --------------------------------------------------------------------------
