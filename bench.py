@@ -359,6 +359,44 @@ def main():
         extra["influence_ms"] = ms_i
         extra["influence_interactions_per_s"] = n * N / (ms_i / 1e3)
         log(f"[bench] field-only step {ms_f:.1f} ms; influence of {n} charges on {N} cells {ms_i:.1f} ms")
+        # parallel-plate counter: 4096 cells (FP64 solve), the field at the
+        # 4096 electrons from all cells and the other electrons, FP64 and mixed
+        m1 = W.parallel_plate_mesh()
+        x1, q1 = W.parallel_plate_electrons()
+        bm1 = bind(ctx, m1)
+        sig1, _ = B.bem_solve_charges(ctx, bm1, dev(m1.rhs))
+        X1, Q1 = dev(x1), dev(q1)
+        n1 = len(q1)
+        inter1 = n1 * m1.n + n1 * (n1 - 1)
+        outs1 = {}
+        for name, prec in (("fp64", B.OBEM_FP64), ("mixed", B.OBEM_MIXED)):
+            res = {}
+
+            def fe1(prec=prec, res=res):
+                res["E"] = B.field_eval(ctx, bm1, sig1, X1, Q1, X1, 1e-7, prec, tgt_is_src=True)
+
+            ms1, _ = timed(fe1, 5, 2)
+            outs1[name] = res["E"]
+            extra[f"parallel_plate_{name}_interactions_per_s"] = inter1 / (ms1 / 1e3)
+            extra[f"parallel_plate_{name}_ms"] = ms1
+        extra["parallel_plate_mixed_vs_fp64_rel_l2"] = float((outs1["mixed"] - outs1["fp64"]).norm() /
+                                                             outs1["fp64"].norm())
+        if not args.no_cpu_baseline:
+            import oracle
+
+            s1 = sig1.cpu().numpy()
+            t0 = time.time()
+            ref1 = oracle.panel_field(x1, m1.a, m1.b, m1.c, s1) + oracle.pair_field(x1, x1, q1, 1e-7, tgt_is_src=True)
+            t1 = time.time() - t0
+            extra["parallel_plate_oracle_interactions_per_s"] = inter1 / t1
+            extra["parallel_plate_fp64_vs_oracle_rel_l2"] = float(np.linalg.norm(outs1["fp64"].cpu().numpy() - ref1) /
+                                                                  np.linalg.norm(ref1))
+            extra["parallel_plate_mixed_vs_oracle_rel_l2"] = float(np.linalg.norm(outs1["mixed"].cpu().numpy() - ref1) /
+                                                                   np.linalg.norm(ref1))
+        extra["parallel_plate_workload"] = f"{n1} electrons x ({m1.n} cells + {n1 - 1} other electrons), FP64 solve"
+        log(f"[bench] parallel plate: fp64 {extra['parallel_plate_fp64_interactions_per_s']:.3e}/s, mixed "
+            f"{extra['parallel_plate_mixed_interactions_per_s']:.3e}/s")
+        del bm1, outs1
         # GEM cell, 1M field points: mixed vs FP64
         pts = dev(W.gem_cell_points())
         npts = int(pts.shape[0])

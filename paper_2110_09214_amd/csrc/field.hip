@@ -867,6 +867,13 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
   const float a_t = fmaf(r0, r0, fmaf(r1, r1, fmaf(r2, r2, soft2)));
   int want = -2;
   if (NN && active) want = want_key(species[perm[i]]);
+  // which partner species any target of the workgroup looks for (the step's
+  // source charges follow their species: cations +e, electrons and anions -e)
+  bool want_pos = false, want_neg = false;
+  if (NN) {
+    want_pos = __syncthreads_or(want == 1);
+    want_neg = __syncthreads_or(want == 0);
+  }
   const int self = active ? (self_map ? self_map[perm[i]] : perm[i]) : -1;
   const int jb = blockIdx.y * chunk;
   const int je = min(n_s, jb + chunk);
@@ -956,6 +963,9 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
     // tiles of equal charges (sources grouped by species) take the charge
     // out of the inner loop: 12 instead of 13 VALU operations per pair
     const bool uniform = __syncthreads_and(qj == q0);
+    // a tile of one charge sign holds no species any target looks for: no
+    // partner search there
+    if (NN && nn_tile && uniform && ((q0 > 0.f && !want_pos) || (q0 < 0.f && !want_neg))) nn_tile = false;
     float px = 0.f, py = 0.f, pz = 0.f, pv = 0.f;
 #define PAIR_TILE(NNT, FQ, HLT)                                                                                \
   pair_tile<WANT_V, NNT, EXCL, FQ, HLT>(S, SL, RL, K, cnt, jt, r0, r1, r2, soft2, self, want, px, py, pz, pv, best, \
