@@ -413,6 +413,21 @@ def main():
             extra[f"gem_cell_{name}_ms"] = ms_g
         d = (outs["mixed"] - outs["fp64"]).norm() / outs["fp64"].norm()
         extra["gem_cell_mixed_vs_fp64_rel_l2"] = float(d)
+        if not args.no_cpu_baseline:
+            import oracle
+
+            ig = np.random.default_rng(13).choice(npts, 256, replace=False)
+            ig_t = torch.as_tensor(ig, device="cuda")
+            pts_h = pts[ig_t].cpu().numpy()
+            t0 = time.time()
+            refg = oracle.panel_field(pts_h, mesh.a, mesh.b, mesh.c, sigma.cpu().numpy())
+            tg = time.time() - t0
+            extra["gem_cell_oracle_interactions_per_s"] = len(ig) * N / tg
+            for name in ("mixed", "fp64"):
+                eg = outs[name][ig_t].cpu().numpy()
+                extra[f"gem_cell_{name}_vs_oracle_rel_l2_on_sample"] = float(np.linalg.norm(eg - refg) /
+                                                                             np.linalg.norm(refg))
+            extra["gem_cell_oracle_sample"] = f"{len(ig)} of the {npts} points against all {N} cells ({tg:.1f}s)"
         extra["gem_cell_workload"] = f"{npts} field points x {N} cells, cell charges from the FP64 solve"
         log(f"[bench] gem cell: mixed {extra['gem_cell_mixed_interactions_per_s']:.3e}/s, "
             f"fp64 {extra['gem_cell_fp64_interactions_per_s']:.3e}/s, rel L2 {float(d):.2e}")

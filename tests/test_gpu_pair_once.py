@@ -88,3 +88,24 @@ def test_pair_once_adjoint_against_oracle(ctx, orc, n, kind):
     err = rel_l2(gt, g_ref)
     print(f"pair-once adjoint n={n} {kind}: rel L2 vs oracle {err:.3g}")
     assert err <= 1e-4
+
+
+def test_profile_work_counts_cover_every_pair(ctx):
+    """obem_profile_work: the directed kernel's terms (the zero self terms
+    included) plus two per pair-once evaluation cover the n^2 ordered terms
+    exactly; without the pair-once evaluation every term is directed."""
+    n = 20011
+    x, q = _cloud(n, 7, "both")
+    X, Q = dev(x), dev(q)
+    ctx.profile(True)
+    ctx.profile_read()
+    ctx.profile_work()
+    B.field_eval(ctx, None, None, X, Q, X, 1e-7, B.OBEM_MIXED, tgt_is_src=True)
+    directed, once = ctx.profile_work()
+    assert directed > 0 and once > 0
+    assert directed + 2 * once == n * n
+    B.field_eval(ctx, None, None, X, Q, X, 1e-7, B.OBEM_MIXED, tgt_is_src=True, want_v=True)
+    directed, once = ctx.profile_work()
+    assert (directed, once) == (n * n, 0)
+    ctx.profile_read()
+    ctx.profile(False)
