@@ -453,7 +453,7 @@ def main():
         p5 = dict(dt=1e-12, step=0, seed=5, max_coll=64, max_ion_per_step=4, ion_v_cap=2e4,
                   box_lo=(-geo5.half_x, -geo5.half_y, -2e-3 - top5 - 2e-3),
                   box_hi=(geo5.half_x, geo5.half_y, top5 + 3e-3), soft=1e-7, r_rec=1e-6,
-                  precision=B.OBEM_MIXED, resolve=1)
+                  precision=B.OBEM_MIXED, resolve=3)
         steps5 = 1000
         tot5 = dict(children=0, recombined=0, absorbed=0, left_world=0, dd_charge_deposited=0, ionisations=0,
                     attachments=0, children_dropped=0)
@@ -494,7 +494,9 @@ def main():
         extra["double_gem_final_backward_ms"] = ms5b
         extra["double_gem_workload"] = (f"{n5} electrons released at rest in the holes of the upper foil, "
                                         f"{m5.n} cells, {steps5} steps of 1 ps, charging-up re-solve every "
-                                        f"step, recombination within 1 um, capacity 2M, mixed; setup (assembly "
+                                        f"step (from the inverse's columns of the dd cells hit when few changed, "
+                                        f"a full refined solve otherwise and every 64 updates), recombination "
+                                        f"within 1 um, capacity 2M, mixed; setup (assembly "
                                         f"+ LU + inverse) {t_setup5:.1f} s; then dL/dsigma of L = sum w.E at "
                                         f"the {nl5} final charges")
         log(f"[bench] double GEM: {steps5} steps, {ms5:.1f} ms per step, {rate5:.3e} interactions/s, n_live "

@@ -370,7 +370,12 @@ typedef struct {
                            same, but when the RHS equals, bit for bit, the one
                            of the mesh's previous re-solve (no new charge, no
                            influence, same rhs0) that solve's sigma is copied
-                           instead of solving again (the result is identical) */
+                           instead of solving again (the result is identical);
+                           3: as 2, and when at most 4096 RHS entries changed
+                           since that re-solve, sigma moves by the inverse's
+                           columns of those entries times their change (sigma
+                           agrees with a full re-solve to rounding; after 64
+                           such updates the next change takes a full re-solve) */
   int32_t influence;    /* with resolve: also move the live particles' influence
                            onto the RHS before the solve (as bem_influence)       */
   const double *rhs0;   /* device, n_panels: [V_i ; sigma_F0,i]                    */
@@ -401,7 +406,8 @@ typedef struct {
 /* One tracking step (ordered as in the paper's dynamic option):
  *  1. if p->resolve: rhs = rhs0 + e * dd_counts / area on dd rows
  *     (eq. (charge-up)), sigma = bem_solve_charges(rhs) (with resolve = 2
- *     skipped when rhs is unchanged since the mesh's last re-solve);
+ *     skipped when rhs is unchanged since the mesh's last re-solve, with
+ *     resolve = 3 also updated from the inverse when few entries changed);
  *  2. E at every live particle from the cells and all other particles,
  *     and each particle's nearest opposite-species partner;
  *  3. electron-cation pairs closer than r_rec recombine (eq. (distRecomb)):

@@ -38,6 +38,11 @@ constexpr double kQuadFp64 = 48.0;
 // keeps the drain at the end of a launch short (measured: 3 % faster pairwise
 // field than one round-robin pass of 15,625 long workgroups at 4M charges).
 constexpr int kSplitWorkgroups = 131072;
+// Incremental re-solve of a tracking step (resolve = 3): at most kIncMax
+// changed right-hand-side entries per step, and a full refined solve after
+// kIncEvery incremental updates.
+constexpr int kIncMax = 4096;
+constexpr int kIncEvery = 64;
 
 // Grow-only device buffer owned by a context.
 struct DevBuf {
@@ -50,7 +55,7 @@ enum WsSlot {
   WS_BBOX = 0, WS_KEYS0, WS_KEYS1, WS_IDX0, WS_IDX1, WS_SORT_TMP, WS_TSORT, WS_ACC, WS_PART,
   WS_NN, WS_MISC0, WS_MISC1, WS_MISC2, WS_MISC3, WS_MISC4, WS_MISC5, WS_MISC6, WS_MISC7,
   WS_SOLVE0, WS_SOLVE1, WS_SOLVE2, WS_SRC, WS_SRCPERM, WS_SRCKEY, WS_SORT_TMP2, WS_TBOX, WS_MAP, WS_STATUS, WS_SRCINV, WS_PANEL,
-  WS_SYMI, WS_SYMJ, WS_SYMR, WS_SYMM, WS_COUNT
+  WS_SYMI, WS_SYMJ, WS_SYMR, WS_SYMM, WS_INC_IDX, WS_INC_DB, WS_COUNT
 };
 
 }  // namespace obem
@@ -81,6 +86,7 @@ struct obem_meshh {
   // last re-solve of a tracking step: its right-hand side and charges (lazy)
   double *rhs_last = nullptr, *sigma_last = nullptr;
   bool last_valid = false;
+  int inc_since_solve = 0;    // incremental updates since the last full re-solve
   // collocation system (lazy)
   double *A = nullptr;        // n x n column-major
   double *LU = nullptr;       // n x n column-major

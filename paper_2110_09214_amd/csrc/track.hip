@@ -714,13 +714,47 @@ __global__ __launch_bounds__(256) void k_gather_sources(int n, const int32_t *__
   sp_out[i] = sp[j];
 }
 
-// Number of entries where a and b differ (bit patterns of the doubles).
-__global__ __launch_bounds__(256) void k_count_diff(int n, const double *__restrict__ a, const double *__restrict__ b,
-                                                    unsigned long long *cnt) {
+// The right-hand side entries that differ (bit patterns) from the last
+// re-solve's, in index order: idx[0..], db = rhs - rhs_last, at most cap of
+// them (the count itself may exceed cap).  One workgroup walks the entries
+// in order, so the list and hence the update's summation order are
+// deterministic.
+__global__ __launch_bounds__(256) void k_changed_rhs(int n, const double *__restrict__ rhs,
+                                                     const double *__restrict__ last, int cap, int32_t *idx,
+                                                     double *db, unsigned long long *count) {
+  __shared__ int wcnt[4];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  int base = 0;
+  for (int c = 0; c < n; c += 256) {
+    const int i = c + t;
+    const bool ch = i < n && __double_as_longlong(rhs[i]) != __double_as_longlong(last[i]);
+    const unsigned long long m = __ballot(ch);
+    if (lane == 0) wcnt[wv] = __popcll(m);
+    __syncthreads();
+    int off = base;
+    for (int k = 0; k < wv; ++k) off += wcnt[k];
+    const int pos = off + __popcll(m & ((1ull << lane) - 1ull));
+    if (ch && pos < cap) {
+      idx[pos] = i;
+      db[pos] = rhs[i] - last[i];
+    }
+    base += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
+  }
+  if (t == 0) *count = (unsigned long long)base;
+}
+
+// sigma = sigma_last + X[:, idx] db: the change of the solution for a
+// change of the right-hand side in k entries, from the inverse X (column
+// major) kept by the mesh; k columns read, added in list order.
+__global__ __launch_bounds__(256) void k_inc_update(int n, int k, const double *__restrict__ X,
+                                                    const int32_t *__restrict__ idx, const double *__restrict__ db,
+                                                    const double *__restrict__ sigma_last, double *sigma) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  const bool d = i < n && __double_as_longlong(a[i]) != __double_as_longlong(b[i]);
-  const unsigned long long m = __ballot(d);
-  if ((threadIdx.x & 63) == 0 && m) atomicAdd(cnt, (unsigned long long)__popcll(m));
+  if (i >= n) return;
+  double d = 0.0;
+  for (int j = 0; j < k; ++j) d = fma(X[(size_t)idx[j] * n + i], db[j], d);
+  sigma[i] = sigma_last[i] + d;
 }
 
 __global__ __launch_bounds__(256) void k_fill_u64(int n, unsigned long long *p, unsigned long long v) {
@@ -1002,7 +1036,7 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
   if (mesh) {
     if (!p->map && !is_device_ptr(sigma)) return fail(ctx, OBEM_EINVAL, "sigma must be device memory");
     if (mesh->n_dd && !is_device_ptr(dd_counts)) return fail(ctx, OBEM_EINVAL, "dd_counts must be device memory");
-    if (p->resolve < 0 || p->resolve > 2) return fail(ctx, OBEM_EINVAL, "resolve must be 0, 1 or 2");
+    if (p->resolve < 0 || p->resolve > 3) return fail(ctx, OBEM_EINVAL, "resolve must be 0, 1, 2 or 3");
     if (p->resolve && !is_device_ptr(p->rhs0)) return fail(ctx, OBEM_EINVAL, "rhs0 must be device memory");
   }
   MapDev gmap;
@@ -1032,12 +1066,14 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
       if (st) return st;
     }
     bool solve = true;
-    if (p->resolve == 2 && mesh->last_valid) {
+    if ((p->resolve == 2 || p->resolve == 3) && mesh->last_valid) {
       unsigned long long *nd = (unsigned long long *)ws_get(ctx, WS_MISC7, sizeof(unsigned long long));
-      if (!nd) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+      int32_t *idx = (int32_t *)ws_get(ctx, WS_INC_IDX, sizeof(int32_t) * kIncMax);
+      double *db = (double *)ws_get(ctx, WS_INC_DB, sizeof(double) * kIncMax);
+      if (!nd || !idx || !db) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
       unsigned long long h = 0;
-      hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, ctx->stream, 1, nd, 0ull);
-      hipLaunchKernelGGL(k_count_diff, dim3(nbt(N)), dim3(256), 0, ctx->stream, N, rhs, mesh->rhs_last, nd);
+      hipLaunchKernelGGL(k_changed_rhs, dim3(1), dim3(256), 0, ctx->stream, N, rhs, mesh->rhs_last, kIncMax, idx,
+                         db, nd);
       OBEM_HIP(ctx, hipGetLastError());
       OBEM_HIP(ctx, hipMemcpyAsync(&h, nd, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
       OBEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -1045,11 +1081,24 @@ extern "C" obem_status track_step(obem_ctx *ctx, obem_meshh *mesh, obem_particle
         OBEM_HIP(ctx, hipMemcpyAsync(sigma, mesh->sigma_last, sizeof(double) * N, hipMemcpyDeviceToDevice,
                                      ctx->stream));
         solve = false;
+      } else if (p->resolve == 3 && h <= (unsigned long long)kIncMax && mesh->inc_since_solve < kIncEvery) {
+        // eq. (charge-up) changes the right-hand side in the few dd cells hit
+        // this step: sigma moves by those columns of the inverse
+        OBEM_PROF(ctx, "solve");
+        hipLaunchKernelGGL(k_inc_update, dim3(nbt(N)), dim3(256), 0, ctx->stream, N, (int)h, mesh->LU, idx, db,
+                           mesh->sigma_last, sigma);
+        OBEM_HIP(ctx, hipGetLastError());
+        OBEM_HIP(ctx, hipMemcpyAsync(mesh->rhs_last, rhs, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
+        OBEM_HIP(ctx, hipMemcpyAsync(mesh->sigma_last, sigma, sizeof(double) * N, hipMemcpyDeviceToDevice,
+                                     ctx->stream));
+        ++mesh->inc_since_solve;
+        solve = false;
       }
     }
     if (solve) {
       st = bem_solve(ctx, mesh, rhs, sigma, 2, nullptr);
       if (st) return st;
+      mesh->inc_since_solve = 0;
       if (!mesh->rhs_last) {
         if (hipMalloc(&mesh->rhs_last, sizeof(double) * N) != hipSuccess ||
             hipMalloc(&mesh->sigma_last, sizeof(double) * N) != hipSuccess) {

@@ -160,6 +160,51 @@ def test_resolve_on_change_matches_always(ctx):
     assert any(d == 0 for d in dep[1:-1])     # ... and some later step keeps it
 
 
+def test_resolve_incremental_matches_full(ctx):
+    """resolve = 3 moves the cell charges by the inverse's columns of the
+    right-hand-side entries that changed (the dd cells hit in the step, eq.
+    (charge-up)) instead of solving again: the charges agree with the full
+    re-solve of resolve = 1 to rounding at every step, and the particle
+    stream stays the same.  Electrons released at several heights above the
+    dielectric slab land over several steps, so the update runs repeatedly."""
+    m, st0 = _scenario(4)
+    rng = np.random.default_rng(44)
+    k = 400
+    hx = np.stack([rng.uniform(-8e-4, 8e-4, k), rng.uniform(-8e-4, 8e-4, k),
+                   4e-4 + np.geomspace(1e-7, 1.2e-5, k)], 1)
+    st = dict(x=np.concatenate([st0["x"], hx]), v=np.concatenate([st0["v"], np.tile([0.0, 0.0, -2e6], (k, 1))]),
+              species=np.concatenate([st0["species"], np.zeros(k, np.int8)]),
+              id=np.arange(len(st0["id"]) + k, dtype=np.int64), next_id=len(st0["id"]) + k)
+    gas = W.synthetic_ar_co2()
+    gas_s, keep = B.gas_struct(gas, "cuda")
+    runs = {}
+    for mode in (1, 3):
+        bm = bind(ctx, m)
+        rhs0 = dev(m.rhs)
+        sig, _ = B.bem_solve_charges(ctx, bm, rhs0)
+        parts = B.Particles(20000, "cuda", dev(st["x"]), dev(st["v"]), dev(st["species"], torch.int8),
+                            dev(st["id"], torch.int64), st["next_id"])
+        counts = torch.zeros(m.n, dtype=torch.int64, device="cuda")
+        hist = []
+        for s_ in range(8):
+            p = _params(s_, B.OBEM_FP64)
+            p["resolve"] = mode if s_ > 0 else 0
+            sg = B.track_step(ctx, bm, parts, gas_s, p, counts, sig, rhs0)
+            g = parts.state()
+            hist.append((host(g["x"]), host(g["id"]), host(counts).copy(), host(sig).copy(),
+                         sg["dd_charge_deposited"]))
+        runs[mode] = hist
+    dep = [h[4] for h in runs[1]]
+    print("dd charges deposited per step", dep)
+    assert sum(1 for d in dep[:-1] if d) >= 4             # several incremental updates
+    for s_, (a, b) in enumerate(zip(runs[1], runs[3])):
+        assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2]), s_
+        err = np.abs(b[3] - a[3]).max() / np.abs(a[3]).max()
+        print("step", s_, "sigma incremental vs full", err)
+        assert err <= 1e-13
+        assert np.abs(b[0] - a[0]).max() <= 1e-12 * 1e-3
+
+
 def test_track_step_capacity_overflow(ctx):
     m, st0 = _scenario(2)
     gas = W.synthetic_ar_co2()
