@@ -1062,7 +1062,7 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
 // k_sym_reduce adds the slots to acc in order.
 constexpr int kSymTiles = 8;
 constexpr int kSymSB = kSymTiles * kThreads;  // particles per super-block
-constexpr int kSymSlots = 32;                 // values of d per launch
+constexpr int kSymSlots = 40;                 // values of d per launch, at most
 
 template <bool NN>
 __global__ __launch_bounds__(kThreads, 4) void k_pair_sym(int n, const double *__restrict__ sx,
@@ -1429,6 +1429,43 @@ static void launch_pair_t(obem_ctx *ctx, dim3 grid, int n_t, const double *xs, c
                        sx, sy, sz, sq, sp, sps, soft * soft, chunk, part, (double *)nnd, nni, self_map);
 }
 
+// Workgroups of k_pair_sym<nn> resident at once on the context's device.
+static int sym_resident(obem_ctx *ctx, bool nn) {
+  int &cache = nn ? ctx->sym_resident_nn : ctx->sym_resident;
+  if (cache > 0) return cache;
+  int per_cu = 0, cus = 0;
+  const void *f = nn ? reinterpret_cast<const void *>(&k_pair_sym<true>)
+                     : reinterpret_cast<const void *>(&k_pair_sym<false>);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kThreads, 0) != hipSuccess || per_cu < 1 || cus < 1) {
+    (void)hipGetLastError();
+    return 1;  // no rounding of the launches to the resident count
+  }
+  cache = per_cu * cus;
+  return cache;
+}
+
+// Values of d for the next pair-once launch: all remaining if they fit,
+// else the count in [kSymSlots / 2, kSymSlots] whose ns x count workgroups
+// leave the smallest share of the launch's last round of resident
+// workgroups idle (equal workgroups run in rounds; at 32 values of d and
+// 1954 super-blocks the last round held 64 of 1024).
+static int sym_launch_count(int ns, int remaining, int resident) {
+  if (remaining <= kSymSlots || resident <= 1) return std::min(remaining, kSymSlots);
+  int best = kSymSlots;
+  double best_waste = 2.0;
+  for (int c = kSymSlots; c >= kSymSlots / 2; --c) {
+    const long long items = (long long)ns * c;
+    const long long idle = (resident - items % resident) % resident;
+    const double waste = (double)idle / (double)items;
+    if (waste < best_waste - 1e-12) {
+      best_waste = waste;
+      best = c;
+    }
+  }
+  return best;
+}
+
 obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, const double *sy, const double *sz,
                               const double *sq, const TargetOrder &to, double soft, obem_precision prec,
                               bool tgt_is_src, bool want_v, const int8_t *species, const int8_t *species_s,
@@ -1530,8 +1567,9 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
       float *Pj = (float *)ws_get(ctx, WS_SYMJ, sizeof(float) * 3 * kSymSlots * (size_t)n_t);
       if (!Pi || !Pj) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
       OBEM_PROF(ctx, "pair_once");
-      for (int d0 = 1; d0 <= hmax; d0 += kSymSlots) {
-        const int dcnt = std::min(kSymSlots, hmax - d0 + 1);
+      const int resident = sym_resident(ctx, nn);
+      for (int d0 = 1, dcnt = 0; d0 <= hmax; d0 += dcnt) {
+        dcnt = sym_launch_count(ns, hmax - d0 + 1, resident);
         const dim3 g(ns, dcnt);
         if (nn)
           hipLaunchKernelGGL(k_pair_sym<true>, g, dim3(kThreads), 0, ctx->stream, n_t, sx, sy, sz, sq, tbox,
