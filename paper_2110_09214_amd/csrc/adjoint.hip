@@ -24,7 +24,7 @@ namespace obem {
 
 constexpr int kT = 256;
 constexpr int kBwdTiles = 4;   // tiles per super-block of the pair-once adjoint
-constexpr int kBwdSlots = 32;  // values of d per pair-once launch
+constexpr int kBwdSlots = 40;  // values of d per pair-once launch, at most
 constexpr int kPTb = 64;
 
 static inline int nbk(int64_t n) { return (int)((n + kT - 1) / kT); }
@@ -1085,8 +1085,11 @@ extern "C" obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh
         float *Pi = (float *)ws_get(ctx, WS_SYMI, sizeof(float) * 3 * kBwdSlots * (size_t)n_t);
         float *Pj = (float *)ws_get(ctx, WS_SYMJ, sizeof(float) * 3 * kBwdSlots * (size_t)n_t);
         if (!Pi || !Pj) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
-        for (int d0 = 1; d0 <= hmax; d0 += kBwdSlots) {
-          const int dcnt = std::min(kBwdSlots, hmax - d0 + 1);
+        if (ctx->bwd_resident <= 0)
+          ctx->bwd_resident = resident_workgroups(reinterpret_cast<const void *>(&k_pair_bwd_sym<kBwdTiles>), kT,
+                                                  ctx->device);
+        for (int d0 = 1, dcnt = 0; d0 <= hmax; d0 += dcnt) {
+          dcnt = launch_slots(ns, hmax - d0 + 1, ctx->bwd_resident, kBwdSlots);
           hipLaunchKernelGGL(k_pair_bwd_sym<kBwdTiles>, dim3(ns, dcnt), dim3(kT), 0, ctx->stream, n_t, so.x, so.y,
                              so.z, so.q, wsrt, sb, dmask, dwpr, (float)(soft * soft), ns, d0, Pi, Pj);
           launch_sym_reduce(ctx, n_t, sbsz, ns, d0, dcnt, Pi, Pj, gx);

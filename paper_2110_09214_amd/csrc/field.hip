@@ -1432,38 +1432,11 @@ static void launch_pair_t(obem_ctx *ctx, dim3 grid, int n_t, const double *xs, c
 // Workgroups of k_pair_sym<nn> resident at once on the context's device.
 static int sym_resident(obem_ctx *ctx, bool nn) {
   int &cache = nn ? ctx->sym_resident_nn : ctx->sym_resident;
-  if (cache > 0) return cache;
-  int per_cu = 0, cus = 0;
-  const void *f = nn ? reinterpret_cast<const void *>(&k_pair_sym<true>)
-                     : reinterpret_cast<const void *>(&k_pair_sym<false>);
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kThreads, 0) != hipSuccess || per_cu < 1 || cus < 1) {
-    (void)hipGetLastError();
-    return 1;  // no rounding of the launches to the resident count
-  }
-  cache = per_cu * cus;
+  if (cache <= 0)
+    cache = resident_workgroups(nn ? reinterpret_cast<const void *>(&k_pair_sym<true>)
+                                   : reinterpret_cast<const void *>(&k_pair_sym<false>),
+                                kThreads, ctx->device);
   return cache;
-}
-
-// Values of d for the next pair-once launch: all remaining if they fit,
-// else the count in [kSymSlots / 2, kSymSlots] whose ns x count workgroups
-// leave the smallest share of the launch's last round of resident
-// workgroups idle (equal workgroups run in rounds; at 32 values of d and
-// 1954 super-blocks the last round held 64 of 1024).
-static int sym_launch_count(int ns, int remaining, int resident) {
-  if (remaining <= kSymSlots || resident <= 1) return std::min(remaining, kSymSlots);
-  int best = kSymSlots;
-  double best_waste = 2.0;
-  for (int c = kSymSlots; c >= kSymSlots / 2; --c) {
-    const long long items = (long long)ns * c;
-    const long long idle = (resident - items % resident) % resident;
-    const double waste = (double)idle / (double)items;
-    if (waste < best_waste - 1e-12) {
-      best_waste = waste;
-      best = c;
-    }
-  }
-  return best;
 }
 
 obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, const double *sy, const double *sz,
@@ -1569,7 +1542,9 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
       OBEM_PROF(ctx, "pair_once");
       const int resident = sym_resident(ctx, nn);
       for (int d0 = 1, dcnt = 0; d0 <= hmax; d0 += dcnt) {
-        dcnt = sym_launch_count(ns, hmax - d0 + 1, resident);
+        // equal workgroups run in rounds: at 32 values of d and 1954
+        // super-blocks the last round of a launch held 64 of 1024
+        dcnt = launch_slots(ns, hmax - d0 + 1, resident, kSymSlots);
         const dim3 g(ns, dcnt);
         if (nn)
           hipLaunchKernelGGL(k_pair_sym<true>, g, dim3(kThreads), 0, ctx->stream, n_t, sx, sy, sz, sq, tbox,

@@ -117,7 +117,7 @@ struct obem_ctx {
   obem::DevBuf ws[obem::WS_COUNT];
   void *rocblas = nullptr;   // rocblas_handle, created on first solve
   bool prof = false;         // per-kernel event timing
-  int sym_resident = 0, sym_resident_nn = 0;  // pair-once workgroups resident at once (lazy)
+  int sym_resident = 0, sym_resident_nn = 0, bwd_resident = 0;  // pair-once workgroups resident at once (lazy)
   // pairwise work while profiling: device count of the directed kernel's
   // terms of pair-once calls (filled from the tile-pair mask), host counts of
   // the directed terms of the other calls and of the pair-once calls' n^2

@@ -3,6 +3,8 @@
 // kernels, shared by the field and its adjoint.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace obem {
@@ -49,6 +51,39 @@ __device__ __forceinline__ bool tile_pair_direct(const double *__restrict__ tbox
 // smaller radius (A on a tie).
 __device__ __forceinline__ const double *sym_origin(const double *__restrict__ sb, int A, int B) {
   return sb[4 * (size_t)B + 3] < sb[4 * (size_t)A + 3] ? sb + 4 * (size_t)B : sb + 4 * (size_t)A;
+}
+
+// Workgroups of `kernel` (blocks of `threads`) resident at once on `device`,
+// or 1 if the runtime cannot tell.
+inline int resident_workgroups(const void *kernel, int threads, int device) {
+  int per_cu = 0, cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1 ||
+      cus < 1) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return per_cu * cus;
+}
+
+// Values of d for the next pair-once launch: all remaining if they fit in
+// max_slots, else the count in [max_slots / 2, max_slots] whose ns x count
+// equal workgroups leave the smallest share of the launch's last round of
+// resident workgroups idle.
+inline int launch_slots(int ns, int remaining, int resident, int max_slots) {
+  if (remaining <= max_slots || resident <= 1) return remaining < max_slots ? remaining : max_slots;
+  int best = max_slots;
+  double best_waste = 2.0;
+  for (int c = max_slots; c >= max_slots / 2; --c) {
+    const long long items = (long long)ns * c;
+    const long long idle = (resident - items % resident) % resident;
+    const double waste = (double)idle / (double)items;
+    if (waste < best_waste - 1e-12) {
+      best_waste = waste;
+      best = c;
+    }
+  }
+  return best;
 }
 
 }  // namespace obem
