@@ -53,8 +53,10 @@ typedef enum {
                       a 7-point rule; pairwise terms and sums in float64      */
   OBEM_MIXED = 1   /* cells nearer than 3 diameters: float64 closed-form
                       integrals.  Farther cells: float32 quadrature of the
-                      cell (7 points up to 8 diameters, 6 up to 40, 3
-                      beyond).  Pairwise terms in float32 from coordinates
+                      cell (7 points within 8 diameters, 6 or more within
+                      40, 3 or more beyond: a group of 64 targets takes the
+                      finest rule one of them may need).  Pairwise terms in
+                      float32 from coordinates
                       recentred near the targets (float32 hi + lo pairs for
                       the sources near them, so close pairs keep their
                       separation exactly).  Sums: float32 over blocks of

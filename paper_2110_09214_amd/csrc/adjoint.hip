@@ -986,7 +986,7 @@ extern "C" obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh
   int excl = 0;
   if (!(soft > 0.0)) excl = 1;
   // targets = sources: with the pair-once evaluation the targets take the
-  // sources' order (charge sign, then Morton; same particles, same tiles)
+  // sources' order (charge sign, then Hilbert; same particles, same tiles)
   const bool once = tis && want_t && excl == 0 && pair_once_applies(n_tgt, precision, soft, false);
   SourceOrder so;
   TargetOrder to;

@@ -385,7 +385,6 @@ static obem_status bind_fill(obem_ctx *ctx, const obem_mesh *mesh, obem_meshh *m
   if (hipMalloc(&m->f, sizeof(double) * MF_COUNT * (size_t)n) != hipSuccess ||
       hipMalloc(&m->kind, (size_t)n) != hipSuccess || hipMalloc(&m->tiles, sizeof(double) * 4 * ntile) != hipSuccess ||
       hipMalloc(&m->tiles48, sizeof(double) * 4 * ntile) != hipSuccess ||
-      hipMalloc(&m->tiles40, sizeof(double) * 4 * ntile) != hipSuccess ||
       hipMalloc(&m->order, sizeof(int32_t) * n) != hipSuccess) {
     (void)hipGetLastError();
     return fail(ctx, OBEM_ENOMEM, "mesh allocation failed");
@@ -401,7 +400,6 @@ static obem_status bind_fill(obem_ctx *ctx, const obem_mesh *mesh, obem_meshh *m
   OBEM_HIP(ctx, hipGetLastError());
   hipLaunchKernelGGL(k_tile_spheres, dim3(ntile), dim3(64), 0, ctx->stream, (int)n, m->f, kNearMixed, m->tiles);
   hipLaunchKernelGGL(k_tile_spheres, dim3(ntile), dim3(64), 0, ctx->stream, (int)n, m->f, kQuadFp64, m->tiles48);
-  hipLaunchKernelGGL(k_tile_spheres, dim3(ntile), dim3(64), 0, ctx->stream, (int)n, m->f, kFar3Mixed, m->tiles40);
   OBEM_HIP(ctx, hipGetLastError());
   {
     TargetOrder co;
@@ -439,7 +437,6 @@ static void free_mesh(obem_meshh *m) {
   (void)hipFree(m->kind);
   (void)hipFree(m->tiles);
   (void)hipFree(m->tiles48);
-  (void)hipFree(m->tiles40);
   (void)hipFree(m->order);
   (void)hipFree(m->rhs_last);
   (void)hipFree(m->sigma_last);

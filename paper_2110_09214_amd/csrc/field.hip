@@ -1,7 +1,7 @@
 // Field evaluation kernels for gfx950: target ordering, cell (panel) field,
 // pairwise point-charge field, fixed-order reduction and scatter.
 //
-// Layout: targets are reordered along a Morton curve so that the 256 targets
+// Layout: targets are reordered along a Hilbert curve so that the 256 targets
 // of a workgroup are spatially compact; each workgroup recentres its targets
 // and the staged source/cell data on its first target (FP64 difference, then
 // FP32), which keeps FP32 differences relative to the pair distance instead
@@ -92,21 +92,57 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v) {
   return v;
 }
 
-__global__ __launch_bounds__(256) void k_morton(int n, const double *__restrict__ x, const double *__restrict__ y,
-                                                const double *__restrict__ z, const double *bbox,
-                                                uint32_t *keys, int32_t *idx) {
+// Index along the Hilbert curve of a cell (x0, x1, x2) of the 1024^3 grid,
+// after J. Skilling's transpose form (AIP Conf. Proc. 707 (2004) 381): undo
+// the excess work level by level, Gray-encode, then interleave the bits with
+// x0 most significant.  Consecutive indices are neighbouring cells, so runs of
+// consecutive points have tighter boxes than along the Morton curve (which
+// jumps): at 4M cloud charges half as many 256-point tile pairs are near
+// each other.
+__device__ __forceinline__ uint32_t hilbert3(uint32_t x0, uint32_t x1, uint32_t x2) {
+  uint32_t X[3] = {x0, x1, x2};
+  for (uint32_t Q = 1u << 9; Q > 1u; Q >>= 1) {
+    const uint32_t P = Q - 1u;
+    if (X[0] & Q) X[0] ^= P;
+#pragma unroll
+    for (int i = 1; i < 3; ++i) {
+      if (X[i] & Q) {
+        X[0] ^= P;
+      } else {
+        const uint32_t t = (X[0] ^ X[i]) & P;
+        X[0] ^= t;
+        X[i] ^= t;
+      }
+    }
+  }
+  X[1] ^= X[0];
+  X[2] ^= X[1];
+  uint32_t t = 0u;
+  for (uint32_t Q = 1u << 9; Q > 1u; Q >>= 1)
+    if (X[2] & Q) t ^= Q - 1u;
+  X[0] ^= t;
+  X[1] ^= t;
+  X[2] ^= t;
+  return spread3(X[2]) | (spread3(X[1]) << 1) | (spread3(X[0]) << 2);
+}
+
+__global__ __launch_bounds__(256) void k_curve_key(int n, const double *__restrict__ x, const double *__restrict__ y,
+                                                   const double *__restrict__ z, const double *bbox,
+                                                   uint32_t *keys, int32_t *idx) {
   int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   double v[3] = {x[i], y[i], z[i]};
   uint32_t q[3];
+  // one scale for the three axes, so that runs along the curve are compact
+  // in space also in a flat or elongated point set
+  const double span = fmax(fmax(bbox[3] - bbox[0], bbox[4] - bbox[1]), bbox[5] - bbox[2]);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double span = bbox[3 + c] - bbox[c];
     double t = span > 0.0 ? (v[c] - bbox[c]) / span : 0.0;
     int qi = (int)(t * 1024.0);
     q[c] = (uint32_t)min(max(qi, 0), 1023);
   }
-  keys[i] = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
+  keys[i] = hilbert3(q[0], q[1], q[2]);
   idx[i] = i;
 }
 
@@ -152,7 +188,7 @@ void launch_tile_boxes(obem_ctx *ctx, int n, const double *src, double *box) {
   if (n > 0) hipLaunchKernelGGL(k_tile_boxes, dim3(nblk(n)), dim3(256), 0, ctx->stream, n, src, box);
 }
 
-// Sources in (charge sign, Morton) order: key of the i-th Morton-sorted
+// Sources in (charge sign, Hilbert) order: key of the i-th Hilbert-sorted
 // source, value its caller index.
 __global__ __launch_bounds__(256) void k_charge_key(int n, const int32_t *__restrict__ perm,
                                                     const double *__restrict__ q, uint8_t *key, int32_t *idx) {
@@ -227,7 +263,7 @@ obem_status order_targets(obem_ctx *ctx, int64_t n64, const double *tx, const do
   if (!bbox || !k0 || !k1 || !i0 || !i1 || !xs) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
   hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(256), 0, ctx->stream, n, tx, ty, tz, bbox + 6);
   hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, ctx->stream, nb, bbox + 6, bbox);
-  hipLaunchKernelGGL(k_morton, dim3(nblk(n)), dim3(256), 0, ctx->stream, n, tx, ty, tz, bbox, k0, i0);
+  hipLaunchKernelGGL(k_curve_key, dim3(nblk(n)), dim3(256), 0, ctx->stream, n, tx, ty, tz, bbox, k0, i0);
   size_t tmp_bytes = 0;
   OBEM_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, k0, k1, i0, i1, n, 0, 30, ctx->stream));
   void *tmp = ws_get(ctx, WS_SORT_TMP, tmp_bytes + 256);
@@ -249,7 +285,7 @@ constexpr int kPT = 64;               // cells per LDS tile
 // (one address per cell, 128-bit LDS reads):
 //   c[0] = centroid, (3 D)^2          c[1] = (40 D)^2, area sigma {w0, wa, wb}
 //   c[2..7] = the 7 points of the degree-5 rule (21 floats), area sigma / 3,
-//             (8 D)^2, 0
+//             (8 D)^2, D
 //   c[8..10] = the 3 points of the degree-2 rule (9 floats), area sigma
 //             {w1, w2} of the 6-point rule, 0
 //   c[11..15] = the 6 points of the degree-4 rule (18 floats), 0, 0
@@ -323,7 +359,7 @@ template <bool WANT_V>
 __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double *__restrict__ xs, int N,
                                                           const double *__restrict__ f,
                                                           const double *__restrict__ sigma, int cchunk,
-                                                          double *part, const double *__restrict__ tiles40) {
+                                                          double *part) {
   __shared__ PanelCell T[kPT];
   const int tid = threadIdx.x;
   const int i0 = blockIdx.x * kThreads;
@@ -334,6 +370,26 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
   const double x1 = active ? xs[(size_t)n_t + i] : c1;
   const double x2 = active ? xs[2 * (size_t)n_t + i] : c2;
   const float r0 = (float)(x0 - c0), r1 = (float)(x1 - c1), r2 = (float)(x2 - c2);
+  // the wave's sphere: centre of its targets' bounding box, radius the
+  // largest distance from it (widened by 1e-4 for the rounding)
+  float cw0, cw1, cw2, rw;
+  {
+    float lo0 = r0, lo1 = r1, lo2 = r2, hi0 = r0, hi1 = r1, hi2 = r2;
+    for (int o = 32; o > 0; o >>= 1) {
+      lo0 = fminf(lo0, __shfl_xor(lo0, o));
+      lo1 = fminf(lo1, __shfl_xor(lo1, o));
+      lo2 = fminf(lo2, __shfl_xor(lo2, o));
+      hi0 = fmaxf(hi0, __shfl_xor(hi0, o));
+      hi1 = fmaxf(hi1, __shfl_xor(hi1, o));
+      hi2 = fmaxf(hi2, __shfl_xor(hi2, o));
+    }
+    cw0 = 0.5f * (lo0 + hi0);
+    cw1 = 0.5f * (lo1 + hi1);
+    cw2 = 0.5f * (lo2 + hi2);
+    rw = sqrtf(dist2f(r0, r1, r2, cw0, cw1, cw2));
+    for (int o = 32; o > 0; o >>= 1) rw = fmaxf(rw, __shfl_xor(rw, o));
+    rw *= 1.0001f;
+  }
   float hx = 0.f, hy = 0.f, hz = 0.f, hv = 0.f, lx = 0.f, ly = 0.f, lz = 0.f, lv = 0.f;
   const int kb = blockIdx.y * cchunk, ke = min(N, kb + cchunk);
   for (int k0 = kb; k0 < ke; k0 += kPT) {
@@ -355,7 +411,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
     if (tid < kPT) {
       const int k = tid;
       float4 g = make_float4(0.f, 0.f, 0.f, 0.f), h = g;
-      float w3 = 0.f, lim8 = 0.f, w61 = 0.f, w62 = 0.f;
+      float w3 = 0.f, lim8 = 0.f, w61 = 0.f, w62 = 0.f, dk = 0.f;
       if (k < cnt) {
         const int kk = k0 + k;
         const double D = f[(size_t)MF_DIAM * N + kk];
@@ -366,6 +422,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
                         (float)(as * Rule7::wb));
         w3 = (float)(as * (1.0 / 3.0));
         lim8 = (float)(kMid6Mixed * kMid6Mixed * D * D);
+        dk = (float)D;
         w61 = (float)(as * Rule6::w1);
         w62 = (float)(as * Rule6::w2);
       }
@@ -374,7 +431,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
       T[k].c[1] = h;
       rec[29] = w3;
       rec[30] = lim8;
-      rec[31] = 0.f;
+      rec[31] = dk;
       rec[41] = w61;
       rec[42] = w62;
       rec[43] = 0.f;
@@ -382,28 +439,60 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
     }
     __syncthreads();
     float px = 0.f, py = 0.f, pz = 0.f, pv = 0.f;
-    // a wave whose targets all lie outside the tile's 40 D sphere (tile
-    // centre, max over its cells of |c_k - centre| + 40 D_k) needs the
-    // 3-point rule for every cell of the tile: no per-cell test
-    const double *ts = tiles40 + 4 * (size_t)(k0 / kPT);
-    const float tr = (float)ts[3] * 1.001f;
-    const bool allfar = __all(dist2f(r0, r1, r2, (float)(ts[0] - c0), (float)(ts[1] - c1), (float)(ts[2] - c2)) >
-                              tr * tr);
-    if (allfar) {
-      for (int k = 0; k < cnt; ++k) {
-        float q[12];
-        load4<3>(&T[k].c[8], q);
-        const float w3 = T[k].c[7].y;
-        const float w[3] = {w3, w3, w3};
-        panel_points<3, WANT_V>(q, w, r0, r1, r2, px, py, pz, pv);
+    // The rule of each cell for the whole wave, from one test per cell
+    // against the wave's sphere: lane k tests cell k, and the ballots give
+    // the cells some lane may see within 40 D (6 points or finer), within
+    // 8 D (7 points) and within 3 D (the per-lane path, which leaves the near
+    // pairs to k_panel_near).  Thresholds 1 % wide of the per-lane ones, so
+    // that a cell not flagged near has no lane inside 3 D by the per-lane
+    // test, and a coarser rule is never taken where a lane needs a finer one.
+    uint64_t m3, m6, m7, mnear;
+    {
+      const int k = tid & 63;
+      float t = 3.0e38f, Dk = 0.f;
+      if (k < cnt) {
+        const float4 g = T[k].c[0];
+        Dk = T[k].c[7].w;
+        t = sqrtf(dist2f(cw0, cw1, cw2, g.x, g.y, g.z)) - rw;
       }
+      const uint64_t f6 = __ballot(t < (float)(kFar3Mixed * 1.01) * Dk);
+      const uint64_t f7 = __ballot(t < (float)(kMid6Mixed * 1.01) * Dk);
+      mnear = __ballot(t < (float)(kNearMixed * 1.01) * Dk);
+      m3 = (cnt == 64 ? ~0ull : ((1ull << cnt) - 1ull)) & ~f6;
+      m6 = f6 & ~f7;
+      m7 = f7 & ~mnear;
     }
-    for (int k = 0; k < (allfar ? 0 : cnt); ++k) {
+    for (; m3; m3 &= m3 - 1ull) {
+      const int k = __builtin_ctzll(m3);
+      float q[12];
+      load4<3>(&T[k].c[8], q);
+      const float w3 = T[k].c[7].y;
+      const float w[3] = {w3, w3, w3};
+      panel_points<3, WANT_V>(q, w, r0, r1, r2, px, py, pz, pv);
+    }
+    for (; m6; m6 &= m6 - 1ull) {
+      const int k = __builtin_ctzll(m6);
+      float q[20];
+      load4<5>(&T[k].c[11], q);
+      const float4 h10 = T[k].c[10];
+      const float w[6] = {h10.y, h10.y, h10.y, h10.z, h10.z, h10.z};
+      panel_points<6, WANT_V>(q, w, r0, r1, r2, px, py, pz, pv);
+    }
+    for (; m7; m7 &= m7 - 1ull) {
+      const int k = __builtin_ctzll(m7);
+      float q[24];
+      load4<6>(&T[k].c[2], q);
+      const float4 h = T[k].c[1];
+      const float w[7] = {h.y, h.z, h.z, h.z, h.w, h.w, h.w};
+      panel_points<7, WANT_V>(q, w, r0, r1, r2, px, py, pz, pv);
+    }
+    for (; mnear; mnear &= mnear - 1ull) {
+      const int k = __builtin_ctzll(mnear);
       const float4 g = T[k].c[0];
       const float R2 = dist2f(r0, r1, r2, g.x, g.y, g.z);
       const bool nearp = R2 < g.w;  // taken by k_panel_near in FP64
       const float4 h = T[k].c[1];
-      const float4 h7 = T[k].c[7];  // {.., area sigma / 3, (8 D)^2, 0}
+      const float4 h7 = T[k].c[7];  // {.., area sigma / 3, (8 D)^2, D}
       // the rule by distance (7 points within 8 D, 6 within 40 D, 3 beyond),
       // taken for the whole wave at the finest rule one of its lanes needs
       const bool need7 = (!nearp) && (R2 < h7.z);
@@ -668,7 +757,7 @@ obem_status launch_panel_field(obem_ctx *ctx, const obem_meshh *m, const double 
 #define PANEL_FAR(K, V, ...) \
   hipLaunchKernelGGL(K<V>, gsplit, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, cchunk, part __VA_ARGS__)
   if (prec == OBEM_MIXED) {
-    if (want_v) PANEL_FAR(k_panel_mixed, true, , m->tiles40); else PANEL_FAR(k_panel_mixed, false, , m->tiles40);
+    if (want_v) PANEL_FAR(k_panel_mixed, true); else PANEL_FAR(k_panel_mixed, false);
   } else {
     if (want_v) PANEL_FAR(k_panel_fp64, true); else PANEL_FAR(k_panel_fp64, false);
   }

@@ -6,13 +6,13 @@
 //   ed rows V_i - Vbar_i,   dd rows sigma_F,i - eps0 (eps_r2 - eps_r1) Ebar_i . n_i.
 //
 // It is the transpose of the cell field: one thread per cell, cells taken in
-// the mesh's Morton order of centroids (a workgroup's cells are spatially
+// the mesh's Hilbert order of centroids (a workgroup's cells are spatially
 // close and are recentred on its first centroid), charges staged in LDS
 // tiles, gridDim.y chunks of charges with per-chunk partial sums reduced in
 // chunk order.  Precision regimes as in the field: mixed = FP32 7-point rule
 // within 8 diameters, 6-point rule within 40, 3-point rule beyond (far
 // kernel, charges ordered by
-// charge sign, then Morton, so the charge comes out of the pair loop), FP64
+// charge sign, then Hilbert, so the charge comes out of the pair loop), FP64
 // closed form within 3 diameters (near kernel, its own partial slots);
 // FP64 = closed form within 48 diameters, FP64 7-point rule beyond.
 #include <algorithm>
@@ -43,7 +43,7 @@ __device__ __forceinline__ void infl_closed(const double *__restrict__ f, int N,
 }
 
 // Far part of the mixed influence, charge-major: a workgroup owns 8 cells
-// (consecutive in the mesh's Morton order) and streams its chunk of the
+// (consecutive in the mesh's Hilbert order) and streams its chunk of the
 // charges in blocks of 1024, 4 per thread (one from each 256-charge tile of
 // the block, so a wave's lanes hold 64 consecutive, spatially close charges).
 // Per cell the rule is chosen per wave over those close charges (7 points

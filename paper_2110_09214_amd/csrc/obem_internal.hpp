@@ -81,8 +81,7 @@ struct obem_meshh {
   double max_diam = 0;
   double *tiles = nullptr;    // per 64-cell tile: centre (3), near-zone radius (3 D)
   double *tiles48 = nullptr;  // the same for the FP64 closed-form zone (48 D)
-  double *tiles40 = nullptr;  // the same for the 3-point zone of the mixed cell field (40 D)
-  int32_t *order = nullptr;   // cell indices in Morton order of the centroids
+  int32_t *order = nullptr;   // cell indices in Hilbert order of the centroids
   // last re-solve of a tracking step: its right-hand side and charges (lazy)
   double *rhs_last = nullptr, *sigma_last = nullptr;
   bool last_valid = false;
@@ -163,7 +162,7 @@ struct ProfScope {
 #define OBEM_PROF(ctx, name) obem::ProfScope obem_prof_scope_(ctx, name)
 
 
-// Target ordering (Morton keys) used by the field kernels.
+// Target ordering (Hilbert keys) used by the field kernels.
 struct TargetOrder {
   int32_t n = 0;
   int32_t *perm = nullptr;     // sorted position -> caller index
@@ -205,7 +204,7 @@ obem_status pair_once_setup(obem_ctx *ctx, int n, int sym_tiles, const double *t
 void launch_sym_reduce(obem_ctx *ctx, int n, int sbsz, int ns, int d0, int dcnt, const float *Pi, const float *Pj,
                        double *acc);
 
-// Copy of the point sources in (charge sign, Morton) order with per-256-tile
+// Copy of the point sources in (charge sign, Hilbert) order with per-256-tile
 // boxes (field.hip); inv (caller index -> position) when asked for.  Uses the
 // target-ordering workspace: call before order_targets of the targets.
 struct SourceOrder {
@@ -273,7 +272,7 @@ __device__ __forceinline__ void map_interp(const MapDev &g, double x, double y, 
 }
 // Checks a caller's map (sizes >= 2, spacing > 0, device arrays) and copies it.
 bool map_dev(const obem_field_map *m, MapDev *g);
-// Map field at the Morton-sorted targets into the accumulator (units 1/k_e,
+// Map field at the Hilbert-sorted targets into the accumulator (units 1/k_e,
 // V component 0), in place of the cell field.
 obem_status launch_map_acc(obem_ctx *ctx, const MapDev &g, const TargetOrder &to, double *acc);
 

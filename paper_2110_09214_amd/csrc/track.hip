@@ -679,7 +679,7 @@ __global__ __launch_bounds__(256) void k_scatter_nn(int n, const int32_t *__rest
   }
 }
 
-// Species key of the particles taken in the targets' Morton order.
+// Species key of the particles taken in the targets' Hilbert order.
 __global__ __launch_bounds__(256) void k_species_key(int n, const int32_t *__restrict__ perm,
                                                      const int8_t *__restrict__ sp, uint8_t *key, int32_t *idx) {
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -690,8 +690,8 @@ __global__ __launch_bounds__(256) void k_species_key(int n, const int32_t *__res
   }
 }
 
-// Source copy grouped by species, Morton order within a species (a stable
-// sort of the Morton-ordered particles by species): its 256-source tiles
+// Source copy grouped by species, Hilbert order within a species (a stable
+// sort of the Hilbert-ordered particles by species): its 256-source tiles
 // each carry one charge, which the pairwise kernel takes out of the inner
 // loop, and are spatially compact, so the nearest-partner search can skip
 // tiles farther than the recombination radius.
@@ -940,7 +940,7 @@ static inline int nbt(int64_t n) { return (int)((n + 255) / 256); }
 // from all charges still in the step (dead / status mask, may be NULL),
 // into E (3 x n, caller order).  With nn (int32 x n) also the nearest
 // opposite-species partner (within r_rec in mixed precision), caller index
-// or -1.  The sources are a copy ordered by species, then Morton.
+// or -1.  The sources are a copy ordered by species, then Hilbert.
 static obem_status step_field(obem_ctx *ctx, obem_meshh *mesh, const double *sigma, const MapDev *map,
                               const obem_particles *S, int n, const obem_step_params *p, const uint8_t *dead,
                               const int8_t *status, double *E, int32_t *nn) {

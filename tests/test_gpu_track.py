@@ -287,7 +287,7 @@ def test_full_size_cloud_step_invariants(ctx, orc):
     fo = torch.empty(3 * n, dtype=torch.float64, device="cuda")
     st = B.track_step(ctx, bm, parts, gas_s, p, counts, sig, rhs, field_out=fo)
     print("full-size step", st)
-    # the step's field (species/Morton source copy, partner search, far tiles
+    # the step's field (species/Hilbert source copy, partner search, far tiles
     # in the expanded form) against the oracle on sampled charges
     E_step = host(fo).reshape(3, n).T
     rows = np.random.default_rng(8).choice(n, 48, replace=False)
