@@ -1082,18 +1082,17 @@ extern "C" obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh
       const int ns = (n_t + sbsz - 1) / sbsz;
       const int hmax = ns / 2;
       if (hmax > 0) {
-        float *Pi = (float *)ws_get(ctx, WS_SYMI, sizeof(float) * 3 * kBwdSlots * (size_t)n_t);
-        float *Pj = (float *)ws_get(ctx, WS_SYMJ, sizeof(float) * 3 * kBwdSlots * (size_t)n_t);
-        if (!Pi || !Pj) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
         if (ctx->bwd_resident <= 0)
           ctx->bwd_resident = resident_workgroups(reinterpret_cast<const void *>(&k_pair_bwd_sym<kBwdTiles>), kT,
                                                   ctx->device);
-        for (int d0 = 1, dcnt = 0; d0 <= hmax; d0 += dcnt) {
-          dcnt = launch_slots(ns, hmax - d0 + 1, ctx->bwd_resident, kBwdSlots);
-          hipLaunchKernelGGL(k_pair_bwd_sym<kBwdTiles>, dim3(ns, dcnt), dim3(kT), 0, ctx->stream, n_t, so.x, so.y,
-                             so.z, so.q, wsrt, sb, dmask, dwpr, (float)(soft * soft), ns, d0, Pi, Pj);
-          launch_sym_reduce(ctx, n_t, sbsz, ns, d0, dcnt, Pi, Pj, gx);
-        }
+        const float soft2 = (float)(soft * soft);
+        st = run_pair_once(ctx, n_t, sbsz, ns, ctx->bwd_resident, kBwdSlots, gx,
+                           [&](int d0, int dcnt, float *pi, float *pj) {
+                             hipLaunchKernelGGL(k_pair_bwd_sym<kBwdTiles>, dim3(ns, dcnt), dim3(kT), 0, ctx->stream,
+                                                n_t, so.x, so.y, so.z, so.q, wsrt, sb, dmask, dwpr, soft2, ns, d0, pi,
+                                                pj);
+                           });
+        if (st) return st;
         OBEM_HIP(ctx, hipGetLastError());
       }
     }

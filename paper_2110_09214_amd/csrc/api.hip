@@ -204,6 +204,17 @@ __global__ __launch_bounds__(64) void k_tile_spheres(int n, const double *f, dou
   }
 }
 
+obem_status aux_stream(obem_ctx *ctx) {
+  if (ctx->aux) return OBEM_OK;
+  OBEM_HIP(ctx, hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+  for (int b = 0; b < 2; ++b) {
+    OBEM_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_slots[b], hipEventDisableTiming));
+    OBEM_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_free[b], hipEventDisableTiming));
+  }
+  OBEM_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+  return OBEM_OK;
+}
+
 }  // namespace obem
 
 using namespace obem;
@@ -289,6 +300,15 @@ obem_status obem_destroy(obem_ctx *ctx) {
     (void)hipEventDestroy(r.stop);
   }
   for (auto e : ctx->prof_pool) (void)hipEventDestroy(e);
+  if (ctx->aux) {
+    (void)hipStreamSynchronize(ctx->aux);
+    for (int b = 0; b < 2; ++b) {
+      if (ctx->ev_slots[b]) (void)hipEventDestroy(ctx->ev_slots[b]);
+      if (ctx->ev_free[b]) (void)hipEventDestroy(ctx->ev_free[b]);
+    }
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    (void)hipStreamDestroy(ctx->aux);
+  }
   if (ctx->work_dev) (void)hipFree(ctx->work_dev);
   for (auto &b : ctx->ws)
     if (b.p) (void)hipFree(b.p);

@@ -1625,32 +1625,27 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
     // of up to kSymSlots values of d (bounded partial buffers)
     const int hmax = ns / 2;
     if (hmax > 0) {
-      float *Pi = (float *)ws_get(ctx, WS_SYMI, sizeof(float) * 3 * kSymSlots * (size_t)n_t);
-      float *Pj = (float *)ws_get(ctx, WS_SYMJ, sizeof(float) * 3 * kSymSlots * (size_t)n_t);
-      if (!Pi || !Pj) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
       OBEM_PROF(ctx, "pair_once");
-      const int resident = sym_resident(ctx, nn);
-      for (int d0 = 1, dcnt = 0; d0 <= hmax; d0 += dcnt) {
-        // equal workgroups run in rounds: at 32 values of d and 1954
-        // super-blocks the last round of a launch held 64 of 1024
-        dcnt = launch_slots(ns, hmax - d0 + 1, resident, kSymSlots);
-        const dim3 g(ns, dcnt);
-        if (nn)
-          hipLaunchKernelGGL(k_pair_sym<true>, g, dim3(kThreads), 0, ctx->stream, n_t, sx, sy, sz, sq, tbox,
-                             nn_cut2d, sb, (float)(soft * soft), ns, d0, Pi, Pj);
-        else
-          hipLaunchKernelGGL(k_pair_sym<false>, g, dim3(kThreads), 0, ctx->stream, n_t, sx, sy, sz, sq, tbox,
-                             nn_cut2d, sb, (float)(soft * soft), ns, d0, Pi, Pj);
-        launch_sym_reduce(ctx, n_t, kSymSB, ns, d0, dcnt, Pi, Pj, acc);
-      }
-      OBEM_HIP(ctx, hipGetLastError());
+      const float soft2 = (float)(soft * soft);
+      obem_status st = run_pair_once(ctx, n_t, kSymSB, ns, sym_resident(ctx, nn), kSymSlots, acc,
+                                     [&](int d0, int dcnt, float *pi, float *pj) {
+                                       const dim3 g(ns, dcnt);
+                                       if (nn)
+                                         hipLaunchKernelGGL(k_pair_sym<true>, g, dim3(kThreads), 0, ctx->stream, n_t,
+                                                            sx, sy, sz, sq, tbox, nn_cut2d, sb, soft2, ns, d0, pi, pj);
+                                       else
+                                         hipLaunchKernelGGL(k_pair_sym<false>, g, dim3(kThreads), 0, ctx->stream, n_t,
+                                                            sx, sy, sz, sq, tbox, nn_cut2d, sb, soft2, ns, d0, pi, pj);
+                                     });
+      if (st) return st;
     }
   }
   return OBEM_OK;
 }
 
 // Up to 2^24 particles: the tile-pair mask takes at most 512 MB and the
-// partial slots 12.9 GB; larger sets keep the directed evaluation.
+// double-buffered partial slots 32 GB; larger sets keep the directed
+// evaluation.
 obem_status pair_once_setup(obem_ctx *ctx, int n, int sym_tiles, const double *tbox, bool nn, double cut2d,
                             double **sb, uint32_t **dmask, int *dwpr) {
   const int ns = (n + sym_tiles * kThreads - 1) / (sym_tiles * kThreads);
@@ -1667,9 +1662,48 @@ obem_status pair_once_setup(obem_ctx *ctx, int n, int sym_tiles, const double *t
   return OBEM_OK;
 }
 
-void launch_sym_reduce(obem_ctx *ctx, int n, int sbsz, int ns, int d0, int dcnt, const float *Pi, const float *Pj,
-                       double *acc) {
-  hipLaunchKernelGGL(k_sym_reduce, dim3(nblk(n)), dim3(256), 0, ctx->stream, n, sbsz, ns, d0, dcnt, Pi, Pj, acc);
+obem_status run_pair_once(obem_ctx *ctx, int n, int sbsz, int ns, int resident, int max_slots, double *acc,
+                          const std::function<void(int, int, float *, float *)> &launch) {
+  const int hmax = ns / 2;
+  if (hmax <= 0) return OBEM_OK;
+  // with more than one launch the slots are double-buffered: launch L's
+  // slots are added to acc on the second stream while launch L + 1
+  // evaluates into the other half (the additions stay in launch order, on
+  // one stream, so the result does not depend on the overlap)
+  const bool dbl = launch_slots(ns, hmax, resident, max_slots) < hmax;
+  const size_t half = 3 * (size_t)max_slots * n;
+  float *Pi = (float *)ws_get(ctx, WS_SYMI, sizeof(float) * half * (dbl ? 2 : 1));
+  float *Pj = (float *)ws_get(ctx, WS_SYMJ, sizeof(float) * half * (dbl ? 2 : 1));
+  if (!Pi || !Pj) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+  if (dbl) {
+    obem_status st = aux_stream(ctx);
+    if (st) return st;
+  }
+  int launch_no = 0;
+  for (int d0 = 1, dcnt = 0; d0 <= hmax; d0 += dcnt, ++launch_no) {
+    // equal workgroups run in rounds: at 32 values of d and 1954
+    // super-blocks the last round of a launch held 64 of 1024
+    dcnt = launch_slots(ns, hmax - d0 + 1, resident, max_slots);
+    const int b = dbl ? (launch_no & 1) : 0;
+    float *pi = Pi + b * half, *pj = Pj + b * half;
+    if (dbl && launch_no >= 2) OBEM_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_free[b], 0));
+    launch(d0, dcnt, pi, pj);
+    OBEM_HIP(ctx, hipGetLastError());
+    hipStream_t rs = ctx->stream;
+    if (dbl) {
+      OBEM_HIP(ctx, hipEventRecord(ctx->ev_slots[b], ctx->stream));
+      OBEM_HIP(ctx, hipStreamWaitEvent(ctx->aux, ctx->ev_slots[b], 0));
+      rs = ctx->aux;
+    }
+    hipLaunchKernelGGL(k_sym_reduce, dim3(nblk(n)), dim3(256), 0, rs, n, sbsz, ns, d0, dcnt, pi, pj, acc);
+    OBEM_HIP(ctx, hipGetLastError());
+    if (dbl) OBEM_HIP(ctx, hipEventRecord(ctx->ev_free[b], ctx->aux));
+  }
+  if (dbl) {
+    OBEM_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->aux));
+    OBEM_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
+  }
+  return OBEM_OK;
 }
 
 bool pair_once_applies(int64_t n, obem_precision prec, double soft, bool want_v) {

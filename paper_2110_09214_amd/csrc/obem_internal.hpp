@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -117,6 +118,10 @@ struct obem_ctx {
   void *rocblas = nullptr;   // rocblas_handle, created on first solve
   bool prof = false;         // per-kernel event timing
   int sym_resident = 0, sym_resident_nn = 0, bwd_resident = 0;  // pair-once workgroups resident at once (lazy)
+  // second stream (default priority) and events for the pair-once slot
+  // reductions, which run beside the next launch (lazy)
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_slots[2] = {}, ev_free[2] = {}, ev_join = nullptr;
   // pairwise work while profiling: device count of the directed kernel's
   // terms of pair-once calls (filled from the tile-pair mask), host counts of
   // the directed terms of the other calls and of the pair-once calls' n^2
@@ -138,6 +143,8 @@ struct obem_ctx {
 namespace obem {
 
 obem_status fail(obem_ctx *ctx, obem_status st, const char *fmt, ...);
+// create the context's second stream and its events on first use
+obem_status aux_stream(obem_ctx *ctx);
 obem_status hip_fail(obem_ctx *ctx, hipError_t e, const char *what, int line);
 // Ensure workspace slot `slot` holds at least `bytes`; returns device pointer or nullptr.
 void *ws_get(obem_ctx *ctx, int slot, size_t bytes);
@@ -199,10 +206,14 @@ bool pair_once_applies(int64_t n, obem_precision prec, double soft, bool want_v)
 // nn: also the pairs within the partner cut cut2d).  Workspace owned by ctx.
 obem_status pair_once_setup(obem_ctx *ctx, int n, int sym_tiles, const double *tbox, bool nn, double cut2d,
                             double **sb, uint32_t **dmask, int *dwpr);
-// Adds the FP32 partial slots of one pair-once launch (d = d0 .. d0 + dcnt - 1)
-// to the FP64 sums acc[3][n], in slot order; sbsz particles per super-block.
-void launch_sym_reduce(obem_ctx *ctx, int n, int sbsz, int ns, int d0, int dcnt, const float *Pi, const float *Pj,
-                       double *acc);
+// The launches of one pair-once evaluation over ns super-blocks of sbsz
+// particles: for d0 = 1 .. ns / 2 in steps of at most max_slots values of d
+// (sized to the resident workgroups), launch(d0, dcnt, Pi, Pj) evaluates
+// into FP32 partial slots on ctx->stream, and the slots are added to the FP64
+// sums acc[3][n] in slot order (on the second stream, beside the next
+// launch, when there is one).  Slot buffers from the workspace.
+obem_status run_pair_once(obem_ctx *ctx, int n, int sbsz, int ns, int resident, int max_slots, double *acc,
+                          const std::function<void(int, int, float *, float *)> &launch);
 
 // Copy of the point sources in (charge sign, Hilbert) order with per-256-tile
 // boxes (field.hip); inv (caller index -> position) when asked for.  Uses the
