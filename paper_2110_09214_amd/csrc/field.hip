@@ -564,6 +564,13 @@ __global__ __launch_bounds__(kThreads) void k_panel_near(int n_t, const double *
   }
   const double wc0 = 0.5 * (lo0 + hi0), wc1 = 0.5 * (lo1 + hi1), wc2 = 0.5 * (lo2 + hi2);
   const double wr = 0.5 * sqrt((hi0 - lo0) * (hi0 - lo0) + (hi1 - lo1) * (hi1 - lo1) + (hi2 - lo2) * (hi2 - lo2));
+  // the same sphere in the recentred FP32 frame, radius measured from its
+  // FP32 centre (widened by 1e-4 for the rounding)
+  const float fw0 = (float)(wc0 - c0), fw1 = (float)(wc1 - c1), fw2 = (float)(wc2 - c2);
+  float fwr = sqrtf(dist2f(r0, r1, r2, fw0, fw1, fw2));
+  for (int o = 32; o > 0; o >>= 1) fwr = fmaxf(fwr, __shfl_xor(fwr, o));
+  fwr *= 1.0001f;
+  const int lane = tid & 63;
   const int ntile = (N + kPT - 1) / kPT;
   double ex = 0.0, ey = 0.0, ez = 0.0, ev = 0.0;
   for (int t = 0; t < ntile; ++t) {
@@ -571,14 +578,30 @@ __global__ __launch_bounds__(kThreads) void k_panel_near(int n_t, const double *
     const double rs = wr + tiles[4 * t + 3];
     if (dx * dx + dy * dy + dz * dz > rs * rs) continue;  // wave-uniform
     const int k0 = t * kPT, cnt = min(kPT, N - k0);
-    for (int k = 0; k < cnt; ++k) {
-      const int kk = k0 + k;
-      const float g0 = (float)(f[(size_t)MF_GX * N + kk] - c0), g1 = (float)(f[(size_t)MF_GY * N + kk] - c1),
-                  g2 = (float)(f[(size_t)MF_GZ * N + kk] - c2);
+    // lane k holds cell k0 + k (centroid recentred to FP32 and the near
+    // limit, exactly as the far kernel stages them) and tests it once
+    // against the wave's sphere; only the cells some lane may see within
+    // 3 D (1 % wide) take the per-lane test
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f, lim = 0.f, dk = 0.f;
+    if (lane < cnt) {
+      const int kk = k0 + lane;
+      g0 = (float)(f[(size_t)MF_GX * N + kk] - c0);
+      g1 = (float)(f[(size_t)MF_GY * N + kk] - c1);
+      g2 = (float)(f[(size_t)MF_GZ * N + kk] - c2);
       const double D = f[(size_t)MF_DIAM * N + kk];
-      const float lim = (float)(kNearMixed * kNearMixed * D * D);
-      const bool nearp = active && dist2f(r0, r1, r2, g0, g1, g2) < lim;
+      lim = (float)(kNearMixed * kNearMixed * D * D);
+      dk = (float)D;
+    }
+    const float tw = sqrtf(dist2f(fw0, fw1, fw2, g0, g1, g2)) - fwr;
+    for (uint64_t m = __ballot(lane < cnt && tw < (float)(kNearMixed * 1.01) * dk); m; m &= m - 1ull) {
+      const int k = __builtin_ctzll(m);
+      const float h0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g0), k));
+      const float h1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g1), k));
+      const float h2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g2), k));
+      const float hl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lim), k));
+      const bool nearp = active && dist2f(r0, r1, r2, h0, h1, h2) < hl;
       if (__any(nearp)) {
+        const int kk = k0 + k;
         if (nearp) near_cell<WANT_V>(f, N, kk, sigma[kk], x0, x1, x2, ex, ey, ez, ev);
       }
     }
