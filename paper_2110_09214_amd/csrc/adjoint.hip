@@ -139,6 +139,60 @@ __device__ __forceinline__ void qpt_adj(float aw, float ex, float ey, float ez, 
   Zz = fmaf(z, ez, Zz);
 }
 
+// The M-point rule of one staged cell (M = 7, 6 or 3) at the recentred
+// target r, accumulated into u, A and Z (qpt_adj).
+template <int M>
+__device__ __forceinline__ void bwd_rule(const BCell &C, float r0, float r1, float r2, float wx, float wy, float wz,
+                                         float &u, float &A, float &Zx, float &Zy, float &Zz) {
+  if (M == 7) {
+    const float4 h = C.c[1];
+    float q[24];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      const float4 t = C.c[2 + m];
+      q[4 * m] = t.x;
+      q[4 * m + 1] = t.y;
+      q[4 * m + 2] = t.z;
+      q[4 * m + 3] = t.w;
+    }
+#pragma unroll
+    for (int m = 0; m < 7; ++m)
+      qpt_adj((m == 0) ? h.y : (m < 4 ? h.z : h.w), r0 - q[3 * m], r1 - q[3 * m + 1], r2 - q[3 * m + 2], wx, wy,
+              wz, u, A, Zx, Zy, Zz);
+  } else if (M == 6) {
+    const float4 t10 = C.c[10];
+    float q[18];
+    q[0] = t10.z;
+    q[1] = t10.w;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const float4 t = C.c[11 + m];
+      q[2 + 4 * m] = t.x;
+      q[3 + 4 * m] = t.y;
+      q[4 + 4 * m] = t.z;
+      q[5 + 4 * m] = t.w;
+    }
+    const float w1 = C.c[7].w, w2 = t10.y;
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+      qpt_adj(m < 3 ? w1 : w2, r0 - q[3 * m], r1 - q[3 * m + 1], r2 - q[3 * m + 2], wx, wy, wz, u, A, Zx, Zy, Zz);
+  } else {
+    const float aw = C.c[7].y;  // area / 3
+    float q[12];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const float4 t = C.c[8 + m];
+      q[4 * m] = t.x;
+      q[4 * m + 1] = t.y;
+      q[4 * m + 2] = t.z;
+      q[4 * m + 3] = t.w;
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+      qpt_adj(aw, r0 - q[3 * m], r1 - q[3 * m + 1], r2 - q[3 * m + 2], wx, wy, wz, u, A, Zx, Zy, Zz);
+  }
+}
+
 // The per-cell sums of w . IE over the workgroup's 256 targets go through
 // LDS: every thread stores its value for each cell of the tile, then 8
 // threads per cell add 32 targets each (FP32, fixed order) and the 8
@@ -169,6 +223,26 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
   // inactive lanes carry w = 0, so all their contributions vanish
   const float wx = active ? (float)ws[i] : 0.f, wy = active ? (float)ws[(size_t)n_t + i] : 0.f,
               wz = active ? (float)ws[2 * (size_t)n_t + i] : 0.f;
+  // the wave's sphere: centre of its targets' bounding box, radius the
+  // largest distance from it (widened by 1e-4 for the rounding)
+  float cw0, cw1, cw2, rw;
+  {
+    float lo0 = r0, lo1 = r1, lo2 = r2, hi0 = r0, hi1 = r1, hi2 = r2;
+    for (int o = 32; o > 0; o >>= 1) {
+      lo0 = fminf(lo0, __shfl_xor(lo0, o));
+      lo1 = fminf(lo1, __shfl_xor(lo1, o));
+      lo2 = fminf(lo2, __shfl_xor(lo2, o));
+      hi0 = fmaxf(hi0, __shfl_xor(hi0, o));
+      hi1 = fmaxf(hi1, __shfl_xor(hi1, o));
+      hi2 = fmaxf(hi2, __shfl_xor(hi2, o));
+    }
+    cw0 = 0.5f * (lo0 + hi0);
+    cw1 = 0.5f * (lo1 + hi1);
+    cw2 = 0.5f * (lo2 + hi2);
+    rw = sqrtf(dist2f(r0, r1, r2, cw0, cw1, cw2));
+    for (int o = 32; o > 0; o >>= 1) rw = fmaxf(rw, __shfl_xor(rw, o));
+    rw *= 1.0001f;
+  }
   float hx = 0, hy = 0, hz = 0, lx = 0, ly = 0, lz = 0;
   const int kb = blockIdx.y * cchunk, ke = min(N, kb + cchunk);
   for (int k0 = kb; k0 < ke; k0 += kPB) {
@@ -211,7 +285,55 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
     }
     __syncthreads();
     float px = 0.f, py = 0.f, pz = 0.f;
-    for (int k = 0; k < cnt; ++k) {
+    // each cell's rule for the whole wave from one test of the cell (lane k
+    // of the wave tests cell k) against the wave's sphere, as in the forward
+    // kernel; only the cells some target may see within 3 D take the
+    // per-lane test, which leaves the near pairs to k_panel_bwd_near
+    uint64_t m3, m6, m7, mnear;
+    {
+      const int k = tid & 63;
+      float t = 3.0e38f, Dk = 0.f;
+      if (k < cnt) {
+        const float4 g = T[k].c[0];
+        Dk = sqrtf(T[k].c[1].x) * (float)(1.0 / kFar3Mixed);
+        t = sqrtf(dist2f(cw0, cw1, cw2, g.x, g.y, g.z)) - rw;
+      }
+      const uint64_t f6 = __ballot(t < (float)(kFar3Mixed * 1.01) * Dk);
+      const uint64_t f7 = __ballot(t < (float)(kMid6Mixed * 1.01) * Dk);
+      mnear = __ballot(t < (float)(kNearMixed * 1.01) * Dk);
+      m3 = ((1ull << cnt) - 1ull) & ~f6;
+      m6 = f6 & ~f7;
+      m7 = f7 & ~mnear;
+    }
+#define BWD_CELL_END                                   \
+  {                                                    \
+    const float sg = T[k].c[7].z;                      \
+    const float sA = sg * A, s3 = -3.0f * sg;          \
+    px = fmaf(sA, wx, fmaf(s3, Zx, px));               \
+    py = fmaf(sA, wy, fmaf(s3, Zy, py));               \
+    pz = fmaf(sA, wz, fmaf(s3, Zz, pz));               \
+    U[k][tid] = u;                                     \
+  }
+    for (; m3; m3 &= m3 - 1ull) {
+      const int k = __builtin_ctzll(m3);
+      float u = 0.f, A = 0.f, Zx = 0.f, Zy = 0.f, Zz = 0.f;
+      bwd_rule<3>(T[k], r0, r1, r2, wx, wy, wz, u, A, Zx, Zy, Zz);
+      BWD_CELL_END
+    }
+    for (; m6; m6 &= m6 - 1ull) {
+      const int k = __builtin_ctzll(m6);
+      float u = 0.f, A = 0.f, Zx = 0.f, Zy = 0.f, Zz = 0.f;
+      bwd_rule<6>(T[k], r0, r1, r2, wx, wy, wz, u, A, Zx, Zy, Zz);
+      BWD_CELL_END
+    }
+    for (; m7; m7 &= m7 - 1ull) {
+      const int k = __builtin_ctzll(m7);
+      float u = 0.f, A = 0.f, Zx = 0.f, Zy = 0.f, Zz = 0.f;
+      bwd_rule<7>(T[k], r0, r1, r2, wx, wy, wz, u, A, Zx, Zy, Zz);
+      BWD_CELL_END
+    }
+    for (; mnear; mnear &= mnear - 1ull) {
+      const int k = __builtin_ctzll(mnear);
       const float4 g = T[k].c[0];
       const float R2 = dist2f(r0, r1, r2, g.x, g.y, g.z);
       const bool nearp = R2 < g.w;  // taken by k_panel_bwd_near in FP64
@@ -221,63 +343,15 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
       const bool need6 = (!nearp) && (R2 < h.x);
       float u = 0.f, A = 0.f, Zx = 0.f, Zy = 0.f, Zz = 0.f;
       if (__any(need7)) {
-        if (!nearp) {
-          float q[24];
-#pragma unroll
-          for (int m = 0; m < 6; ++m) {
-            const float4 t = T[k].c[2 + m];
-            q[4 * m] = t.x;
-            q[4 * m + 1] = t.y;
-            q[4 * m + 2] = t.z;
-            q[4 * m + 3] = t.w;
-          }
-#pragma unroll
-          for (int m = 0; m < 7; ++m)
-            qpt_adj((m == 0) ? h.y : (m < 4 ? h.z : h.w), r0 - q[3 * m], r1 - q[3 * m + 1], r2 - q[3 * m + 2], wx,
-                    wy, wz, u, A, Zx, Zy, Zz);
-        }
+        if (!nearp) bwd_rule<7>(T[k], r0, r1, r2, wx, wy, wz, u, A, Zx, Zy, Zz);
       } else if (__any(need6)) {
-        if (!nearp) {
-          const float4 t10 = T[k].c[10];
-          float q[18];
-          q[0] = t10.z;
-          q[1] = t10.w;
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const float4 t = T[k].c[11 + m];
-            q[2 + 4 * m] = t.x;
-            q[3 + 4 * m] = t.y;
-            q[4 + 4 * m] = t.z;
-            q[5 + 4 * m] = t.w;
-          }
-          const float w1 = T[k].c[7].w, w2 = t10.y;
-#pragma unroll
-          for (int m = 0; m < 6; ++m)
-            qpt_adj(m < 3 ? w1 : w2, r0 - q[3 * m], r1 - q[3 * m + 1], r2 - q[3 * m + 2], wx, wy, wz, u, A, Zx,
-                    Zy, Zz);
-        }
+        if (!nearp) bwd_rule<6>(T[k], r0, r1, r2, wx, wy, wz, u, A, Zx, Zy, Zz);
       } else if (!nearp) {
-        const float aw = T[k].c[7].y;  // area / 3
-        float q[12];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          const float4 t = T[k].c[8 + m];
-          q[4 * m] = t.x;
-          q[4 * m + 1] = t.y;
-          q[4 * m + 2] = t.z;
-          q[4 * m + 3] = t.w;
-        }
-#pragma unroll
-        for (int m = 0; m < 3; ++m)
-          qpt_adj(aw, r0 - q[3 * m], r1 - q[3 * m + 1], r2 - q[3 * m + 2], wx, wy, wz, u, A, Zx, Zy, Zz);
+        bwd_rule<3>(T[k], r0, r1, r2, wx, wy, wz, u, A, Zx, Zy, Zz);
       }
-      const float sg = T[k].c[7].z;
-      const float sA = sg * A, s3 = -3.0f * sg;
-      px = fmaf(sA, wx, fmaf(s3, Zx, px));
-      py = fmaf(sA, wy, fmaf(s3, Zy, py));
-      pz = fmaf(sA, wz, fmaf(s3, Zz, pz));
-      U[k][tid] = u;
+      BWD_CELL_END
     }
+#undef BWD_CELL_END
     neum(hx, lx, px);
     neum(hy, ly, py);
     neum(hz, lz, pz);
@@ -354,6 +428,15 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_near(int n_t, const double *__
   const double bc0 = 0.5 * (lo[0] + hi[0]), bc1 = 0.5 * (lo[1] + hi[1]), bc2 = 0.5 * (lo[2] + hi[2]);
   const double br = 0.5 * sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
                                (hi[2] - lo[2]) * (hi[2] - lo[2]));
+  // the same sphere in the recentred FP32 frame, radius measured from its
+  // FP32 centre over the workgroup (widened by 1e-4 for the rounding)
+  const float fb0 = (float)(bc0 - c0), fb1 = (float)(bc1 - c1), fb2 = (float)(bc2 - c2);
+  float fbr = sqrtf(dist2f(r0, r1, r2, fb0, fb1, fb2));
+  for (int o = 32; o > 0; o >>= 1) fbr = fmaxf(fbr, __shfl_xor(fbr, o));
+  if (lane == 0) red[wv] = (double)fbr;
+  __syncthreads();
+  fbr = (float)fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * 1.0001f;
+  __syncthreads();
   double nx = 0.0, ny = 0.0, nz = 0.0;
   const int ntile = (N + 63) / 64;
   for (int t = 0; t < ntile; ++t) {
@@ -361,12 +444,29 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_near(int n_t, const double *__
     const double rs = (br + tiles[4 * t + 3]) * (1.0 + 1e-5);
     if (dx * dx + dy * dy + dz * dz > rs * rs) continue;  // workgroup-uniform
     const int k0 = t * 64, cnt = min(64, N - k0);
-    for (int k = 0; k < cnt; ++k) {
-      const int kk = k0 + k;
-      const float g0 = (float)(f[(size_t)MF_GX * N + kk] - c0), g1 = (float)(f[(size_t)MF_GY * N + kk] - c1),
-                  g2 = (float)(f[(size_t)MF_GZ * N + kk] - c2);
+    // lane k of every wave holds cell k0 + k (centroid recentred to FP32 and
+    // the near limit, as the far kernel stages them) and tests it against the
+    // workgroup's sphere: the same values in every wave, so the mask of the
+    // cells some target may see within 3 D (1 % wide) is workgroup-uniform
+    float cg0 = 0.f, cg1 = 0.f, cg2 = 0.f, clim = 0.f, cdk = 0.f;
+    if (lane < cnt) {
+      const int kk = k0 + lane;
+      cg0 = (float)(f[(size_t)MF_GX * N + kk] - c0);
+      cg1 = (float)(f[(size_t)MF_GY * N + kk] - c1);
+      cg2 = (float)(f[(size_t)MF_GZ * N + kk] - c2);
       const double D = f[(size_t)MF_DIAM * N + kk];
-      const bool nearp = active && dist2f(r0, r1, r2, g0, g1, g2) < (float)(kNearMixed * kNearMixed * D * D);
+      clim = (float)(kNearMixed * kNearMixed * D * D);
+      cdk = (float)D;
+    }
+    const float tw = sqrtf(dist2f(fb0, fb1, fb2, cg0, cg1, cg2)) - fbr;
+    for (uint64_t m = __ballot(lane < cnt && tw < (float)(kNearMixed * 1.01) * cdk); m; m &= m - 1ull) {
+      const int k = __builtin_ctzll(m);
+      const int kk = k0 + k;
+      const float g0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cg0), k));
+      const float g1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cg1), k));
+      const float g2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cg2), k));
+      const float gl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(clim), k));
+      const bool nearp = active && dist2f(r0, r1, r2, g0, g1, g2) < gl;
       if (!__syncthreads_or(nearp)) continue;
       double un = 0.0;
       if (nearp) {
