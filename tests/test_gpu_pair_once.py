@@ -6,10 +6,13 @@ the antisymmetry of the softened pair term of eq. (nbody).
 Checked at every particle against the oracle, side by side with the
 directed evaluation of the same call with the potential requested (which
 never takes the pair-once path), and for run-to-run bit equality.  The
-sizes are ragged (a last super-block of one particle, partial tiles, two
-launches of the slot loop), the charges mix both signs and zeros (the
-general form with both charges per pair) and one sign only (charges out of
-the loop)."""
+sizes are ragged (a last super-block of one particle, partial tiles), the
+charges mix both signs and zeros (the general form with both charges per
+pair) and one sign only (charges out of the loop).  Above about 164k
+particles the values of d take more than one launch, and the partial slots
+of each launch are added on a second stream while the next launch runs:
+checked at 200,003 particles for bit-equal repeats, against the directed
+evaluation at every particle and against the oracle on a sample."""
 import numpy as np
 import pytest
 import torch
@@ -67,6 +70,60 @@ def test_pair_once_against_directed_and_oracle(ctx, orc, n, kind):
     assert err_o <= 1e-5
     assert err_do <= 1e-5
     assert e_w1 <= 2e-5 and e_wd <= 2e-5
+
+
+@pytest.mark.parametrize("kind", ["both", "electrons"])
+def test_pair_once_several_launches(ctx, orc, kind):
+    """200,003 particles: 98 super-blocks, 49 values of d in two launches
+    (double-buffered slots, reductions on the second stream)."""
+    n = 200_003
+    x, q = _cloud(n, 77, kind)
+    X, Q = dev(x), dev(q)
+    E1 = host(B.field_eval(ctx, None, None, X, Q, X, 1e-7, B.OBEM_MIXED, tgt_is_src=True))
+    E1b = host(B.field_eval(ctx, None, None, X, Q, X, 1e-7, B.OBEM_MIXED, tgt_is_src=True))
+    assert np.array_equal(E1, E1b)
+    Ed, _ = B.field_eval(ctx, None, None, X, Q, X, 1e-7, B.OBEM_MIXED, tgt_is_src=True, want_v=True)
+    Ed = host(Ed)
+    err_d = rel_l2(E1, Ed)
+    # the oracle on 256 sampled particles (with the softening the self term
+    # is exactly zero, so the sample needs no exclusion)
+    ii = np.random.default_rng(5).choice(n, 256, replace=False)
+    ref = orc.pair_field(x[ii], x, q, 1e-7)
+    err_o = rel_l2(E1[ii], ref)
+    err_do = rel_l2(Ed[ii], ref)
+    print(f"pair-once n={n} {kind}: vs directed {err_d:.3g} (all particles); on 256 sampled: vs oracle "
+          f"{err_o:.3g} (directed {err_do:.3g})")
+    assert err_d <= 1e-5
+    assert err_o <= 1e-5 and err_do <= 1e-5
+
+
+def test_pair_once_adjoint_several_launches(ctx, orc):
+    """The pair-once adjoint over two launches (100,003 particles in 98
+    super-blocks of 1024, reductions on the second stream): bit-equal
+    repeats, and the gradient at every particle against the oracle for a
+    weight w that is zero outside 128 sampled particles S.  Then
+    dL/dx_k = [k in S] sum_j q_j J(x_k - x_j) w_k - q_k sum_(i in S) J(x_i - x_k) w_i,
+    which the oracle gives as its target gradient (S as targets) plus its
+    source gradient (all particles as sources) at O(|S| n) cost; the
+    softened self pair of a sampled particle enters both with opposite signs."""
+    n = 100_003
+    x, q = _cloud(n, 91, "both")
+    ii = np.sort(np.random.default_rng(3).choice(n, 128, replace=False))
+    w = np.zeros_like(x)
+    w[ii] = np.random.default_rng(4).normal(size=(len(ii), 3))
+    _, g1, _ = B.field_eval_backward(ctx, None, None, dev(x), dev(q), dev(x), 1e-7, dev(w), B.OBEM_MIXED,
+                                     tgt_is_src=True)
+    _, g2, _ = B.field_eval_backward(ctx, None, None, dev(x), dev(q), dev(x), 1e-7, dev(w), B.OBEM_MIXED,
+                                     tgt_is_src=True)
+    g1 = host(g1)
+    assert np.array_equal(g1, host(g2))
+    gt, gs = orc.pair_backward(x[ii], x, q, 1e-7, w[ii], tgt_is_src=False)
+    ref = gs.copy()
+    ref[ii] += gt
+    err = rel_l2(g1, ref)
+    err_s = rel_l2(g1[ii], ref[ii])
+    print(f"pair-once adjoint n={n}, w on 128 particles: rel L2 vs oracle {err:.3g} (sampled particles {err_s:.3g})")
+    assert err <= 1e-4 and err_s <= 1e-4
 
 
 @pytest.mark.parametrize("n,kind", [(4097, "electrons"), (8000, "both"), (9001, "both"), (9001, "with_zeros")])
