@@ -41,8 +41,8 @@ __device__ __forceinline__ void neum(float &s, float &c, float v) {
 // FP64 closed-form Jacobian of a unit-density cell contracted with w:
 //   gtw = G^T w = sum_e (m_e . w) grad f_e + (n . w) grad Omega
 // and ie_w = w . IE.  P[k] = vertex k minus the target.
-__device__ __forceinline__ void cell_grad_closed(const d3 P[3], d3 n, double twoarea, d3 w, d3 &gtw,
-                                                 double &ie_w) {
+__device__ __forceinline__ void cell_grad_closed(const d3 P[3], d3 n, double twoarea, const CellEdges &E, d3 w,
+                                                 d3 &gtw, double &ie_w) {
   double R[3] = {norm3(P[0]), norm3(P[1]), norm3(P[2])};
   double h = -dot3(P[0], n);
   double num = twoarea * h;
@@ -58,10 +58,8 @@ __device__ __forceinline__ void cell_grad_closed(const d3 P[3], d3 n, double two
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     const int e1 = (e + 1) % 3;
-    d3 t = P[e1] - P[e];
-    const double L = norm3(t);
-    t = t * (1.0 / L);
-    const d3 m = cross3(t, n);
+    const d3 t = E.t[e], m = E.m[e];
+    const double L = E.L[e];
     double lm, R0sq;
     const double f = edge_log(P[e], R[e], R[e1], t, L, &lm, &R0sq);
     const double lp = lm + L;
@@ -476,7 +474,7 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_near(int n_t, const double *__
         P[2] = mk3(f[(size_t)MF_CX * N + kk] - x0, f[(size_t)MF_CY * N + kk] - x1, f[(size_t)MF_CZ * N + kk] - x2);
         const d3 nn = mk3(f[(size_t)MF_NX * N + kk], f[(size_t)MF_NY * N + kk], f[(size_t)MF_NZ * N + kk]);
         d3 g;
-        cell_grad_closed(P, nn, 2.0 * f[(size_t)MF_AREA * N + kk], w, g, un);
+        cell_grad_closed(P, nn, 2.0 * f[(size_t)MF_AREA * N + kk], cell_edges(f, N, kk), w, g, un);
         const double sg = sigma[kk];
         nx = fma(sg, g.x, nx);
         ny = fma(sg, g.y, ny);
@@ -527,7 +525,7 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_fp64(int n_t, const double *__
           P[1] = mk3(f[(size_t)MF_BX * N + kk] - x0, f[(size_t)MF_BY * N + kk] - x1, f[(size_t)MF_BZ * N + kk] - x2);
           P[2] = mk3(f[(size_t)MF_CX * N + kk] - x0, f[(size_t)MF_CY * N + kk] - x1, f[(size_t)MF_CZ * N + kk] - x2);
           const d3 nn = mk3(f[(size_t)MF_NX * N + kk], f[(size_t)MF_NY * N + kk], f[(size_t)MF_NZ * N + kk]);
-          cell_grad_closed(P, nn, 2.0 * f[(size_t)MF_AREA * N + kk], w, g, u);
+          cell_grad_closed(P, nn, 2.0 * f[(size_t)MF_AREA * N + kk], cell_edges(f, N, kk), w, g, u);
         }
       }
       if (__any(quad)) {

@@ -175,6 +175,21 @@ __global__ __launch_bounds__(256) void k_mesh_derive(int n, double *f, const int
     F(MF_Q6 + 3 * q + 1) = p.y;
     F(MF_Q6 + 3 * q + 2) = p.z;
   }
+  // edge data of the closed form: unit tangent, length, t x n
+  const d3 v[3] = {a, b, c};
+  for (int e = 0; e < 3; ++e) {
+    d3 t = v[(e + 1) % 3] - v[e];
+    const double Le = norm3(t);
+    t = t * (1.0 / Le);
+    const d3 m = cross3(t, nn);
+    F(MF_T + 3 * e) = t.x;
+    F(MF_T + 3 * e + 1) = t.y;
+    F(MF_T + 3 * e + 2) = t.z;
+    F(MF_EL + e) = Le;
+    F(MF_M + 3 * e) = m.x;
+    F(MF_M + 3 * e + 1) = m.y;
+    F(MF_M + 3 * e + 2) = m.z;
+  }
 }
 
 // Zone bounding spheres of consecutive 64-cell tiles: centre = mean

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_bem_assemble(int N, const double *__res
         P[1] = mk3(f[(size_t)MF_BX * N + j] - x0, f[(size_t)MF_BY * N + j] - x1, f[(size_t)MF_BZ * N + j] - x2);
         P[2] = mk3(f[(size_t)MF_CX * N + j] - x0, f[(size_t)MF_CY * N + j] - x1, f[(size_t)MF_CZ * N + j] - x2);
         const d3 n = mk3(f[(size_t)MF_NX * N + j], f[(size_t)MF_NY * N + j], f[(size_t)MF_NZ * N + j]);
-        cell_closed_form<true>(P, n, 2.0 * f[(size_t)MF_AREA * N + j], ie, iv);
+        cell_closed_form<true>(P, n, 2.0 * f[(size_t)MF_AREA * N + j], cell_edges(f, N, j), ie, iv);
       }
       val = dd ? coef * dot3(ni, ie) : coef * iv;
     }

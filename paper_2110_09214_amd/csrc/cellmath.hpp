@@ -42,23 +42,38 @@ __device__ __forceinline__ double edge_log(d3 Pm, double Rm, double Rp, d3 t, do
   double R0sq = dot3(tx, tx);
   double s = lp + lm, Rs = Rp + Rm;
   double f;
+  // L (1 +- s/Rs) / den as one quotient: L (Rs +- s) / (Rs den), where
+  // Rs +- s adds two non-negative terms
   if (s >= 0.0) {
-    double den = (lm >= 0.0) ? (Rm + lm) : R0sq / (Rm - lm);
-    f = log1p(L * (1.0 + s / Rs) / den);
+    if (lm >= 0.0)
+      f = log1p(L * (Rs + s) / (Rs * (Rm + lm)));
+    else
+      f = log1p(L * (Rs + s) * (Rm - lm) / (Rs * R0sq));
   } else {
-    double den = (lp <= 0.0) ? (Rp - lp) : R0sq / (Rp + lp);
-    f = log1p(L * (1.0 - s / Rs) / den);
+    if (lp <= 0.0)
+      f = log1p(L * (Rs - s) / (Rs * (Rp - lp)));
+    else
+      f = log1p(L * (Rs - s) * (Rp + lp) / (Rs * R0sq));
   }
   if (lm_out) *lm_out = lm;
   if (R0sq_out) *R0sq_out = R0sq;
   return f;
 }
 
+// Edge data of a cell, made once per cell when the mesh is bound: unit
+// tangent t_e of edge e (vertex e to vertex e + 1), its length and the
+// in-plane outward normal m_e = t_e x n.
+struct CellEdges {
+  d3 t[3], m[3];
+  double L[3];
+};
+
 // Closed form in FP64.  P[k] = vertex k minus the target; n = unit normal;
 // twoarea = |(b-a)x(c-a)|.  A target exactly in the plane gets Omega = 0 (the
 // principal value of the normal field).
 template <bool WANT_V>
-__device__ __forceinline__ void cell_closed_form(const d3 P[3], d3 n, double twoarea, d3 &IE, double &IV) {
+__device__ __forceinline__ void cell_closed_form(const d3 P[3], d3 n, double twoarea, const CellEdges &E, d3 &IE,
+                                                 double &IV) {
   double R[3] = {norm3(P[0]), norm3(P[1]), norm3(P[2])};
   double h = -dot3(P[0], n);
   double num = twoarea * h;
@@ -73,13 +88,9 @@ __device__ __forceinline__ void cell_closed_form(const d3 P[3], d3 n, double two
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     const int e1 = (e + 1) % 3;
-    d3 t = P[e1] - P[e];
-    double L = norm3(t);
-    t = t * (1.0 / L);
-    d3 m = cross3(t, n);
-    double f = edge_log(P[e], R[e], R[e1], t, L, nullptr, nullptr);
-    IE = IE + m * f;
-    if (WANT_V) IV += dot3(m, P[e]) * f;
+    double f = edge_log(P[e], R[e], R[e1], E.t[e], E.L[e], nullptr, nullptr);
+    IE = IE + E.m[e] * f;
+    if (WANT_V) IV += dot3(E.m[e], P[e]) * f;
   }
 }
 

@@ -346,7 +346,7 @@ __device__ __forceinline__ void near_cell(const double *__restrict__ f, int N, i
   double twoarea = 2.0 * f[MF_AREA * (size_t)N + k];
   d3 IE;
   double IV;
-  cell_closed_form<WANT_V>(P, n, twoarea, IE, IV);
+  cell_closed_form<WANT_V>(P, n, twoarea, cell_edges(f, N, k), IE, IV);
   ex = fma(sig, IE.x, ex);
   ey = fma(sig, IE.y, ey);
   ez = fma(sig, IE.z, ez);
@@ -625,6 +625,14 @@ struct CellF64 {
   double g[3], lim, q[21], w[7];
 };
 
+// The value of lane k (wave-uniform k) of a double.
+__device__ __forceinline__ double readlane_f64(double v, int k) {
+  const unsigned long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, k);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), k);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps
 // y <- y + y (1/2 - x/2 y^2) (quadratic convergence; a few ulp at the end).
 __device__ __forceinline__ double rsqrt_f64(double x) {
@@ -726,11 +734,26 @@ __global__ __launch_bounds__(kThreads) void k_panel_fp64_near(int n_t, const dou
     const double rs = (wr + tiles[4 * t + 3]) * (1.0 + 1e-9);
     if (dx * dx + dy * dy + dz * dz > rs * rs) continue;  // wave-uniform
     const int k0 = t * 64, cnt = min(64, N - k0);
-    for (int k = 0; k < cnt; ++k) {
+    // lane k holds cell k0 + k and tests it once against the wave's sphere
+    // (0.1 % wide); only the cells some lane may see within 48 D take the
+    // per-lane test, on the same FP64 values as the far kernel's
+    const int lane = threadIdx.x & 63;
+    double cg0 = 0.0, cg1 = 0.0, cg2 = 0.0, cD = 0.0;
+    bool flag = false;
+    if (lane < cnt) {
+      const int kk = k0 + lane;
+      cg0 = f[(size_t)MF_GX * N + kk];
+      cg1 = f[(size_t)MF_GY * N + kk];
+      cg2 = f[(size_t)MF_GZ * N + kk];
+      cD = f[(size_t)MF_DIAM * N + kk];
+      const double u0 = cg0 - wc0, u1 = cg1 - wc1, u2 = cg2 - wc2;
+      flag = sqrt(u0 * u0 + u1 * u1 + u2 * u2) - wr < kQuadFp64 * 1.001 * cD;
+    }
+    for (uint64_t m = __ballot(flag); m; m &= m - 1ull) {
+      const int k = __builtin_ctzll(m);
       const int kk = k0 + k;
-      const double gx = x0 - f[(size_t)MF_GX * N + kk], gy = x1 - f[(size_t)MF_GY * N + kk],
-                   gz = x2 - f[(size_t)MF_GZ * N + kk];
-      const double D = f[(size_t)MF_DIAM * N + kk];
+      const double gx = x0 - readlane_f64(cg0, k), gy = x1 - readlane_f64(cg1, k), gz = x2 - readlane_f64(cg2, k);
+      const double D = readlane_f64(cD, k);
       const bool nearp = active && !(fma(gx, gx, fma(gy, gy, gz * gz)) >= kQuadFp64 * kQuadFp64 * D * D);
       if (__any(nearp)) {
         if (nearp) near_cell<WANT_V>(f, N, kk, sigma[kk], x0, x1, x2, ex, ey, ez, ev);

@@ -35,7 +35,7 @@ __device__ __forceinline__ void infl_closed(const double *__restrict__ f, int N,
   const d3 n = mk3(f[(size_t)MF_NX * N + k], f[(size_t)MF_NY * N + k], f[(size_t)MF_NZ * N + k]);
   d3 IE;
   double IV;
-  cell_closed_form<true>(P, n, 2.0 * f[(size_t)MF_AREA * N + k], IE, IV);
+  cell_closed_form<true>(P, n, 2.0 * f[(size_t)MF_AREA * N + k], cell_edges(f, N, k), IE, IV);
   sv = fma(q, IV, sv);
   ex = fma(q, IE.x, ex);
   ey = fma(q, IE.y, ey);

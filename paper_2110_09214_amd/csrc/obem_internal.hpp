@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "obem.h"
+#include "cellmath.hpp"
 
 namespace obem {
 
@@ -70,8 +71,25 @@ enum MeshField {
   MF_Q7 = 19,            // 7 quadrature points x 3 coordinates (21 arrays)
   MF_Q3 = MF_Q7 + 21,    // 3 quadrature points x 3 coordinates (9 arrays)
   MF_Q6 = MF_Q3 + 9,     // 6 quadrature points x 3 coordinates (18 arrays)
-  MF_COUNT = MF_Q6 + 18
+  MF_T = MF_Q6 + 18,     // unit tangents of the edges a->b, b->c, c->a (9 arrays)
+  MF_EL = MF_T + 9,      // their lengths (3 arrays)
+  MF_M = MF_EL + 3,      // in-plane outward normals t_e x n (9 arrays)
+  MF_COUNT = MF_M + 9
 };
+
+namespace obem {
+// The edge data of cell k from the field-major mesh block f (N cells).
+__device__ __forceinline__ CellEdges cell_edges(const double *__restrict__ f, size_t N, int k) {
+  CellEdges E;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    E.t[e] = mk3(f[(MF_T + 3 * e) * N + k], f[(MF_T + 3 * e + 1) * N + k], f[(MF_T + 3 * e + 2) * N + k]);
+    E.m[e] = mk3(f[(MF_M + 3 * e) * N + k], f[(MF_M + 3 * e + 1) * N + k], f[(MF_M + 3 * e + 2) * N + k]);
+    E.L[e] = f[(MF_EL + e) * N + k];
+  }
+  return E;
+}
+}  // namespace obem
 
 struct obem_meshh {
   int64_t n = 0;
