@@ -533,16 +533,19 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
   }
 }
 
-// FP64 near zone (R < 3 D) of the mixed mode, added to the far-field result.
-// Each wave bounds its 64 targets by a sphere and skips whole 64-cell tiles
-// whose near-zone sphere (tile centre, max over cells of |c_k - centre| +
-// 3 D_k, slightly inflated) it does not meet; inside a tile the per-pair test
-// is the far kernel's FP32 test, so the two kernels partition the pairs.
+// FP64 near zone (R < 3 D) of the mixed mode, added to the far kernel's
+// partial sums of the same cell range (gridDim.y splits the cells as in the
+// far kernel, so small target sets still fill the chip).  Each wave bounds
+// its 64 targets by a sphere and skips whole 64-cell tiles whose near-zone
+// sphere (tile centre, max over cells of |c_k - centre| + 3 D_k, slightly
+// inflated) it does not meet; inside a tile the per-pair test is the far
+// kernel's FP32 test, so the two kernels partition the pairs.
 template <bool WANT_V>
 __global__ __launch_bounds__(kThreads) void k_panel_near(int n_t, const double *__restrict__ xs, int N,
                                                          const double *__restrict__ f,
                                                          const double *__restrict__ sigma,
-                                                         const double *__restrict__ tiles, double *acc) {
+                                                         const double *__restrict__ tiles, int cchunk,
+                                                         double *part) {
   const int tid = threadIdx.x;
   const int i0 = blockIdx.x * kThreads;
   const int i = i0 + tid;
@@ -571,9 +574,10 @@ __global__ __launch_bounds__(kThreads) void k_panel_near(int n_t, const double *
   for (int o = 32; o > 0; o >>= 1) fwr = fmaxf(fwr, __shfl_xor(fwr, o));
   fwr *= 1.0001f;
   const int lane = tid & 63;
-  const int ntile = (N + kPT - 1) / kPT;
+  // the cell range of split blockIdx.y (cchunk is a multiple of the tile)
+  const int tb = blockIdx.y * cchunk / kPT, te = (min(N, (blockIdx.y + 1) * cchunk) + kPT - 1) / kPT;
   double ex = 0.0, ey = 0.0, ez = 0.0, ev = 0.0;
-  for (int t = 0; t < ntile; ++t) {
+  for (int t = tb; t < te; ++t) {
     const double dx = wc0 - tiles[4 * t], dy = wc1 - tiles[4 * t + 1], dz = wc2 - tiles[4 * t + 2];
     const double rs = wr + tiles[4 * t + 3];
     if (dx * dx + dy * dy + dz * dz > rs * rs) continue;  // wave-uniform
@@ -607,6 +611,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_near(int n_t, const double *
     }
   }
   if (active) {
+    double *acc = part + (size_t)blockIdx.y * 4 * n_t;
     acc[i] += ex;
     acc[(size_t)n_t + i] += ey;
     acc[2 * (size_t)n_t + i] += ez;
@@ -702,14 +707,16 @@ __global__ __launch_bounds__(kThreads) void k_panel_fp64(int n_t, const double *
   }
 }
 
-// FP64 closed-form zone (R < 48 D), added to the far kernel's result.  Each
+// FP64 closed-form zone (R < 48 D), added to the far kernel's partial sums
+// of the same cell range (split by gridDim.y as in the far kernel).  Each
 // wave bounds its 64 targets by a sphere and visits the 64-cell tiles whose
 // zone sphere (centre, max_k |c_k - centre| + 48 D_k) it meets.
 template <bool WANT_V>
 __global__ __launch_bounds__(kThreads) void k_panel_fp64_near(int n_t, const double *__restrict__ xs, int N,
                                                               const double *__restrict__ f,
                                                               const double *__restrict__ sigma,
-                                                              const double *__restrict__ tiles, double *acc) {
+                                                              const double *__restrict__ tiles, int cchunk,
+                                                              double *part) {
   const int i = blockIdx.x * kThreads + threadIdx.x;
   const bool active = i < n_t;
   const int i0 = blockIdx.x * kThreads;
@@ -727,9 +734,10 @@ __global__ __launch_bounds__(kThreads) void k_panel_fp64_near(int n_t, const dou
   }
   const double wc0 = 0.5 * (lo0 + hi0), wc1 = 0.5 * (lo1 + hi1), wc2 = 0.5 * (lo2 + hi2);
   const double wr = 0.5 * sqrt((hi0 - lo0) * (hi0 - lo0) + (hi1 - lo1) * (hi1 - lo1) + (hi2 - lo2) * (hi2 - lo2));
-  const int ntile = (N + 63) / 64;
+  // the cell range of split blockIdx.y (cchunk is a multiple of the tile)
+  const int tb = blockIdx.y * cchunk / 64, te = (min(N, (blockIdx.y + 1) * cchunk) + 63) / 64;
   double ex = 0.0, ey = 0.0, ez = 0.0, ev = 0.0;
-  for (int t = 0; t < ntile; ++t) {
+  for (int t = tb; t < te; ++t) {
     const double dx = wc0 - tiles[4 * t], dy = wc1 - tiles[4 * t + 1], dz = wc2 - tiles[4 * t + 2];
     const double rs = (wr + tiles[4 * t + 3]) * (1.0 + 1e-9);
     if (dx * dx + dy * dy + dz * dz > rs * rs) continue;  // wave-uniform
@@ -761,6 +769,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_fp64_near(int n_t, const dou
     }
   }
   if (active) {
+    double *acc = part + (size_t)blockIdx.y * 4 * n_t;
     acc[i] += ex;
     acc[(size_t)n_t + i] += ey;
     acc[2 * (size_t)n_t + i] += ez;
@@ -798,7 +807,7 @@ obem_status launch_panel_field(obem_ctx *ctx, const obem_meshh *m, const double 
     part = (double *)ws_get(ctx, WS_PANEL, sizeof(double) * 4 * (size_t)n_t * ns);
     if (!part) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
   }
-  dim3 grid(bt), gsplit(bt, ns), block(kThreads);
+  dim3 gsplit(bt, ns), block(kThreads);
   OBEM_PROF(ctx, "panel");
 #define PANEL_FAR(K, V, ...) \
   hipLaunchKernelGGL(K<V>, gsplit, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, cchunk, part __VA_ARGS__)
@@ -807,22 +816,19 @@ obem_status launch_panel_field(obem_ctx *ctx, const obem_meshh *m, const double 
   } else {
     if (want_v) PANEL_FAR(k_panel_fp64, true); else PANEL_FAR(k_panel_fp64, false);
   }
+  // the near kernel of split y adds the closed-form pairs of the same cell
+  // range into the same slot (one writer per entry, after the far kernel),
+  // then the slots are added in split order
+#define PANEL_NEAR(K, V, T) \
+  hipLaunchKernelGGL(K<V>, gsplit, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, T, cchunk, part)
+  if (prec == OBEM_MIXED) {
+    if (want_v) PANEL_NEAR(k_panel_near, true, m->tiles); else PANEL_NEAR(k_panel_near, false, m->tiles);
+  } else {
+    if (want_v) PANEL_NEAR(k_panel_fp64_near, true, m->tiles48); else PANEL_NEAR(k_panel_fp64_near, false, m->tiles48);
+  }
+#undef PANEL_NEAR
 #undef PANEL_FAR
   if (ns > 1) hipLaunchKernelGGL(k_panel_reduce, dim3(nblk(n_t)), dim3(256), 0, ctx->stream, n_t, ns, part, acc);
-  if (prec == OBEM_MIXED) {
-    if (want_v)
-      hipLaunchKernelGGL(k_panel_near<true>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, m->tiles, acc);
-    else
-      hipLaunchKernelGGL(k_panel_near<false>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma, m->tiles,
-                         acc);
-  } else {
-    if (want_v)
-      hipLaunchKernelGGL(k_panel_fp64_near<true>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma,
-                         m->tiles48, acc);
-    else
-      hipLaunchKernelGGL(k_panel_fp64_near<false>, grid, block, 0, ctx->stream, n_t, to.xs, N, m->f, sigma,
-                         m->tiles48, acc);
-  }
   OBEM_HIP(ctx, hipGetLastError());
   return OBEM_OK;
 }
