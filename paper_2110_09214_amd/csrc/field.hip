@@ -1593,9 +1593,9 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
   const int bt = nblk(n_t);
   // about 128k workgroups (64 rounds of the 2048 resident ones), so that the
   // last workgroups to start are short and the chip drains quickly at the
-  // end; chunks >= 1024 sources
+  // end; chunks >= 512 sources
   int nsplit = (kSplitWorkgroups + bt - 1) / bt;
-  nsplit = std::max(1, std::min(nsplit, (n_s + 1023) / 1024));
+  nsplit = std::max(1, std::min(nsplit, (n_s + 511) / 512));
   nsplit = std::min(nsplit, 64);
   int chunk = (n_s + nsplit - 1) / nsplit;
   chunk = (chunk + kThreads - 1) / kThreads * kThreads;
@@ -1723,7 +1723,7 @@ obem_status run_pair_once(obem_ctx *ctx, int n, int sbsz, int ns, int resident, 
   // evaluates into the other half (the additions stay in launch order, on
   // one stream, so the result does not depend on the overlap)
   const bool dbl = launch_slots(ns, hmax, resident, max_slots) < hmax;
-  const size_t half = 3 * (size_t)max_slots * n;
+  const size_t half = 3 * (size_t)std::min(max_slots, hmax) * n;
   float *Pi = (float *)ws_get(ctx, WS_SYMI, sizeof(float) * half * (dbl ? 2 : 1));
   float *Pj = (float *)ws_get(ctx, WS_SYMJ, sizeof(float) * half * (dbl ? 2 : 1));
   if (!Pi || !Pj) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");

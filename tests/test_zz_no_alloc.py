@@ -2,7 +2,8 @@
 that cannot allocate) against field_eval through the C ABI: two calls in a
 row on one context, the second with a smaller input, with cells and charges
 in both precisions (the mixed one large enough for the pair-once
-evaluation), then the size limit."""
+evaluation), the largest call (OBEM_NOALLOC_MAX_POINTS charges in a 40,776-cell
+mesh), then the size limit."""
 import ctypes as C
 
 import numpy as np
@@ -55,6 +56,26 @@ def test_noalloc_matches_field_eval_twice(ctx, prec):
     assert st == 0
     E1 = B.field_eval(ctx, None, None, X, Q, xt, 1e-7, prec)
     assert rel_l2(host(E0), host(E1)) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [B.OBEM_MIXED, B.OBEM_FP64])
+def test_noalloc_at_the_limit(ctx, prec):
+    """OBEM_NOALLOC_MAX_POINTS charges (targets = sources) in the 40,776-cell
+    GEM cell: the workspace of the largest call fits the static array."""
+    m = W.gem_cell_mesh()
+    bm = bind(ctx, m)
+    sig = dev(synthetic_sigma(m))
+    n = 16384
+    rng = np.random.default_rng(23)
+    x = rng.normal(size=(n, 3)) * 3e-5 + np.array([0, 0, 2e-4])
+    q = rng.choice([-1.0, 1.0], size=n) * W.E_CHARGE
+    X, Q = dev(x), dev(q)
+    st, E0 = _noalloc(ctx, bm, sig, X, Q, X, 1e-7, prec, True)
+    assert st == 0, ctx.lib.obem_last_error(ctx.h)
+    E1 = B.field_eval(ctx, bm, sig, X, Q, X, 1e-7, prec, tgt_is_src=True)
+    err = rel_l2(host(E0), host(E1))
+    print(f"noalloc at the limit, prec {prec}: rel L2 vs field_eval {err:.3g}")
+    assert err <= TOL[prec]
 
 
 def test_noalloc_rejects_sizes_beyond_the_limit(ctx):
