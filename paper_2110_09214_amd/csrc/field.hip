@@ -795,9 +795,9 @@ obem_status launch_panel_field(obem_ctx *ctx, const obem_meshh *m, const double 
   if (n_t == 0) return OBEM_OK;
   const int N = (int)m->n;
   const int bt = nblk(n_t);
-  // cell ranges of >= 256 cells (a multiple of both LDS tiles), about
+  // cell ranges of >= 64 cells (a multiple of both LDS tiles), about
   // kSplitWorkgroups workgroups in all
-  int ns = std::max(1, std::min((kSplitWorkgroups + bt - 1) / bt, (N + 255) / 256));
+  int ns = std::max(1, std::min((kSplitWorkgroups + bt - 1) / bt, (N + 63) / 64));
   ns = std::min(ns, 64);
   int cchunk = (N + ns - 1) / ns;
   cchunk = (cchunk + 63) / 64 * 64;
