@@ -205,9 +205,14 @@ obem_status bem_influence(obem_ctx *ctx, const obem_meshh *mesh, int64_t n_src, 
  * With OBEM_TGT_IS_SRC, OBEM_MIXED, soft > 0, no potential and 4097 to 2^24
  * charges, the pairwise sum evaluates every unordered pair of charges in
  * different 2048-charge blocks once for both (the pair term is
- * antisymmetric); its FP32 partial sums take 768 n bytes of context
- * workspace (3.1 GB at n = 4M), its tile-pair mask (n / 256)^2 / 8 bytes, and
- * the partial sums are added in FP64 in a fixed order.
+ * antisymmetric); its FP32 partial sums take up to 960 n bytes of context
+ * workspace per launch of up to 40 block distances, twice that when the
+ * distances take more than one launch (7.7 GB at n = 4M), its tile-pair mask
+ * (n / 256)^2 / 8 bytes, and the partial sums are added in FP64 in a fixed
+ * order.  With more than one launch, a second stream of the context (default
+ * priority, created on first use) adds each launch's partial sums while the
+ * next launch runs; the caller's stream waits for it before the call
+ * returns, so the call stays ordered on the caller's stream.
  * track_step uses the same evaluation for its field. */
 obem_status field_eval(obem_ctx *ctx, const obem_meshh *mesh, const double *sigma, int64_t n_src,
                        const double *sx, const double *sy, const double *sz, const double *sq,
@@ -247,7 +252,8 @@ obem_status field_eval_noalloc(obem_ctx *ctx, const obem_meshh *mesh, const doub
  * no floating-point atomics); source tiles are recomputed, nothing is kept
  * from the forward call.  With OBEM_TGT_IS_SRC under the conditions of
  * field_eval's pair-once evaluation, the pairwise term J(d) a of each pair
- * of charges in different 1024-charge blocks is evaluated once for both. */
+ * of charges in different 1024-charge blocks is evaluated once for both
+ * (partial sums and the second stream as in field_eval). */
 obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh, const double *sigma,
                                 int64_t n_src, const double *sx, const double *sy, const double *sz,
                                 const double *sq, int64_t n_tgt, const double *tx, const double *ty,
