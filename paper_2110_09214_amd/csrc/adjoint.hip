@@ -384,17 +384,18 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
   }
 }
 
-// FP64 near zone of the mixed cell adjoint, added to gx and to gsp after the
-// far kernel (same workgroups, so gsp[b][k] is read and written by one
-// workgroup only).  The workgroup bounds its 256 targets by a sphere and
+// FP64 near zone of the mixed cell adjoint, added after the far kernel to
+// its position-gradient slot of the same cell range (gridDim.y splits the
+// cells as the far kernel does) and to gsp (same workgroups and cell ranges,
+// so gsp[b][k] is read and written by one workgroup only).  The workgroup bounds its 256 targets by a sphere and
 // visits the 64-cell tiles whose near-zone sphere (centre, max_k |c_k -
 // centre| + 3 D_k) it meets, with a relative margin for the FP32 test.
 __global__ __launch_bounds__(kT) void k_panel_bwd_near(int n_t, const double *__restrict__ xs,
                                                        const double *__restrict__ ws, int N,
                                                        const double *__restrict__ f,
                                                        const double *__restrict__ sigma,
-                                                       const double *__restrict__ tiles, int want_x, double *gx,
-                                                       double *gsp) {
+                                                       const double *__restrict__ tiles, int want_x, int cchunk,
+                                                       double *gxp, double *gsp) {
   __shared__ double box[4][6];
   __shared__ double red[4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -436,8 +437,9 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_near(int n_t, const double *__
   fbr = (float)fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * 1.0001f;
   __syncthreads();
   double nx = 0.0, ny = 0.0, nz = 0.0;
-  const int ntile = (N + 63) / 64;
-  for (int t = 0; t < ntile; ++t) {
+  // the cell range of split blockIdx.y (cchunk is a multiple of the tile)
+  const int tb = blockIdx.y * cchunk / 64, te = (min(N, (blockIdx.y + 1) * cchunk) + 63) / 64;
+  for (int t = tb; t < te; ++t) {
     const double dx = bc0 - tiles[4 * t], dy = bc1 - tiles[4 * t + 1], dz = bc2 - tiles[4 * t + 2];
     const double rs = (br + tiles[4 * t + 3]) * (1.0 + 1e-5);
     if (dx * dx + dy * dy + dz * dz > rs * rs) continue;  // workgroup-uniform
@@ -488,6 +490,7 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_near(int n_t, const double *__
     }
   }
   if (active && want_x) {
+    double *gx = gxp + (size_t)blockIdx.y * 3 * n_t;
     gx[i] += nx;
     gx[(size_t)n_t + i] += ny;
     gx[2 * (size_t)n_t + i] += nz;
@@ -1112,11 +1115,12 @@ extern "C" obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh
     if (!gsp) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed (%d x %d partials)", bt, N);
     OBEM_PROF(ctx, "panel_bwd");
     if (precision == OBEM_MIXED) {
-      // cell ranges of >= 256 cells, about kSplitWorkgroups workgroups in all
-      int ns = std::max(1, std::min((kSplitWorkgroups + bt - 1) / bt, (N + 255) / 256));
+      // cell ranges of >= 64 cells (whole 64-cell tiles of the near kernel),
+      // about kSplitWorkgroups workgroups in all
+      int ns = std::max(1, std::min((kSplitWorkgroups + bt - 1) / bt, (N + 63) / 64));
       ns = std::min(ns, 64);
       int cchunk = (N + ns - 1) / ns;
-      cchunk = (cchunk + kPB - 1) / kPB * kPB;
+      cchunk = (cchunk + 63) / 64 * 64;
       ns = (N + cchunk - 1) / cchunk;
       double *gxp = gx;
       if (ns > 1) {
@@ -1125,9 +1129,11 @@ extern "C" obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh
       }
       hipLaunchKernelGGL(k_panel_bwd_mixed, dim3(bt, ns), dim3(kT), 0, ctx->stream, n_t, to.xs, wsrt, N, mesh->f,
                          sigma, 1, cchunk, gxp, gsp);
+      // the near kernel of split y adds into the same slot (and into gsp for
+      // the cells of its range), then the slots are added in split order
+      hipLaunchKernelGGL(k_panel_bwd_near, dim3(bt, ns), dim3(kT), 0, ctx->stream, n_t, to.xs, wsrt, N, mesh->f,
+                         sigma, mesh->tiles, 1, cchunk, gxp, gsp);
       if (ns > 1) hipLaunchKernelGGL(k_sum_chunks3, dim3(bt), dim3(256), 0, ctx->stream, n_t, ns, gxp, 0, gx);
-      hipLaunchKernelGGL(k_panel_bwd_near, dim3(bt), dim3(kT), 0, ctx->stream, n_t, to.xs, wsrt, N, mesh->f, sigma,
-                         mesh->tiles, 1, gx, gsp);
     } else
       hipLaunchKernelGGL(k_panel_bwd_fp64, dim3(bt), dim3(kT), 0, ctx->stream, n_t, to.xs, wsrt, N, mesh->f, sigma, 1,
                          gx, gsp);
