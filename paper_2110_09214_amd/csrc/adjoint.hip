@@ -501,8 +501,8 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_near(int n_t, const double *__
 __global__ __launch_bounds__(kT) void k_panel_bwd_fp64(int n_t, const double *__restrict__ xs,
                                                        const double *__restrict__ ws, int N,
                                                        const double *__restrict__ f,
-                                                       const double *__restrict__ sigma, int want_x, double *gx,
-                                                       double *gsp) {
+                                                       const double *__restrict__ sigma, int want_x, int cchunk,
+                                                       double *gxp, double *gsp) {
   __shared__ double red[4][kPTb];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int i = blockIdx.x * kT + tid;
@@ -511,8 +511,10 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_fp64(int n_t, const double *__
   const double x0 = xs[ii], x1 = xs[(size_t)n_t + ii], x2 = xs[2 * (size_t)n_t + ii];
   const d3 w = active ? mk3(ws[i], ws[(size_t)n_t + i], ws[2 * (size_t)n_t + i]) : mk3(0, 0, 0);
   double gxx = 0, gyy = 0, gzz = 0;
-  for (int k0 = 0; k0 < N; k0 += kPTb) {
-    const int cnt = min(kPTb, N - k0);
+  // the cell range of split blockIdx.y
+  const int kb = blockIdx.y * cchunk, ke = min(N, kb + cchunk);
+  for (int k0 = kb; k0 < ke; k0 += kPTb) {
+    const int cnt = min(kPTb, ke - k0);
     for (int k = 0; k < cnt; ++k) {
       const int kk = k0 + k;
       const double dx = x0 - f[(size_t)MF_GX * N + kk], dy = x1 - f[(size_t)MF_GY * N + kk],
@@ -563,6 +565,7 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_fp64(int n_t, const double *__
     __syncthreads();
   }
   if (active && want_x) {
+    double *gx = gxp + (size_t)blockIdx.y * 3 * n_t;
     gx[i] = gxx;
     gx[(size_t)n_t + i] = gyy;
     gx[2 * (size_t)n_t + i] = gzz;
@@ -1134,9 +1137,22 @@ extern "C" obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh
       hipLaunchKernelGGL(k_panel_bwd_near, dim3(bt, ns), dim3(kT), 0, ctx->stream, n_t, to.xs, wsrt, N, mesh->f,
                          sigma, mesh->tiles, 1, cchunk, gxp, gsp);
       if (ns > 1) hipLaunchKernelGGL(k_sum_chunks3, dim3(bt), dim3(256), 0, ctx->stream, n_t, ns, gxp, 0, gx);
-    } else
-      hipLaunchKernelGGL(k_panel_bwd_fp64, dim3(bt), dim3(kT), 0, ctx->stream, n_t, to.xs, wsrt, N, mesh->f, sigma, 1,
-                         gx, gsp);
+    } else {
+      // cell ranges as in the mixed path (whole tiles of kPTb cells)
+      int ns = std::max(1, std::min((kSplitWorkgroups + bt - 1) / bt, (N + 63) / 64));
+      ns = std::min(ns, 64);
+      int cchunk = (N + ns - 1) / ns;
+      cchunk = (cchunk + 63) / 64 * 64;
+      ns = (N + cchunk - 1) / cchunk;
+      double *gxp = gx;
+      if (ns > 1) {
+        gxp = (double *)ws_get(ctx, WS_PANEL, sizeof(double) * 3 * (size_t)n_t * ns);
+        if (!gxp) return fail(ctx, OBEM_ENOMEM, "workspace allocation failed");
+      }
+      hipLaunchKernelGGL(k_panel_bwd_fp64, dim3(bt, ns), dim3(kT), 0, ctx->stream, n_t, to.xs, wsrt, N, mesh->f,
+                         sigma, 1, cchunk, gxp, gsp);
+      if (ns > 1) hipLaunchKernelGGL(k_sum_chunks3, dim3(bt), dim3(256), 0, ctx->stream, n_t, ns, gxp, 0, gx);
+    }
     OBEM_HIP(ctx, hipGetLastError());
     have_gx = true;
     if (want_sig) {
