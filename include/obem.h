@@ -205,9 +205,9 @@ obem_status bem_influence(obem_ctx *ctx, const obem_meshh *mesh, int64_t n_src, 
  * With OBEM_TGT_IS_SRC, OBEM_MIXED, soft > 0, no potential and 4097 to 2^24
  * charges, the pairwise sum evaluates every unordered pair of charges in
  * different 2048-charge blocks once for both (the pair term is
- * antisymmetric); its FP32 partial sums take up to 960 n bytes of context
- * workspace per launch of up to 40 block distances, twice that when the
- * distances take more than one launch (7.7 GB at n = 4M), its tile-pair mask
+ * antisymmetric); its FP32 partial sums take up to 1920 n bytes of context
+ * workspace per launch of up to 80 block distances, twice that when the
+ * distances take more than one launch (15.4 GB at n = 4M), its tile-pair mask
  * (n / 256)^2 / 8 bytes, and the partial sums are added in FP64 in a fixed
  * order.  With more than one launch, a second stream of the context (default
  * priority, created on first use) adds each launch's partial sums while the

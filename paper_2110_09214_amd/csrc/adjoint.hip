@@ -24,7 +24,7 @@ namespace obem {
 
 constexpr int kT = 256;
 constexpr int kBwdTiles = 4;   // tiles per super-block of the pair-once adjoint
-constexpr int kBwdSlots = 40;  // values of d per pair-once launch, at most
+constexpr int kBwdSlots = 80;  // values of d per pair-once launch, at most
 constexpr int kPTb = 64;
 
 static inline int nbk(int64_t n) { return (int)((n + kT - 1) / kT); }

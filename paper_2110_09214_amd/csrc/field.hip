@@ -1203,7 +1203,7 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
 // k_sym_reduce adds the slots to acc in order.
 constexpr int kSymTiles = 8;
 constexpr int kSymSB = kSymTiles * kThreads;  // particles per super-block
-constexpr int kSymSlots = 40;                 // values of d per launch, at most
+constexpr int kSymSlots = 80;                 // values of d per launch, at most
 
 template <bool NN>
 __global__ __launch_bounds__(kThreads, 4) void k_pair_sym(int n, const double *__restrict__ sx,

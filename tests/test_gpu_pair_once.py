@@ -8,11 +8,11 @@ directed evaluation of the same call with the potential requested (which
 never takes the pair-once path), and for run-to-run bit equality.  The
 sizes are ragged (a last super-block of one particle, partial tiles), the
 charges mix both signs and zeros (the general form with both charges per
-pair) and one sign only (charges out of the loop).  Above about 164k
-particles the values of d take more than one launch, and the partial slots
-of each launch are added on a second stream while the next launch runs:
-checked at 200,003 particles for bit-equal repeats, against the directed
-evaluation at every particle and against the oracle on a sample."""
+pair) and one sign only (charges out of the loop).  Above about 330k
+particles (165k in the adjoint) the values of d take more than one launch,
+and the partial slots of each launch are added on a second stream while the
+next launch runs: checked at 400,003 particles (200,003 in the adjoint) for
+bit-equal repeats and against the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -74,9 +74,9 @@ def test_pair_once_against_directed_and_oracle(ctx, orc, n, kind):
 
 @pytest.mark.parametrize("kind", ["both", "electrons"])
 def test_pair_once_several_launches(ctx, orc, kind):
-    """200,003 particles: 98 super-blocks, 49 values of d in two launches
+    """400,003 particles: 196 super-blocks, 98 values of d in two launches
     (double-buffered slots, reductions on the second stream)."""
-    n = 200_003
+    n = 400_003
     x, q = _cloud(n, 77, kind)
     X, Q = dev(x), dev(q)
     E1 = host(B.field_eval(ctx, None, None, X, Q, X, 1e-7, B.OBEM_MIXED, tgt_is_src=True))
@@ -98,7 +98,7 @@ def test_pair_once_several_launches(ctx, orc, kind):
 
 
 def test_pair_once_adjoint_several_launches(ctx, orc):
-    """The pair-once adjoint over two launches (100,003 particles in 98
+    """The pair-once adjoint over two launches (200,003 particles in 196
     super-blocks of 1024, reductions on the second stream): bit-equal
     repeats, and the gradient at every particle against the oracle for a
     weight w that is zero outside 128 sampled particles S.  Then
@@ -106,7 +106,7 @@ def test_pair_once_adjoint_several_launches(ctx, orc):
     which the oracle gives as its target gradient (S as targets) plus its
     source gradient (all particles as sources) at O(|S| n) cost; the
     softened self pair of a sampled particle enters both with opposite signs."""
-    n = 100_003
+    n = 200_003
     x, q = _cloud(n, 91, "both")
     ii = np.sort(np.random.default_rng(3).choice(n, 128, replace=False))
     w = np.zeros_like(x)
