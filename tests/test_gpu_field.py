@@ -181,3 +181,31 @@ def test_input_order_does_not_matter(ctx, orc, prec):
     print(f"input order, prec {prec}: permuted vs original {d:.3g}; vs oracle on 64 charges {err:.3g}")
     assert d <= (1e-12 if prec == B.OBEM_FP64 else 1e-6)
     assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [B.OBEM_FP64, B.OBEM_MIXED])
+def test_double_gem_start_full_size_sampled(ctx, orc, prec):
+    """The double-GEM run's first field at full size: the 200,000 electrons
+    released inside the holes of the upper foil (a tenth of the hole radius
+    from the walls) in the 60,752-cell mesh, targets = sources (the pair-once
+    path in mixed precision), smooth cell charges; 48 sampled electrons plus
+    the 16 nearest the hole walls against the oracle's sum over all cells and
+    all other electrons."""
+    m = W.double_gem_mesh()
+    bm = bind(ctx, m)
+    sig = synthetic_sigma(m)
+    x, sp = W.double_gem_avalanche_start()
+    q = np.full(len(x), -W.E_CHARGE)
+    E = host(B.field_eval(ctx, bm, dev(sig), dev(x), dev(q), dev(x), 1e-7, prec, tgt_is_src=True))
+    rng = np.random.default_rng(31)
+    geo = W.GemGeometry(m=10, n_r=5, n_cone=6)
+    cen = np.array(geo.hole_centres())
+    r = np.min(np.hypot(x[:, None, 0] - cen[None, :, 0], x[:, None, 1] - cen[None, :, 1]), axis=1)
+    tk = geo.t_kapton / 2
+    r_hole = np.where(np.abs(x[:, 2]) < tk, geo.r_inner + (geo.r_outer - geo.r_inner) * np.abs(x[:, 2]) / tk,
+                      geo.r_outer)
+    rows = np.concatenate([rng.choice(len(x), 48, replace=False), np.argsort(r_hole - r)[:16]])
+    ref = orc.panel_field(x[rows], m.a, m.b, m.c, sig) + orc.pair_field(x[rows], x, q, 1e-7)
+    err = rel_l2(E[rows], ref)
+    print(f"double GEM start, prec {prec}: rel L2 vs oracle on {len(rows)} electrons {err:.3g}")
+    assert err <= TOL[prec]
