@@ -53,9 +53,12 @@ typedef enum {
                       a 7-point rule; pairwise terms and sums in float64      */
   OBEM_MIXED = 1   /* cells nearer than 3 diameters: float64 closed-form
                       integrals.  Farther cells: float32 quadrature of the
-                      cell (7 points within 8 diameters, 6 or more within
-                      40, 3 or more beyond: a group of 64 targets takes the
-                      finest rule one of them may need).  Pairwise terms in
+                      cell (7 points within 6 diameters, 6 within 16, 4
+                      within 40, 3 beyond, each rule's truncation error
+                      below the float32 rounding floor; a group of 64
+                      targets takes the finest rule one of them may need;
+                      the adjoint and the influence keep 7 points within 8,
+                      6 within 40, 3 beyond).  Pairwise terms in
                       float32 from coordinates
                       recentred near the targets (float32 hi + lo pairs for
                       the sources near them, so close pairs keep their

@@ -175,6 +175,14 @@ __global__ __launch_bounds__(256) void k_mesh_derive(int n, double *f, const int
     F(MF_Q6 + 3 * q + 1) = p.y;
     F(MF_Q6 + 3 * q + 2) = p.z;
   }
+  const double bary4[3][3] = {{Rule4::b, Rule4::a, Rule4::a}, {Rule4::a, Rule4::b, Rule4::a},
+                              {Rule4::a, Rule4::a, Rule4::b}};
+  for (int q = 0; q < 3; ++q) {
+    d3 p = a * bary4[q][0] + b * bary4[q][1] + c * bary4[q][2];
+    F(MF_Q4 + 3 * q) = p.x;
+    F(MF_Q4 + 3 * q + 1) = p.y;
+    F(MF_Q4 + 3 * q + 2) = p.z;
+  }
   // edge data of the closed form: unit tangent, length, t x n
   const d3 v[3] = {a, b, c};
   for (int e = 0; e < 3; ++e) {

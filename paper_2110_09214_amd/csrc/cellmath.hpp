@@ -114,6 +114,13 @@ struct Rule6 {
   static constexpr double a2 = 0.091576213509771, b2 = 0.816847572980459, w2 = 0.109951743655322;
 };
 
+// Degree-3, 4-point rule on the triangle (Strang and Fix, An Analysis of the
+// Finite Element Method, 1973): the centroid with weight -27/48 and
+// (3/5, 1/5, 1/5) in its 3 permutations with weight 25/48.
+struct Rule4 {
+  static constexpr double a = 0.2, b = 0.6, wc = -27.0 / 48.0, wp = 25.0 / 48.0;
+};
+
 struct Rule7 {
   // a = (6 - sqrt 15)/21, b = (6 + sqrt 15)/21
   static constexpr double a = 0.10128650732345633880;

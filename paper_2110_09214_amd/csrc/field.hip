@@ -281,16 +281,19 @@ obem_status order_targets(obem_ctx *ctx, int64_t n64, const double *tx, const do
 // ---------------------------------------------------------------------------
 constexpr int kPT = 64;               // cells per LDS tile
 
-// One cell of an LDS tile, recentred FP32, as 16 float4 records read whole
+// One cell of an LDS tile, recentred FP32, as 19 float4 records read whole
 // (one address per cell, 128-bit LDS reads):
 //   c[0] = centroid, (3 D)^2          c[1] = (40 D)^2, area sigma {w0, wa, wb}
 //   c[2..7] = the 7 points of the degree-5 rule (21 floats), area sigma / 3,
-//             (8 D)^2, D
+//             (6 D)^2, D
 //   c[8..10] = the 3 points of the degree-2 rule (9 floats), area sigma
-//             {w1, w2} of the 6-point rule, 0
-//   c[11..15] = the 6 points of the degree-4 rule (18 floats), 0, 0
+//             {w1, w2} of the 6-point rule, (16 D)^2
+//   c[11..15] = the 6 points of the degree-4 rule (18 floats), area sigma
+//             {wc, wp} of the 4-point rule
+//   c[16..18] = the 3 outer points of the degree-3 rule (9 floats; its
+//             fourth point is the centroid), 0, 0, 0
 struct PanelCell {
-  float4 c[16];
+  float4 c[19];
 };
 
 // sum over the M rule points of w {e/|e|^3, 1/|e|}, e = target - point
@@ -395,23 +398,23 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
   for (int k0 = kb; k0 < ke; k0 += kPT) {
     const int cnt = min(kPT, ke - k0);
     __syncthreads();
-    // staging, coalesced along the cells: the 48 rule coordinates (7-, 3- and
-    // 6-point rules) of the 64 cells, then one thread per cell for centroid,
-    // limits and weights
-    for (int idx = tid; idx < 48 * kPT; idx += kThreads) {
+    // staging, coalesced along the cells: the 57 rule coordinates (7-, 3-, 6-
+    // and 4-point rules) of the 64 cells, then one thread per cell for
+    // centroid, limits and weights
+    for (int idx = tid; idx < 57 * kPT; idx += kThreads) {
       const int m = idx / kPT, k = idx % kPT;
       float v = 0.f;
-      const int src = (m < 21) ? MF_Q7 + m : (m < 30 ? MF_Q3 + (m - 21) : MF_Q6 + (m - 30));
+      const int src = (m < 21) ? MF_Q7 + m : (m < 30 ? MF_Q3 + (m - 21) : (m < 48 ? MF_Q6 + (m - 30) : MF_Q4 + (m - 48)));
       if (k < cnt) {
-        const int c = (m < 21 ? m : (m < 30 ? m - 21 : m - 30)) % 3;
+        const int c = (m < 21 ? m : (m < 30 ? m - 21 : (m < 48 ? m - 30 : m - 48))) % 3;
         v = (float)(f[(size_t)src * N + k0 + k] - (c == 0 ? c0 : (c == 1 ? c1 : c2)));
       }
-      reinterpret_cast<float *>(&T[k])[m < 21 ? 8 + m : (m < 30 ? 32 + (m - 21) : 44 + (m - 30))] = v;
+      reinterpret_cast<float *>(&T[k])[m < 21 ? 8 + m : (m < 30 ? 32 + (m - 21) : (m < 48 ? 44 + (m - 30) : 64 + (m - 48)))] = v;
     }
     if (tid < kPT) {
       const int k = tid;
       float4 g = make_float4(0.f, 0.f, 0.f, 0.f), h = g;
-      float w3 = 0.f, lim8 = 0.f, w61 = 0.f, w62 = 0.f, dk = 0.f;
+      float w3 = 0.f, lim7 = 0.f, lim6 = 0.f, w61 = 0.f, w62 = 0.f, w4c = 0.f, w4p = 0.f, dk = 0.f;
       if (k < cnt) {
         const int kk = k0 + k;
         const double D = f[(size_t)MF_DIAM * N + kk];
@@ -421,32 +424,38 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
         h = make_float4((float)(kFar3Mixed * kFar3Mixed * D * D), (float)(as * Rule7::w0), (float)(as * Rule7::wa),
                         (float)(as * Rule7::wb));
         w3 = (float)(as * (1.0 / 3.0));
-        lim8 = (float)(kMid6Mixed * kMid6Mixed * D * D);
+        lim7 = (float)(kFwd6 * kFwd6 * D * D);
+        lim6 = (float)(kFwd4 * kFwd4 * D * D);
         dk = (float)D;
         w61 = (float)(as * Rule6::w1);
         w62 = (float)(as * Rule6::w2);
+        w4c = (float)(as * Rule4::wc);
+        w4p = (float)(as * Rule4::wp);
       }
       float *rec = reinterpret_cast<float *>(&T[k]);
       T[k].c[0] = g;
       T[k].c[1] = h;
       rec[29] = w3;
-      rec[30] = lim8;
+      rec[30] = lim7;
       rec[31] = dk;
       rec[41] = w61;
       rec[42] = w62;
-      rec[43] = 0.f;
-      rec[62] = rec[63] = 0.f;
+      rec[43] = lim6;
+      rec[62] = w4c;
+      rec[63] = w4p;
+      rec[73] = rec[74] = rec[75] = 0.f;
     }
     __syncthreads();
     float px = 0.f, py = 0.f, pz = 0.f, pv = 0.f;
     // The rule of each cell for the whole wave, from one test per cell
     // against the wave's sphere: lane k tests cell k, and the ballots give
-    // the cells some lane may see within 40 D (6 points or finer), within
-    // 8 D (7 points) and within 3 D (the per-lane path, which leaves the near
-    // pairs to k_panel_near).  Thresholds 1 % wide of the per-lane ones, so
-    // that a cell not flagged near has no lane inside 3 D by the per-lane
-    // test, and a coarser rule is never taken where a lane needs a finer one.
-    uint64_t m3, m6, m7, mnear;
+    // the cells some lane may see within 40 D (4 points or finer), 16 D (6
+    // or finer), 6 D (7 points) and 3 D (the per-lane path, which leaves the
+    // near pairs to k_panel_near).  Thresholds 1 % wide of the per-lane
+    // ones, so that a cell not flagged near has no lane inside 3 D by the
+    // per-lane test, and a coarser rule is never taken where a lane needs a
+    // finer one.
+    uint64_t m3, m4, m6, m7, mnear;
     {
       const int k = tid & 63;
       float t = 3.0e38f, Dk = 0.f;
@@ -455,10 +464,12 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
         Dk = T[k].c[7].w;
         t = sqrtf(dist2f(cw0, cw1, cw2, g.x, g.y, g.z)) - rw;
       }
-      const uint64_t f6 = __ballot(t < (float)(kFar3Mixed * 1.01) * Dk);
-      const uint64_t f7 = __ballot(t < (float)(kMid6Mixed * 1.01) * Dk);
+      const uint64_t f4 = __ballot(t < (float)(kFar3Mixed * 1.01) * Dk);
+      const uint64_t f6 = __ballot(t < (float)(kFwd4 * 1.01) * Dk);
+      const uint64_t f7 = __ballot(t < (float)(kFwd6 * 1.01) * Dk);
       mnear = __ballot(t < (float)(kNearMixed * 1.01) * Dk);
-      m3 = (cnt == 64 ? ~0ull : ((1ull << cnt) - 1ull)) & ~f6;
+      m3 = (cnt == 64 ? ~0ull : ((1ull << cnt) - 1ull)) & ~f4;
+      m4 = f4 & ~f6;
       m6 = f6 & ~f7;
       m7 = f7 & ~mnear;
     }
@@ -469,6 +480,18 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
       const float w3 = T[k].c[7].y;
       const float w[3] = {w3, w3, w3};
       panel_points<3, WANT_V>(q, w, r0, r1, r2, px, py, pz, pv);
+    }
+    for (; m4; m4 &= m4 - 1ull) {
+      const int k = __builtin_ctzll(m4);
+      float q[15];
+      const float4 g = T[k].c[0];
+      q[0] = g.x;
+      q[1] = g.y;
+      q[2] = g.z;
+      load4<3>(&T[k].c[16], q + 3);
+      const float4 h15 = T[k].c[15];
+      const float w[4] = {h15.z, h15.w, h15.w, h15.w};
+      panel_points<4, WANT_V>(q, w, r0, r1, r2, px, py, pz, pv);
     }
     for (; m6; m6 &= m6 - 1ull) {
       const int k = __builtin_ctzll(m6);
@@ -492,11 +515,14 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
       const float R2 = dist2f(r0, r1, r2, g.x, g.y, g.z);
       const bool nearp = R2 < g.w;  // taken by k_panel_near in FP64
       const float4 h = T[k].c[1];
-      const float4 h7 = T[k].c[7];  // {.., area sigma / 3, (8 D)^2, D}
-      // the rule by distance (7 points within 8 D, 6 within 40 D, 3 beyond),
-      // taken for the whole wave at the finest rule one of its lanes needs
+      const float4 h7 = T[k].c[7];    // {.., area sigma / 3, (6 D)^2, D}
+      const float4 h10 = T[k].c[10];  // {.., w1, w2, (16 D)^2}
+      // the rule by distance (7 points within 6 D, 6 within 16 D, 4 within
+      // 40 D, 3 beyond), taken for the whole wave at the finest rule one of
+      // its lanes needs
       const bool need7 = (!nearp) && (R2 < h7.z);
-      const bool need6 = (!nearp) && (R2 < h.x);
+      const bool need6 = (!nearp) && (R2 < h10.w);
+      const bool need4 = (!nearp) && (R2 < h.x);
       if (__any(need7)) {
         if (!nearp) {
           float q[24];
@@ -508,9 +534,19 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
         if (!nearp) {
           float q[20];
           load4<5>(&T[k].c[11], q);
-          const float4 h10 = T[k].c[10];
           const float w[6] = {h10.y, h10.y, h10.y, h10.z, h10.z, h10.z};
           panel_points<6, WANT_V>(q, w, r0, r1, r2, px, py, pz, pv);
+        }
+      } else if (__any(need4)) {
+        if (!nearp) {
+          float q[15];
+          q[0] = g.x;
+          q[1] = g.y;
+          q[2] = g.z;
+          load4<3>(&T[k].c[16], q + 3);
+          const float4 h15 = T[k].c[15];
+          const float w[4] = {h15.z, h15.w, h15.w, h15.w};
+          panel_points<4, WANT_V>(q, w, r0, r1, r2, px, py, pz, pv);
         }
       } else if (!nearp) {
         float q[12];

@@ -34,6 +34,11 @@ constexpr double kKe = 1.0 / (4.0 * kPi * kEps0);
 constexpr double kNearMixed = 3.0;
 constexpr double kFar3Mixed = 40.0;  // 3-point rule from here on (mixed)
 constexpr double kMid6Mixed = 8.0;   // 6-point rule from here to kFar3Mixed (mixed)
+// Zones of the mixed cell field (forward kernel): the cheapest rule whose
+// truncation error stays below the FP32 rounding floor (about 2e-7): 7
+// points from 3 D, 6 from kFwd6 D, 4 from kFwd4 D, 3 from kFar3Mixed D.
+constexpr double kFwd6 = 6.0;
+constexpr double kFwd4 = 16.0;
 constexpr double kQuadFp64 = 48.0;
 // Workgroup count that the source- or charge-split launches aim at: 64
 // rounds of the 2048 workgroups resident at once (8 per CU, 256 CUs), which
@@ -71,7 +76,8 @@ enum MeshField {
   MF_Q7 = 19,            // 7 quadrature points x 3 coordinates (21 arrays)
   MF_Q3 = MF_Q7 + 21,    // 3 quadrature points x 3 coordinates (9 arrays)
   MF_Q6 = MF_Q3 + 9,     // 6 quadrature points x 3 coordinates (18 arrays)
-  MF_T = MF_Q6 + 18,     // unit tangents of the edges a->b, b->c, c->a (9 arrays)
+  MF_Q4 = MF_Q6 + 18,    // outer points of the 4-point rule x 3 coordinates (9 arrays)
+  MF_T = MF_Q4 + 9,      // unit tangents of the edges a->b, b->c, c->a (9 arrays)
   MF_EL = MF_T + 9,      // their lengths (3 arrays)
   MF_M = MF_EL + 3,      // in-plane outward normals t_e x n (9 arrays)
   MF_COUNT = MF_M + 9
