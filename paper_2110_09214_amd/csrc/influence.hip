@@ -57,14 +57,19 @@ constexpr int kCB = 8;   // cells per workgroup
 constexpr int kCS = 4;   // charges per thread and block
 constexpr int kUP = kTI + 4;
 
-// One cell of the far kernel's LDS tile, recentred FP32, 16 float4 records:
+// One cell of the far kernel's LDS tile, recentred FP32, 19 float4 records:
 //   c[0] = centroid, (3 D)^2          c[1] = (40 D)^2, area {w0, wa, wb}
-//   c[2..7] = the 7 rule points (21 floats), area / 3, (8 D)^2, 0
+//   c[2..7] = the 7 rule points (21 floats), area / 3, (6 D)^2, 0
 //   c[8..10] = the 3 rule points (9 floats), area {w1, w2} of the 6-point
-//              rule, 0
-//   c[11..15] = the 6 rule points (18 floats), 0, 0
+//              rule, (16 D)^2
+//   c[11..15] = the 6 rule points (18 floats), area {wc, wp} of the 4-point
+//              rule
+//   c[16..18] = the 3 outer points of the 4-point rule (9 floats; its fourth
+//              is the centroid), 0, 0, 0
+// (the zones of the forward field: 7 points within 6 D, 6 within 16 D, 4
+// within 40 D, 3 beyond)
 struct ICell {
-  float4 c[16];
+  float4 c[19];
 };
 
 // sum over m of w_m {1/|e_m|, e_m/|e_m|^3}, e_m = p - point m
@@ -99,12 +104,12 @@ __global__ __launch_bounds__(kTI) void k_influence_mixed(int N, const double *__
   // recentred on the first cell of the 256-cell group, as the near kernel
   const int kr = ord[(kb / kTI) * kTI];
   const double c0 = f[(size_t)MF_GX * N + kr], c1 = f[(size_t)MF_GY * N + kr], c2 = f[(size_t)MF_GZ * N + kr];
-  for (int idx = tid; idx < 48 * kCB; idx += kTI) {
+  for (int idx = tid; idx < 57 * kCB; idx += kTI) {
     const int m = idx / kCB, k = idx % kCB;
     const int kk = ord[min(kb + k, N - 1)];
-    const int src = (m < 21) ? MF_Q7 + m : (m < 30 ? MF_Q3 + (m - 21) : MF_Q6 + (m - 30));
-    const int c = (m < 21 ? m : (m < 30 ? m - 21 : m - 30)) % 3;
-    reinterpret_cast<float *>(&T[k])[m < 21 ? 8 + m : (m < 30 ? 32 + (m - 21) : 44 + (m - 30))] =
+    const int src = (m < 21) ? MF_Q7 + m : (m < 30 ? MF_Q3 + (m - 21) : (m < 48 ? MF_Q6 + (m - 30) : MF_Q4 + (m - 48)));
+    const int c = (m < 21 ? m : (m < 30 ? m - 21 : (m < 48 ? m - 30 : m - 48))) % 3;
+    reinterpret_cast<float *>(&T[k])[m < 21 ? 8 + m : (m < 30 ? 32 + (m - 21) : (m < 48 ? 44 + (m - 30) : 64 + (m - 48)))] =
         (float)(f[(size_t)src * N + kk] - (c == 0 ? c0 : (c == 1 ? c1 : c2)));
   }
   if (tid < kCB) {
@@ -116,11 +121,14 @@ __global__ __launch_bounds__(kTI) void k_influence_mixed(int N, const double *__
     T[tid].c[1] = make_float4((float)(kFar3Mixed * kFar3Mixed * D * D), (float)(ar * Rule7::w0),
                               (float)(ar * Rule7::wa), (float)(ar * Rule7::wb));
     rec[29] = (float)(ar / 3.0);
-    rec[30] = (float)(kMid6Mixed * kMid6Mixed * D * D);
+    rec[30] = (float)(kFwd6 * kFwd6 * D * D);
     rec[31] = 0.f;
     rec[41] = (float)(ar * Rule6::w1);
     rec[42] = (float)(ar * Rule6::w2);
-    rec[43] = rec[62] = rec[63] = 0.f;
+    rec[43] = (float)(kFwd4 * kFwd4 * D * D);
+    rec[62] = (float)(ar * Rule4::wc);
+    rec[63] = (float)(ar * Rule4::wp);
+    rec[73] = rec[74] = rec[75] = 0.f;
   }
   __syncthreads();
   double accd = 0.0;  // threads 0..31: (cell tid / 4, component tid % 4)
@@ -145,9 +153,12 @@ __global__ __launch_bounds__(kTI) void k_influence_mixed(int N, const double *__
       for (int c = 0; c < kCS; ++c) {
         const float R2 = dist2f(px[c], py[c], pz[c], g.x, g.y, g.z);
         const bool nearp = R2 < g.w;  // taken by k_influence_near in FP64
-        // 7 points within 8 D, 6 within 40 D, 3 beyond (finest rule of the wave)
+        // 7 points within 6 D, 6 within 16 D, 4 within 40 D, 3 beyond (finest
+        // rule of the wave)
+        const float lim6 = reinterpret_cast<const float *>(&T[k])[43];
         const bool need7 = !nearp && R2 < h7.z;
-        const bool need6 = !nearp && R2 < h.x;
+        const bool need6 = !nearp && R2 < lim6;
+        const bool need4 = !nearp && R2 < h.x;
         float sv = 0.f, ex = 0.f, ey = 0.f, ez = 0.f;
         if (__any(need7)) {
           if (!nearp) {
@@ -156,6 +167,18 @@ __global__ __launch_bounds__(kTI) void k_influence_mixed(int N, const double *__
             for (int u = 0; u < 21; ++u) q[u] = reinterpret_cast<const float *>(&T[k])[8 + u];
             const float w[7] = {h.y, h.z, h.z, h.z, h.w, h.w, h.w};
             infl_points<7>(px[c], py[c], pz[c], q, w, sv, ex, ey, ez);
+          }
+        } else if (__any(need4) && !__any(need6)) {
+          if (!nearp) {
+            const float *rec = reinterpret_cast<const float *>(&T[k]);
+            float q[12];
+            q[0] = g.x;
+            q[1] = g.y;
+            q[2] = g.z;
+#pragma unroll
+            for (int u = 0; u < 9; ++u) q[3 + u] = rec[64 + u];
+            const float w[4] = {rec[62], rec[63], rec[63], rec[63]};
+            infl_points<4>(px[c], py[c], pz[c], q, w, sv, ex, ey, ez);
           }
         } else if (__any(need6)) {
           if (!nearp) {
