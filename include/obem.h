@@ -57,8 +57,8 @@ typedef enum {
                       within 40, 3 beyond, each rule's truncation error
                       below the float32 rounding floor; a group of 64
                       targets takes the finest rule one of them may need;
-                      the same in the influence; the adjoint keeps 7 points
-                      within 8, 6 within 40, 3 beyond).  Pairwise terms in
+                      the same in the influence and the adjoint).
+                      Pairwise terms in
                       float32 from coordinates
                       recentred near the targets (float32 hi + lo pairs for
                       the sources near them, so close pairs keep their

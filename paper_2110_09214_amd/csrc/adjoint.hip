@@ -85,8 +85,8 @@ __device__ __forceinline__ void cell_grad_closed(const d3 P[3], d3 n, double two
 
 // ---------------------------------------------------------------------------
 // Cell adjoint, mixed precision (regimes as in the forward kernels).  The far
-// kernel takes the pairs beyond 3 D with the FP32 rules (7 points up to 8 D,
-// 6 up to 40 D, 3 beyond); the near kernel then adds the pairs within 3 D
+// kernel takes the pairs beyond 3 D with the FP32 rules (7 points up to 6 D,
+// 6 up to 16 D, 4 up to 40 D, 3 beyond); the near kernel then adds the pairs within 3 D
 // (FP64 closed form), both deciding with the same FP32 test on the same
 // recentred values.
 // gx: 3 x n_t (sorted order) position gradient in units of 1/k_e;
@@ -95,17 +95,20 @@ __device__ __forceinline__ void cell_grad_closed(const d3 P[3], d3 n, double two
 constexpr int kPB = 32;        // cells per LDS tile of the far kernel
 constexpr int kUPad = kT + 4;  // row pitch of the w . IE buffer (floats)
 constexpr int kParts = kT / kPB;
-// (8 D)^2 / (40 D)^2: the 7-point bound from the 3-point one
-constexpr float kR76 = (float)((kMid6Mixed / kFar3Mixed) * (kMid6Mixed / kFar3Mixed));
+// the zone bounds as fractions of (40 D)^2: 7 points within 6 D, 6 within
+// 16 D (the zones of the forward field)
+constexpr float kR7 = (float)((kFwd6 / kFar3Mixed) * (kFwd6 / kFar3Mixed));
+constexpr float kR6 = (float)((kFwd4 / kFar3Mixed) * (kFwd4 / kFar3Mixed));
 
-// One cell of the far kernel's tile, recentred FP32, 15 float4 records
-// (60 floats, so that tile + w . IE buffer fit four workgroups per CU):
+// One cell of the far kernel's tile, recentred FP32, 18 float4 records:
 //   c[0] = centroid, (3 D)^2          c[1] = (40 D)^2, area {w0, wa, wb}
 //   floats 8..28 = the 7 rule points, 29 = area / 3, 30 = sigma,
 //   31 = area w1 of the 6-point rule
 //   floats 32..40 = the 3 rule points, 41 = area w2, 42..59 = the 6 rule points
+//   floats 60..68 = the 3 outer points of the 4-point rule (its fourth is the
+//   centroid; its weights are -27/16 and 25/16 of float 29), 69..71 = 0
 struct BCell {
-  float4 c[15];
+  float4 c[18];
 };
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -174,6 +177,20 @@ __device__ __forceinline__ void bwd_rule(const BCell &C, float r0, float r1, flo
 #pragma unroll
     for (int m = 0; m < 6; ++m)
       qpt_adj(m < 3 ? w1 : w2, r0 - q[3 * m], r1 - q[3 * m + 1], r2 - q[3 * m + 2], wx, wy, wz, u, A, Zx, Zy, Zz);
+  } else if (M == 4) {
+    const float aw = C.c[7].y;  // area / 3
+    const float4 g = C.c[0];
+    const float *rec = reinterpret_cast<const float *>(&C);
+    float q[12];
+    q[0] = g.x;
+    q[1] = g.y;
+    q[2] = g.z;
+#pragma unroll
+    for (int u = 0; u < 9; ++u) q[3 + u] = rec[60 + u];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      qpt_adj(m == 0 ? aw * -1.6875f : aw * 1.5625f, r0 - q[3 * m], r1 - q[3 * m + 1], r2 - q[3 * m + 2], wx, wy,
+              wz, u, A, Zx, Zy, Zz);
   } else {
     const float aw = C.c[7].y;  // area / 3
     float q[12];
@@ -206,7 +223,7 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
   // written after the pair loop's last read of the tile and read before the
   // next tile is staged
   static_assert(sizeof(double) * kParts * kPB <= sizeof(BCell) * kPB, "partials exceed the tile");
-  __shared__ __align__(16) float4 Traw[kPB * 15];
+  __shared__ __align__(16) float4 Traw[kPB * 18];
   __shared__ __align__(16) float U[kPB][kUPad];
   BCell *T = reinterpret_cast<BCell *>(Traw);
   double(*red)[kPB] = reinterpret_cast<double(*)[kPB]>(Traw);
@@ -246,15 +263,15 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
   for (int k0 = kb; k0 < ke; k0 += kPB) {
     const int cnt = min(kPB, ke - k0);
     __syncthreads();
-    for (int idx = tid; idx < 48 * kPB; idx += kT) {
+    for (int idx = tid; idx < 57 * kPB; idx += kT) {
       const int m = idx / kPB, k = idx % kPB;
       float v = 0.f;
-      const int src = (m < 21) ? MF_Q7 + m : (m < 30 ? MF_Q3 + (m - 21) : MF_Q6 + (m - 30));
+      const int src = (m < 21) ? MF_Q7 + m : (m < 30 ? MF_Q3 + (m - 21) : (m < 48 ? MF_Q6 + (m - 30) : MF_Q4 + (m - 48)));
       if (k < cnt) {
-        const int c = (m < 21 ? m : (m < 30 ? m - 21 : m - 30)) % 3;
+        const int c = (m < 21 ? m : (m < 30 ? m - 21 : (m < 48 ? m - 30 : m - 48))) % 3;
         v = (float)(f[(size_t)src * N + k0 + k] - (c == 0 ? c0 : (c == 1 ? c1 : c2)));
       }
-      reinterpret_cast<float *>(&T[k])[m < 21 ? 8 + m : (m < 30 ? 32 + (m - 21) : 42 + (m - 30))] = v;
+      reinterpret_cast<float *>(&T[k])[m < 21 ? 8 + m : (m < 30 ? 32 + (m - 21) : (m < 48 ? 42 + (m - 30) : 60 + (m - 48)))] = v;
     }
     if (tid < kPB) {
       const int k = tid;
@@ -280,6 +297,7 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
       rec[30] = sg;
       rec[31] = w61;
       rec[41] = w62;
+      rec[69] = rec[70] = rec[71] = 0.f;
     }
     __syncthreads();
     float px = 0.f, py = 0.f, pz = 0.f;
@@ -287,7 +305,7 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
     // of the wave tests cell k) against the wave's sphere, as in the forward
     // kernel; only the cells some target may see within 3 D take the
     // per-lane test, which leaves the near pairs to k_panel_bwd_near
-    uint64_t m3, m6, m7, mnear;
+    uint64_t m3, m4, m6, m7, mnear;
     {
       const int k = tid & 63;
       float t = 3.0e38f, Dk = 0.f;
@@ -296,10 +314,12 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
         Dk = sqrtf(T[k].c[1].x) * (float)(1.0 / kFar3Mixed);
         t = sqrtf(dist2f(cw0, cw1, cw2, g.x, g.y, g.z)) - rw;
       }
-      const uint64_t f6 = __ballot(t < (float)(kFar3Mixed * 1.01) * Dk);
-      const uint64_t f7 = __ballot(t < (float)(kMid6Mixed * 1.01) * Dk);
+      const uint64_t f4 = __ballot(t < (float)(kFar3Mixed * 1.01) * Dk);
+      const uint64_t f6 = __ballot(t < (float)(kFwd4 * 1.01) * Dk);
+      const uint64_t f7 = __ballot(t < (float)(kFwd6 * 1.01) * Dk);
       mnear = __ballot(t < (float)(kNearMixed * 1.01) * Dk);
-      m3 = ((1ull << cnt) - 1ull) & ~f6;
+      m3 = ((1ull << cnt) - 1ull) & ~f4;
+      m4 = f4 & ~f6;
       m6 = f6 & ~f7;
       m7 = f7 & ~mnear;
     }
@@ -316,6 +336,12 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
       const int k = __builtin_ctzll(m3);
       float u = 0.f, A = 0.f, Zx = 0.f, Zy = 0.f, Zz = 0.f;
       bwd_rule<3>(T[k], r0, r1, r2, wx, wy, wz, u, A, Zx, Zy, Zz);
+      BWD_CELL_END
+    }
+    for (; m4; m4 &= m4 - 1ull) {
+      const int k = __builtin_ctzll(m4);
+      float u = 0.f, A = 0.f, Zx = 0.f, Zy = 0.f, Zz = 0.f;
+      bwd_rule<4>(T[k], r0, r1, r2, wx, wy, wz, u, A, Zx, Zy, Zz);
       BWD_CELL_END
     }
     for (; m6; m6 &= m6 - 1ull) {
@@ -336,14 +362,18 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
       const float R2 = dist2f(r0, r1, r2, g.x, g.y, g.z);
       const bool nearp = R2 < g.w;  // taken by k_panel_bwd_near in FP64
       const float4 h = T[k].c[1];
-      // 7 points within 8 D, 6 within 40 D, 3 beyond (finest rule of the wave)
-      const bool need7 = (!nearp) && (R2 < h.x * kR76);
-      const bool need6 = (!nearp) && (R2 < h.x);
+      // 7 points within 6 D, 6 within 16 D, 4 within 40 D, 3 beyond (finest
+      // rule of the wave)
+      const bool need7 = (!nearp) && (R2 < h.x * kR7);
+      const bool need6 = (!nearp) && (R2 < h.x * kR6);
+      const bool need4 = (!nearp) && (R2 < h.x);
       float u = 0.f, A = 0.f, Zx = 0.f, Zy = 0.f, Zz = 0.f;
       if (__any(need7)) {
         if (!nearp) bwd_rule<7>(T[k], r0, r1, r2, wx, wy, wz, u, A, Zx, Zy, Zz);
       } else if (__any(need6)) {
         if (!nearp) bwd_rule<6>(T[k], r0, r1, r2, wx, wy, wz, u, A, Zx, Zy, Zz);
+      } else if (__any(need4)) {
+        if (!nearp) bwd_rule<4>(T[k], r0, r1, r2, wx, wy, wz, u, A, Zx, Zy, Zz);
       } else if (!nearp) {
         bwd_rule<3>(T[k], r0, r1, r2, wx, wy, wz, u, A, Zx, Zy, Zz);
       }
