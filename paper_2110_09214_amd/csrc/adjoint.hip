@@ -732,7 +732,7 @@ __global__ __launch_bounds__(kT, 4) void k_pair_bwd_sym(int n, const double *__r
                                                       const double *__restrict__ sq,
                                                       const double *__restrict__ w, const double *__restrict__ sb,
                                                       const uint32_t *__restrict__ dmask, int dwpr, float soft2,
-                                                      int ns, int d0, float *__restrict__ Pi,
+                                                      int ns, int d0, int dcnt, float *__restrict__ Pi,
                                                       float *__restrict__ Pj) {
   // positions and charges, and the weights (q_A w_j with one charge per
   // side, else w_j), each group of 64 sources twice in a row
@@ -743,10 +743,10 @@ __global__ __launch_bounds__(kT, 4) void k_pair_bwd_sym(int n, const double *__r
   static_assert(T * T <= 64, "one mask bit per lane of a wave");
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nxt = ((lane + 1) & 63) << 2;
-  const int A = blockIdx.x;
-  const int dd = blockIdx.y;
+  int A, dd;
+  if (!sym_item(ns, dcnt, A, dd)) return;  // workgroup-uniform, before any barrier
   const int d = d0 + dd;
-  if (d > sym_h(A, ns)) return;  // workgroup-uniform, before any barrier
+  if (d > sym_h(A, ns)) return;
   const int B = (A + d) % ns;
   const int a0 = A * T * kT, b0 = B * T * kT;
   const double *org = sym_origin(sb, A, B);
@@ -1238,9 +1238,9 @@ extern "C" obem_status field_eval_backward(obem_ctx *ctx, const obem_meshh *mesh
         const float soft2 = (float)(soft * soft);
         st = run_pair_once(ctx, n_t, sbsz, ns, ctx->bwd_resident, kBwdSlots, gx,
                            [&](int d0, int dcnt, float *pi, float *pj) {
-                             hipLaunchKernelGGL(k_pair_bwd_sym<kBwdTiles>, dim3(ns, dcnt), dim3(kT), 0, ctx->stream,
-                                                n_t, so.x, so.y, so.z, so.q, wsrt, sb, dmask, dwpr, soft2, ns, d0, pi,
-                                                pj);
+                             hipLaunchKernelGGL(k_pair_bwd_sym<kBwdTiles>, dim3(sym_grid(ns, dcnt)), dim3(kT), 0,
+                                                ctx->stream, n_t, so.x, so.y, so.z, so.q, wsrt, sb, dmask, dwpr, soft2,
+                                                ns, d0, dcnt, pi, pj);
                            });
         if (st) return st;
         OBEM_HIP(ctx, hipGetLastError());

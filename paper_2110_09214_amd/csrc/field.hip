@@ -1248,7 +1248,8 @@ __global__ __launch_bounds__(kThreads, 4) void k_pair_sym(int n, const double *_
                                                         const double *__restrict__ sq,
                                                         const double *__restrict__ tbox, double nn_cut2d,
                                                         const double *__restrict__ sb, float soft2, int ns,
-                                                        int d0, float *__restrict__ Pi, float *__restrict__ Pj) {
+                                                        int d0, int dcnt, float *__restrict__ Pi,
+                                                        float *__restrict__ Pj) {
   // each group of 64 sources twice in a row, so that step m of lane l reads
   // entry l + m without a wrap (constant offsets in the unrolled steps)
   __shared__ float4 S[kThreads / 64][128];
@@ -1256,10 +1257,10 @@ __global__ __launch_bounds__(kThreads, 4) void k_pair_sym(int n, const double *_
   __shared__ unsigned long long skipS;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nxt = ((lane + 1) & 63) << 2;  // byte address of the next lane
-  const int A = blockIdx.x;
-  const int dd = blockIdx.y;
+  int A, dd;
+  if (!sym_item(ns, dcnt, A, dd)) return;  // workgroup-uniform, before any barrier
   const int d = d0 + dd;
-  if (d > sym_h(A, ns)) return;  // workgroup-uniform, before any barrier
+  if (d > sym_h(A, ns)) return;
   const int B = (A + d) % ns;
   const int a0 = A * kSymSB, b0 = B * kSymSB;
   const double *org = sym_origin(sb, A, B);
@@ -1717,13 +1718,15 @@ obem_status launch_pair_field(obem_ctx *ctx, int64_t n_src, const double *sx, co
       const float soft2 = (float)(soft * soft);
       obem_status st = run_pair_once(ctx, n_t, kSymSB, ns, sym_resident(ctx, nn), kSymSlots, acc,
                                      [&](int d0, int dcnt, float *pi, float *pj) {
-                                       const dim3 g(ns, dcnt);
+                                       const dim3 g(sym_grid(ns, dcnt));
                                        if (nn)
                                          hipLaunchKernelGGL(k_pair_sym<true>, g, dim3(kThreads), 0, ctx->stream, n_t,
-                                                            sx, sy, sz, sq, tbox, nn_cut2d, sb, soft2, ns, d0, pi, pj);
+                                                            sx, sy, sz, sq, tbox, nn_cut2d, sb, soft2, ns, d0, dcnt,
+                                                            pi, pj);
                                        else
                                          hipLaunchKernelGGL(k_pair_sym<false>, g, dim3(kThreads), 0, ctx->stream, n_t,
-                                                            sx, sy, sz, sq, tbox, nn_cut2d, sb, soft2, ns, d0, pi, pj);
+                                                            sx, sy, sz, sq, tbox, nn_cut2d, sb, soft2, ns, d0, dcnt,
+                                                            pi, pj);
                                      });
       if (st) return st;
     }

@@ -53,6 +53,36 @@ __device__ __forceinline__ const double *sym_origin(const double *__restrict__ s
   return sb[4 * (size_t)B + 3] < sb[4 * (size_t)A + 3] ? sb + 4 * (size_t)B : sb + 4 * (size_t)A;
 }
 
+// Work item (A, dd) of workgroup w of a pair-once launch over ns super-blocks
+// and dcnt values of d, in a one-dimensional grid of nw = sym_grid(ns, dcnt)
+// workgroups.  The chip deals workgroups to its 8 XCDs in turn (w mod 8), and
+// each XCD has an L2 of its own, so item t = (w mod 8) (nw / 8) + w / 8 gives
+// every XCD a contiguous run of items.  Items run over A within bands of 16
+// values of d (d fastest), so the 256 workgroups an XCD holds at once share
+// 16 super-blocks A and about 31 super-blocks B in its L2 instead of reading
+// 256 of each.  Returns false for the few padding workgroups beyond
+// ns x dcnt.  Any order gives the same result (each workgroup writes its own
+// slots); the order only sets what the L2 can reuse.
+constexpr int kSymXcds = 8;
+constexpr int kSymBand = 16;
+
+inline unsigned sym_grid(int ns, int dcnt) {
+  const long long t = (long long)ns * dcnt;
+  return (unsigned)((t + kSymXcds - 1) / kSymXcds * kSymXcds);
+}
+
+__device__ __forceinline__ bool sym_item(int ns, int dcnt, int &A, int &dd) {
+  const int w = (int)blockIdx.x, nw = (int)gridDim.x;
+  const int t = (w % kSymXcds) * (nw / kSymXcds) + w / kSymXcds;
+  if (t >= ns * dcnt) return false;
+  const int band = t / (ns * kSymBand);
+  const int bw = min(kSymBand, dcnt - band * kSymBand);
+  const int r = t - band * ns * kSymBand;
+  A = r / bw;
+  dd = band * kSymBand + r % bw;
+  return true;
+}
+
 // Workgroups of `kernel` (blocks of `threads`) resident at once on `device`,
 // or 1 if the runtime cannot tell.
 inline int resident_workgroups(const void *kernel, int threads, int device) {
