@@ -263,15 +263,33 @@ __global__ __launch_bounds__(kT) void k_panel_bwd_mixed(int n_t, const double *_
   for (int k0 = kb; k0 < ke; k0 += kPB) {
     const int cnt = min(kPB, ke - k0);
     __syncthreads();
-    for (int idx = tid; idx < 57 * kPB; idx += kT) {
-      const int m = idx / kPB, k = idx % kPB;
-      float v = 0.f;
-      const int src = (m < 21) ? MF_Q7 + m : (m < 30 ? MF_Q3 + (m - 21) : (m < 48 ? MF_Q6 + (m - 30) : MF_Q4 + (m - 48)));
-      if (k < cnt) {
-        const int c = (m < 21 ? m : (m < 30 ? m - 21 : (m < 48 ? m - 30 : m - 48))) % 3;
-        v = (float)(f[(size_t)src * N + k0 + k] - (c == 0 ? c0 : (c == 1 ? c1 : c2)));
+    // staging, coalesced along the cells: the 57 rule coordinates (arrays
+    // MF_Q7 + m) of the 32 cells.  Wave w takes row pairs p = w, w + 4, ...
+    // (p < 30): lanes 0..31 row p, lanes 32..63 row p + 30 (for p < 27), lane
+    // k & 31 on cell k & 31; both rows of a pair hold the same coordinate, so
+    // the origin is the same for the whole wave, and the wave's loads are
+    // all issued before the first is used.
+    {
+      const int k = tid & 31, h = (tid >> 5) & 1;
+      const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+      const bool ok = k < cnt;
+      const double *fk = f + (size_t)(MF_Q7 + 30 * h) * N + k0 + k;
+      float *rec = reinterpret_cast<float *>(&T[k]);
+      double v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int p = w + 4 * j;
+        v[j] = (p < 30 && (h == 0 || p < 27) && ok) ? fk[(size_t)p * N] : 0.0;
       }
-      reinterpret_cast<float *>(&T[k])[m < 21 ? 8 + m : (m < 30 ? 32 + (m - 21) : (m < 48 ? 42 + (m - 30) : 60 + (m - 48)))] = v;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int p = w + 4 * j;
+        if (p < 30 && (h == 0 || p < 27)) {
+          const int c = p % 3;
+          const double o = c == 0 ? c0 : (c == 1 ? c1 : c2);
+          rec[p + 30 * h + (h ? 12 : (p < 21 ? 8 : 11))] = ok ? (float)(v[j] - o) : 0.f;
+        }
+      }
     }
     if (tid < kPB) {
       const int k = tid;

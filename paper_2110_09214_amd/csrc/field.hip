@@ -399,17 +399,32 @@ __global__ __launch_bounds__(kThreads) void k_panel_mixed(int n_t, const double 
     const int cnt = min(kPT, ke - k0);
     __syncthreads();
     // staging, coalesced along the cells: the 57 rule coordinates (7-, 3-, 6-
-    // and 4-point rules) of the 64 cells, then one thread per cell for
-    // centroid, limits and weights
-    for (int idx = tid; idx < 57 * kPT; idx += kThreads) {
-      const int m = idx / kPT, k = idx % kPT;
-      float v = 0.f;
-      const int src = (m < 21) ? MF_Q7 + m : (m < 30 ? MF_Q3 + (m - 21) : (m < 48 ? MF_Q6 + (m - 30) : MF_Q4 + (m - 48)));
-      if (k < cnt) {
-        const int c = (m < 21 ? m : (m < 30 ? m - 21 : (m < 48 ? m - 30 : m - 48))) % 3;
-        v = (float)(f[(size_t)src * N + k0 + k] - (c == 0 ? c0 : (c == 1 ? c1 : c2)));
+    // and 4-point rules, arrays MF_Q7 + m) of the 64 cells, wave w taking
+    // rows m = w, w + 4, ... with lane k on cell k; a row's array, record
+    // slot and coordinate are the same for the whole wave, and the wave's
+    // loads are all issued before the first is used.  Then one thread per
+    // cell for centroid, limits and weights.
+    {
+      const int k = tid & 63;
+      const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+      const bool ok = k < cnt;
+      const double *fk = f + (size_t)MF_Q7 * N + k0 + k;
+      float *rec = reinterpret_cast<float *>(&T[k]);
+      double v[15];
+#pragma unroll
+      for (int j = 0; j < 15; ++j) {
+        const int m = w + 4 * j;
+        v[j] = (m < 57 && ok) ? fk[(size_t)m * N] : 0.0;
       }
-      reinterpret_cast<float *>(&T[k])[m < 21 ? 8 + m : (m < 30 ? 32 + (m - 21) : (m < 48 ? 44 + (m - 30) : 64 + (m - 48)))] = v;
+#pragma unroll
+      for (int j = 0; j < 15; ++j) {
+        const int m = w + 4 * j;
+        if (m < 57) {
+          const int c = m % 3;
+          const double o = c == 0 ? c0 : (c == 1 ? c1 : c2);
+          rec[m + (m < 21 ? 8 : (m < 30 ? 11 : (m < 48 ? 14 : 16)))] = ok ? (float)(v[j] - o) : 0.f;
+        }
+      }
     }
     if (tid < kPT) {
       const int k = tid;
