@@ -1042,8 +1042,14 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
   __shared__ float4 S2[kFar ? kThreads : 1];
   __shared__ int K[kThreads];
   __shared__ float WB[kThreads / 64][6];
+  // one-dimensional grid, the source chunks of a target tile consecutive:
+  // with targets = sources nearly all the directed tile pairs of a target
+  // tile lie in one chunk, so the busy workgroups are spread evenly over the
+  // launch instead of coming in one block per chunk
+  const int nsplit = (n_s + chunk - 1) / chunk;
+  const int tt = (int)blockIdx.x / nsplit, split = (int)blockIdx.x % nsplit;
   const int tid = threadIdx.x;
-  const int i0 = blockIdx.x * kThreads;
+  const int i0 = tt * kThreads;
   const int i = i0 + tid;
   const bool active = i < n_t;
   const double c0 = xs[i0], c1 = xs[(size_t)n_t + i0], c2 = xs[2 * (size_t)n_t + i0];
@@ -1067,7 +1073,7 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
     want_neg = __syncthreads_or(want == 0);
   }
   const int self = active ? (self_map ? self_map[perm[i]] : perm[i]) : -1;
-  const int jb = blockIdx.y * chunk;
+  const int jb = split * chunk;
   const int je = min(n_s, jb + chunk);
   // Bounding box of the workgroup's targets (recentred FP32), tested against
   // each source tile's box (tbox, FP64, 256-source tiles): tiles farther
@@ -1114,11 +1120,25 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
   int bidx = -1;
   for (int jt = jb; jt < je; jt += kThreads) {
     // targets are the sources in the same order under sym_tiles: this
-    // workgroup's targets are source tile blockIdx.x, and the tile pairs
-    // that tile_pair_direct (dmask) does not keep here are evaluated by
-    // k_pair_sym
-    if (sym_tiles && !((dmask[(size_t)blockIdx.x * dwpr + ((jt / kThreads) >> 5)] >> ((jt / kThreads) & 31)) & 1u))
-      continue;
+    // workgroup's targets are source tile tt, and the tile pairs that
+    // tile_pair_direct (dmask, row tt) does not keep here are evaluated by
+    // k_pair_sym; skip to the next tile of the row, a word (32 tiles) at a
+    // time (scalar)
+    if (sym_tiles) {
+      const uint32_t *mrow = dmask + (size_t)tt * dwpr;
+      const int be = (je + kThreads - 1) / kThreads;
+      int b = jt / kThreads;
+      uint32_t wd = mrow[b >> 5] >> (b & 31);
+      while (wd == 0u) {
+        b = (b | 31) + 1;
+        if (b >= be) break;
+        wd = mrow[b >> 5];
+      }
+      if (b >= be) break;
+      b += __builtin_ctz(wd);
+      if (b >= be) break;
+      jt = b * kThreads;
+    }
     const int cnt = min(kThreads, je - jt);
     const float q0 = (float)sq[jt];
     bool nn_tile = NN;
@@ -1135,7 +1155,7 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
       close_tile = gap2 < close2;
     }
     if (sym_tiles) {
-      const bool np = NN && tiles_gap2(tbox, blockIdx.x, jt / kThreads) <= nn_cut2d;
+      const bool np = NN && tiles_gap2(tbox, tt, jt / kThreads) <= nn_cut2d;
       nn_tile = np;
       far_tile = far_tile && !np;
     }
@@ -1202,14 +1222,14 @@ __global__ __launch_bounds__(kThreads, 7) void k_pair_mixed(int n_t, const doubl
     if (WANT_V) neumaier(hv, lv, pv);
   }
   if (active) {
-    const size_t o = (size_t)blockIdx.y * 4 * n_t;
+    const size_t o = (size_t)split * 4 * n_t;
     part[o + i] = (double)hx + (double)lx;
     part[o + (size_t)n_t + i] = (double)hy + (double)ly;
     part[o + 2 * (size_t)n_t + i] = (double)hz + (double)lz;
     part[o + 3 * (size_t)n_t + i] = WANT_V ? (double)hv + (double)lv : 0.0;
     if (NN) {
-      nn_d2p[(size_t)blockIdx.y * n_t + i] = best;
-      nn_ip[(size_t)blockIdx.y * n_t + i] = bidx;
+      nn_d2p[(size_t)split * n_t + i] = best;
+      nn_ip[(size_t)split * n_t + i] = bidx;
     }
   }
 }
@@ -1614,7 +1634,8 @@ static void launch_pair_t(obem_ctx *ctx, dim3 grid, int n_t, const double *xs, c
                           const int32_t *self_map, int sym_tiles, double nn_cut2d, const uint32_t *dmask,
                           int dwpr) {
   if (prec == OBEM_MIXED)
-    hipLaunchKernelGGL((k_pair_mixed<WANT_V, NN, CZ>), grid, dim3(kThreads), 0, ctx->stream, n_t, xs, perm, n_s,
+    hipLaunchKernelGGL((k_pair_mixed<WANT_V, NN, CZ>), dim3(grid.x * grid.y), dim3(kThreads), 0, ctx->stream, n_t,
+                       xs, perm, n_s,
                        sx, sy, sz, sq, sp, sps, (float)(soft * soft), chunk, part, (float *)nnd, nni, tbox, nn_cut2,
                        self_map, sym_tiles, nn_cut2d, dmask, dwpr);
   else
