@@ -344,7 +344,7 @@ def main():
         extra = {}
 
         def field_step():
-            B.bem_solve_charges(ctx, bm, rhs, sigma, max_refine=2, want_info=False)
+            B.bem_solve_charges(ctx, bm, rhs, sigma, max_refine=1, want_info=False)
             B.field_eval(ctx, bm, sigma, X, Q, X, 1e-7, B.OBEM_MIXED, tgt_is_src=True, out=E)
 
         ms_f, _ = timed(field_step, 2, 1)

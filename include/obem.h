@@ -416,7 +416,8 @@ typedef struct {
 
 /* One tracking step (ordered as in the paper's dynamic option):
  *  1. if p->resolve: rhs = rhs0 + e * dd_counts / area on dd rows
- *     (eq. (charge-up)), sigma = bem_solve_charges(rhs) (with resolve = 2
+ *     (eq. (charge-up)), sigma = bem_solve_charges(rhs) with one
+ *     refinement sweep (with resolve = 2
  *     skipped when rhs is unchanged since the mesh's last re-solve, with
  *     resolve = 3 also updated from the inverse when few entries changed);
  *  2. E at every live particle from the cells and all other particles,
