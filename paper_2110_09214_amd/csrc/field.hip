@@ -1493,17 +1493,27 @@ __global__ __launch_bounds__(256) void k_sym_reduce(int n, int sbsz, int ns, int
   if (p >= n) return;
   const int A = p / sbsz;
   const int hA = sym_h(A, ns);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    double s = acc[(size_t)c * n + p];
-    for (int dd = 0; dd < dcnt; ++dd) {
-      const int d = d0 + dd;
-      const size_t o = ((size_t)dd * 3 + c) * n + p;
-      if (d <= hA) s += (double)Pi[o];
-      if (d <= sym_h((A - d + ns) % ns, ns)) s += (double)Pj[o];
+  // the three components side by side, so that six loads per slot are in
+  // flight (each component keeps its order of additions)
+  double s0 = acc[p], s1 = acc[(size_t)n + p], s2 = acc[2 * (size_t)n + p];
+#pragma unroll 4
+  for (int dd = 0; dd < dcnt; ++dd) {
+    const int d = d0 + dd;
+    const size_t o = (size_t)dd * 3 * n + p;
+    if (d <= hA) {
+      s0 += (double)Pi[o];
+      s1 += (double)Pi[o + (size_t)n];
+      s2 += (double)Pi[o + 2 * (size_t)n];
     }
-    acc[(size_t)c * n + p] = s;
+    if (d <= sym_h((A - d + ns) % ns, ns)) {
+      s0 += (double)Pj[o];
+      s1 += (double)Pj[o + (size_t)n];
+      s2 += (double)Pj[o + 2 * (size_t)n];
+    }
   }
+  acc[p] = s0;
+  acc[(size_t)n + p] = s1;
+  acc[2 * (size_t)n + p] = s2;
 }
 
 template <bool WANT_V, bool NN, int EXCL>
